@@ -1,0 +1,223 @@
+"""FP64 CPU oracle for the generalized winding number (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never touches it and the
+two share no code.  The arithmetic lives in ``wn_oracle.c`` (plain C, FP64,
+OpenMP over independent outputs); this module loads it with ``ctypes`` and adds
+the trivial element-wise maps (occupancy, sigmoid-MSE loss) in numpy FP64.
+
+Paper sections followed (arXiv 2407.11272):
+  * Section 2.2, Eq. 5: W(q) = (1/4 pi) sum_f Omega_f(q);
+  * Section 2.2, Eq. 7 with the half-angle factor 2, and Eq. 8 (ATAN2 cases);
+  * Algorithm 1 (per-face normalise, alpha, beta, ATAN2, accumulate);
+  * Section 2.1, Eq. 3: for a closed surface W is the occupancy; the map to a hard
+    or soft occupancy uses a threshold or a sigmoid around 0.5.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wn_oracle.c")
+_LIB = os.path.join(_HERE, "libwn_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _bind(lib):
+    lib.wno_atan2_eq8.restype = ctypes.c_double
+    lib.wno_atan2_eq8.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.wno_solid_angle.restype = ctypes.c_double
+    lib.wno_solid_angle.argtypes = [_dp, _dp, _dp, _dp]
+    lib.wno_alpha_beta.restype = None
+    lib.wno_alpha_beta.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
+    lib.wno_solid_angle_grad.restype = None
+    lib.wno_solid_angle_grad.argtypes = [_dp, _dp, _dp, _dp, _dp]
+    lib.wno_winding.restype = ctypes.c_int
+    lib.wno_winding.argtypes = [_dp, ctypes.c_int64, _lp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, ctypes.c_int]
+    lib.wno_grad.restype = ctypes.c_int
+    lib.wno_grad.argtypes = [_dp, ctypes.c_int64, _lp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp,
+                             ctypes.c_int]
+    lib.wno_min_dist.restype = ctypes.c_int
+    lib.wno_min_dist.argtypes = [_dp, ctypes.c_int64, _lp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp,
+                                 ctypes.c_int]
+    lib.wno_grid_points.restype = None
+    lib.wno_grid_points.argtypes = [_dp, _dp, _lp, _dp]
+    lib.wno_max_threads.restype = ctypes.c_int
+    lib.wno_max_threads.argtypes = []
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+class use_library:
+    """Context manager that routes every oracle call to another build of the same
+    source (the mutation tests load deliberately broken copies this way)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _bind(ctypes.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_lp)
+
+
+def max_threads() -> int:
+    return int(_load().wno_max_threads())
+
+
+def atan2_eq8(y: float, x: float) -> float:
+    """Section 2.2, Eq. 8 case table (ATAN2(0, 0) = 0; y = -0 counts as y >= 0)."""
+    return float(_load().wno_atan2_eq8(float(y), float(x)))
+
+
+def alpha_beta(v0, v1, v2, q):
+    """Section 2.2, Eq. 7 numerator det(e0,e1,e2) and denominator 1 + sum of dots."""
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    args = [_d(x) for x in (v0, v1, v2, q)]
+    _load().wno_alpha_beta(*(p for _, p in args), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def solid_angle(v0, v1, v2, q) -> float:
+    """Omega = 2 ATAN2(alpha, beta) of one triangle at q (Eq. 7 with the factor 2)."""
+    args = [_d(x) for x in (v0, v1, v2, q)]
+    return float(_load().wno_solid_angle(*(p for _, p in args)))
+
+
+def solid_angle_grad(v0, v1, v2, q) -> np.ndarray:
+    """dOmega/dv_j as a [3, 3] array (row j = vertex j)."""
+    out = np.zeros(9, dtype=np.float64)
+    args = [_d(x) for x in (v0, v1, v2, q)]
+    _load().wno_solid_angle_grad(*(p for _, p in args), out.ctypes.data_as(_dp))
+    return out.reshape(3, 3)
+
+
+def grid_points(grid) -> np.ndarray:
+    """Voxel centres ``lo + (idx + 1/2)(hi - lo)/n`` in FP64, C order (z fastest)."""
+    lo, plo = _d(np.asarray(grid.lo, dtype=np.float64))
+    hi, phi = _d(np.asarray(grid.hi, dtype=np.float64))
+    n, pn = _i(np.asarray(grid.n, dtype=np.int64))
+    Q = np.empty((int(np.prod(n)), 3), dtype=np.float64)
+    _load().wno_grid_points(plo, phi, pn, Q.ctypes.data_as(_dp))
+    return Q
+
+
+def winding(V, F, Q, threads: int = 0) -> np.ndarray:
+    """W(q) for every row of Q by brute force over all faces (Eq. 5, 7, 8), FP64."""
+    V, pv = _d(np.asarray(V).reshape(-1, 3))
+    F, pf = _i(np.asarray(F).reshape(-1, 3))
+    Q, pq = _d(np.asarray(Q).reshape(-1, 3))
+    W = np.empty(len(Q), dtype=np.float64)
+    rc = _load().wno_winding(pv, len(V), pf, len(F), pq, len(Q), W.ctypes.data_as(_dp), int(threads))
+    if rc != 0:
+        raise ValueError("oracle: face index out of range")
+    return W
+
+
+def winding_grid(V, F, grid, threads: int = 0) -> np.ndarray:
+    return winding(V, F, grid_points(grid), threads)
+
+
+def grad(V, F, Q, dLdW, threads: int = 0):
+    """(dL/dT [nF, 3, 3], dL/dV [nV, 3]) for the given dL/dW at the rows of Q."""
+    V, pv = _d(np.asarray(V).reshape(-1, 3))
+    F, pf = _i(np.asarray(F).reshape(-1, 3))
+    Q, pq = _d(np.asarray(Q).reshape(-1, 3))
+    g, pg = _d(np.asarray(dLdW).reshape(-1))
+    if len(g) != len(Q):
+        raise ValueError("dLdW must have one entry per query point")
+    T = np.zeros((len(F), 9), dtype=np.float64)
+    D = np.zeros((len(V), 3), dtype=np.float64)
+    rc = _load().wno_grad(pv, len(V), pf, len(F), pq, len(Q), pg, T.ctypes.data_as(_dp), D.ctypes.data_as(_dp),
+                          int(threads))
+    if rc != 0:
+        raise ValueError("oracle: face index out of range")
+    return T.reshape(-1, 3, 3), D
+
+
+def min_dist(V, F, Q, threads: int = 0):
+    """(distance to nearest edge or vertex, distance to nearest face) per query point."""
+    V, pv = _d(np.asarray(V).reshape(-1, 3))
+    F, pf = _i(np.asarray(F).reshape(-1, 3))
+    Q, pq = _d(np.asarray(Q).reshape(-1, 3))
+    de = np.empty(len(Q))
+    df = np.empty(len(Q))
+    rc = _load().wno_min_dist(pv, len(V), pf, len(F), pq, len(Q), de.ctypes.data_as(_dp), df.ctypes.data_as(_dp),
+                              int(threads))
+    if rc != 0:
+        raise ValueError("oracle: face index out of range")
+    return de, df
+
+
+def guard_mask(V, F, Q, edge_tol: float = 1e-4, face_tol: float = 1e-6, threads: int = 0) -> np.ndarray:
+    """True where a point is too close to the surface for an FP32 result to be held
+    to the FP64 one: within ``edge_tol`` of an edge or vertex, or ``face_tol`` of a face.
+    Section 2.2 notes the field is binary except at points on the surface."""
+    de, df = min_dist(V, F, Q, threads)
+    return (de < edge_tol) | (df < face_tol)
+
+
+# ------------------------------------------------------------ occupancy maps ---
+
+def occupancy_threshold(W, tau: float = 0.5) -> np.ndarray:
+    """Hard occupancy 1[W > tau] as uint8 (Eq. 3: W is the occupancy of a closed surface)."""
+    return (np.asarray(W, dtype=np.float64) > tau).astype(np.uint8)
+
+
+def occupancy_sigmoid(W, tau: float = 0.5, k: float = 50.0) -> np.ndarray:
+    """Soft occupancy 1 / (1 + exp(-k (W - tau)))."""
+    W = np.asarray(W, dtype=np.float64)
+    return 1.0 / (1.0 + np.exp(-k * (W - tau)))
+
+
+def sigmoid_mse(W, target, tau: float = 0.5, k: float = 50.0):
+    """Loss L = mean_q (sigmoid(k (W_q - tau)) - target_q)^2 and dL/dW_q."""
+    W = np.asarray(W, dtype=np.float64)
+    t = np.asarray(target, dtype=np.float64)
+    s = occupancy_sigmoid(W, tau, k)
+    n = max(len(W), 1)
+    L = float(np.sum((s - t) ** 2) / n)
+    dLdW = 2.0 * (s - t) / n * k * s * (1.0 - s)
+    return L, dLdW

@@ -1,0 +1,75 @@
+"""Mutation check of the oracle's pins: plausible mistakes are planted in a copy of the
+oracle's C source (on the CPU, in a temporary directory), and every such mutant must
+fail at least one pin of ``test_oracle_pins``.  This shows the pins constrain each
+term of the oracle (Eq. 5, 7, 8 and the gradient), not just its overall shape.
+"""
+import inspect
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "wn_oracle.c")
+
+# (name, original text, replacement); each original must occur in the source.
+MUTANTS = [
+    ("no_half_angle_factor", "nsum_add(&s, 2.0 * wno_atan2_eq8(a, b));", "nsum_add(&s, wno_atan2_eq8(a, b));"),
+    ("no_half_angle_factor_single", "return 2.0 * wno_atan2_eq8(a, b);", "return wno_atan2_eq8(a, b);"),
+    ("plain_arctan", "nsum_add(&s, 2.0 * wno_atan2_eq8(a, b));", "nsum_add(&s, 2.0 * atan(a / b));"),
+    ("beta_sign", "+ dot3(e[2], e[0]);\n}", "- dot3(e[2], e[0]);\n}"),
+    ("beta_missing_one", "*beta = 1.0 + dot3", "*beta = dot3"),
+    ("transposed_cross", "cross3(e[1], e[2], x12);\n    *alpha", "cross3(e[2], e[1], x12);\n    *alpha"),
+    ("wrong_vertex_index", "V + 3 * F[3 * f + 1], V + 3 * F[3 * f + 2], q, &a, &b);",
+     "V + 3 * F[3 * f + 1], V + 3 * F[3 * f + 1], q, &a, &b);"),
+    ("eq8_branch_sign", "if (y >= 0) return atan(y / x) + M_PI;", "if (y >= 0) return atan(y / x) - M_PI;"),
+    ("eq8_zero_case", "if (y < 0) return -M_PI / 2;\n    return 0.0;", "if (y < 0) return -M_PI / 2;\n    return M_PI;"),
+    ("eq8_strict_y", "if (y >= 0) return atan(y / x) + M_PI;", "if (y > 0) return atan(y / x) + M_PI;"),
+    ("zero_vertex_direction", "e[j][c] = len > 0 ? r[c] / len : 0.0;\n    }\n    double x12[3];\n    cross3(e[1], e[2], x12);\n    *alpha",
+     "e[j][c] = len > 0 ? r[c] / len : 0.57735;\n    }\n    double x12[3];\n    cross3(e[1], e[2], x12);\n    *alpha"),
+    ("wrong_normaliser", "W[i] = nsum_get(&s) / (4.0 * M_PI);", "W[i] = nsum_get(&s) / (2.0 * M_PI);"),
+    ("grad_no_projection", "out[3 * j + c] = (g[c] - ge * e[j][c]) / len[j];", "out[3 * j + c] = g[c] / len[j];"),
+    ("grad_sign", "(beta * u[c] - alpha * (e[k][c] + e[l][c]))", "(beta * u[c] + alpha * (e[k][c] + e[l][c]))"),
+    ("grad_cyclic_order", "int k = (j + 1) % 3, l = (j + 2) % 3;", "int k = (j + 2) % 3, l = (j + 1) % 3;"),
+    ("grad_no_radius", "out[3 * j + c] = (g[c] - ge * e[j][c]) / len[j];", "out[3 * j + c] = (g[c] - ge * e[j][c]);"),
+    ("grad_scale", "T[9 * f + c] = nsum_get(&s[c]) / (4.0 * M_PI);", "T[9 * f + c] = nsum_get(&s[c]);"),
+    ("grad_gather_index", "nsum_add(&acc[3 * F[3 * f + j] + c]", "nsum_add(&acc[3 * F[3 * f] + c]"),
+    ("grid_half_offset", "((double)ijk[d] + 0.5)", "((double)ijk[d])"),
+    ("dist_plane", "return fabs(t) * sqrt(nn);", "return fabs(t) * nn;"),
+]
+
+PIN_TESTS = [fn for name, fn in inspect.getmembers(pins, inspect.isfunction)
+             if name.startswith("test_") and "orc" in inspect.signature(fn).parameters]
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutant {name}: pattern not found"
+    mutated = src.replace(old, new, 1)
+    assert mutated != src
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(mutated)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(c), "-lm"],
+                   check=True)
+    return str(so)
+
+
+def test_pins_pass_on_unmodified_oracle(orc):
+    for fn in PIN_TESTS:
+        fn(orc)
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_every_mutant_is_caught(tmp_path, orc, name, old, new):
+    so = _build(tmp_path, name, old, new)
+    failed = []
+    with oracle.use_library(so):
+        for fn in PIN_TESTS:
+            try:
+                fn(oracle)
+            except Exception:  # an assertion, or a numerical error a pin provokes
+                failed.append(fn.__name__)
+    assert failed, f"mutant {name} passed every pin"

@@ -1,0 +1,445 @@
+"""Pins of the FP64 oracle against results the paper and mathematics fix, not against itself.
+
+Each test names the passage of arXiv 2407.11272 it follows.  Independent formulas
+(L'Huilier's spherical excess, quadrature of the flux integral, the Biot-Savart edge
+sum, half-space and ray-parity inside tests, finite differences) are written here in
+numpy and share nothing with the oracle's C code.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import wn_inputs as wi
+from wn_inputs.meshgen import signed_volume
+
+PI = math.pi
+
+
+# ------------------------------------------------------------ independent refs
+
+def lhuilier_signed(v, q):
+    """Signed solid angle of the spherical triangle (L'Huilier), sign from det(e0,e1,e2)."""
+    e = [(np.asarray(x, float) - q) / np.linalg.norm(np.asarray(x, float) - q) for x in v]
+
+    def ang(a, b):
+        return math.atan2(np.linalg.norm(np.cross(a, b)), float(a @ b))
+
+    a, b, c = ang(e[1], e[2]), ang(e[2], e[0]), ang(e[0], e[1])
+    s = 0.5 * (a + b + c)
+    t = math.tan(s / 2) * math.tan((s - a) / 2) * math.tan((s - b) / 2) * math.tan((s - c) / 2)
+    E = 4.0 * math.atan(math.sqrt(max(t, 0.0)))
+    return math.copysign(E, np.linalg.det(np.array(e)))
+
+
+def flux_quadrature(v, q, n=48):
+    """Section 2.1, Eq. 2 on one triangle: integral of <n, (x-q)/|x-q|^3> ds by a
+    Duffy-collapsed Gauss-Legendre product rule (returns the solid angle, 4 pi W)."""
+    v0, v1, v2 = (np.asarray(x, float) for x in v)
+    N = np.cross(v1 - v0, v2 - v0)  # n ds = N du dv
+    g, w = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1.0)
+    w = 0.5 * w
+    S, T = np.meshgrid(g, g, indexing="ij")
+    WS, WT = np.meshgrid(w, w, indexing="ij")
+    u = S * (1 - T)
+    vv = S * T
+    X = v0 + u[..., None] * (v1 - v0) + vv[..., None] * (v2 - v0)
+    D = X - q
+    r3 = np.linalg.norm(D, axis=-1) ** 3
+    f = (D @ N) / r3
+    return float(np.sum(f * S * WS * WT))
+
+
+def biot_savart_grad_q(v, q):
+    """Gradient of the signed solid angle with respect to the observation point: the
+    Biot-Savart sum over the directed boundary edges a -> b with A = a - q, B = b - q."""
+    g = np.zeros(3)
+    for i in range(3):
+        A = np.asarray(v[i], float) - q
+        B = np.asarray(v[(i + 1) % 3], float) - q
+        a, b = np.linalg.norm(A), np.linalg.norm(B)
+        g += np.cross(A, B) * (a + b) / (a * b * (a * b + A @ B))
+    return g
+
+
+def convex_inside(V, F, Q, eps=0.0):
+    """Half-space test for a convex outward-wound mesh: inside iff behind every face plane."""
+    a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    n = np.cross(b - a, c - a)
+    s = np.einsum("qfd,fd->qf", Q[:, None, :] - a[None], n)
+    return np.all(s < -eps, axis=1), np.any(s > eps, axis=1)
+
+
+def ray_parity(V, F, Q, direction=(0.5773502691896258, 0.5773502691896257, 0.5773502691896259)):
+    """Crossing count of the ray q + t d (t > 0) with every face (Moller-Trumbore), mod 2."""
+    d = np.asarray(direction, float)
+    a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    e1, e2 = b - a, c - a
+    p = np.cross(d, e2)
+    det = np.einsum("fd,fd->f", e1, p)
+    out = []
+    for q in Q:
+        s = q - a
+        u = np.einsum("fd,fd->f", s, p) / det
+        qq = np.cross(s, e1)
+        v = (qq @ d) / det
+        t = np.einsum("fd,fd->f", e2, qq) / det
+        hit = (u > 0) & (v > 0) & (u + v < 1) & (t > 0)
+        out.append(int(hit.sum()) % 2)
+    return np.array(out)
+
+
+# ------------------------------------------------------------------- Eq. 8
+
+def test_atan2_eq8_case_table(orc):
+    """Section 2.2, Eq. 8: every branch of the case table at points with known angles."""
+    assert orc.atan2_eq8(1.0, 1.0) == pytest.approx(PI / 4, abs=1e-15)
+    assert orc.atan2_eq8(1.0, -1.0) == pytest.approx(3 * PI / 4, abs=1e-15)
+    assert orc.atan2_eq8(-1.0, -1.0) == pytest.approx(-3 * PI / 4, abs=1e-15)
+    assert orc.atan2_eq8(-1.0, 1.0) == pytest.approx(-PI / 4, abs=1e-15)
+    assert orc.atan2_eq8(2.0, 0.0) == PI / 2
+    assert orc.atan2_eq8(-2.0, 0.0) == -PI / 2
+    assert orc.atan2_eq8(2.0, -0.0) == PI / 2
+    # x = 0, y = 0 gives 0 whatever the signs of the zeros
+    for y in (0.0, -0.0):
+        for x in (0.0, -0.0):
+            assert orc.atan2_eq8(y, x) == 0.0
+    # x < 0 and y = 0: the y >= 0 branch, +pi, also for y = -0 (-0 >= 0 holds)
+    assert orc.atan2_eq8(0.0, -3.0) == pytest.approx(PI, abs=1e-15)
+    assert orc.atan2_eq8(-0.0, -3.0) == pytest.approx(PI, abs=1e-15)
+    # agrees with the library atan2 away from the zero cases
+    rng = np.random.default_rng(11)
+    for y, x in rng.normal(size=(200, 2)):
+        assert orc.atan2_eq8(y, x) == pytest.approx(math.atan2(y, x), abs=1e-15)
+
+
+# ------------------------------------------------------------- closed forms
+
+def test_octant_triangle_is_one_eighth(orc):
+    """Eq. 7 with the half-angle factor 2: the triangle (e_x, e_y, e_z) seen from the
+    origin subtends one octant, Omega = 4 pi / 8, so W = 1/8."""
+    v = [[1, 0, 0], [0, 1, 0], [0, 0, 1]]
+    q = [0, 0, 0]
+    a, b = orc.alpha_beta(*v, q)
+    assert a == pytest.approx(1.0, abs=1e-15) and b == pytest.approx(1.0, abs=1e-15)
+    assert orc.solid_angle(*v, q) == pytest.approx(4 * PI / 8, abs=1e-15)
+    assert orc.winding(np.array(v, float), np.array([[0, 1, 2]]), [q])[0] == pytest.approx(1 / 8, abs=1e-15)
+    # scaled vertices, same directions: same solid angle
+    assert orc.solid_angle([3, 0, 0], [0, 0.5, 0], [0, 0, 7], q) == pytest.approx(PI / 2, abs=1e-14)
+    # cyclic relabelling keeps it, a swap flips it
+    assert orc.solid_angle(v[1], v[2], v[0], q) == pytest.approx(PI / 2, abs=1e-15)
+    assert orc.solid_angle(v[0], v[2], v[1], q) == pytest.approx(-PI / 2, abs=1e-15)
+
+
+def test_regular_solids_from_centre(orc):
+    """Eq. 3: a closed surface has W = 1 at interior points; each octahedron face is an octant."""
+    V, F = wi.octahedron_mesh(1.0)
+    assert signed_volume(V, F) > 0
+    for f in F:
+        assert orc.solid_angle(*V[f], [0, 0, 0]) == pytest.approx(PI / 2, abs=1e-14)
+    W = orc.winding(V, F, [[0, 0, 0], [0.2, -0.1, 0.3], [1.5, 0, 0], [0.0, 0.0, -4.0]])
+    np.testing.assert_allclose(W, [1, 1, 0, 0], atol=1e-14)
+
+
+def test_cube_special_positions(orc):
+    """Eq. 8 zeros and the vertex reading: on the closed unit cube,
+    centre -> 1; a vertex -> 1/8 (octant, the incident faces give 0);
+    an edge midpoint -> 1/4 (dihedral angle pi/2, the two incident faces give 0);
+    a face centre, which lies on that face's diagonal -> 1/2 (half-space)."""
+    V, F = wi.cube_mesh(0.0, 1.0)
+    assert signed_volume(V, F) == pytest.approx(1.0)
+    Q = [[0.5, 0.5, 0.5], [0, 0, 0], [1, 1, 1], [0.5, 0, 0], [0, 1, 0.5], [0.5, 0.5, 0], [1, 0.5, 0.5],
+         [3, 3, 3]]
+    W = orc.winding(V, F, Q)
+    np.testing.assert_allclose(W, [1, 1 / 8, 1 / 8, 1 / 4, 1 / 4, 1 / 2, 1 / 2, 0], atol=1e-14)
+
+
+def test_vertex_and_edge_faces_contribute_zero(orc):
+    """A face with q at one of its vertices gives 0 (unit vector of a zero vector taken
+    as 0, then ATAN2(0, beta >= 0) = 0); q on an edge gives alpha = beta = 0 -> 0."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        v = rng.normal(size=(3, 3))
+        for j in range(3):
+            assert orc.solid_angle(*v, v[j]) == 0.0
+        # midpoint of an edge with exactly representable coordinates
+        a = np.round(rng.normal(size=3) * 8) / 8
+        b = a + np.array([0.5, 0.0, 0.0])
+        c = rng.normal(size=3)
+        assert orc.solid_angle(a, b, c, (a + b) / 2) == 0.0
+
+
+def test_degenerate_face_contributes_nothing(orc):
+    """A collinear (zero-area) face subtends no solid angle from any point."""
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        a = rng.normal(size=3)
+        d = rng.normal(size=3)
+        v = [a, a + 0.3 * d, a + 1.1 * d]
+        q = rng.normal(size=3) * 2
+        assert abs(orc.solid_angle(*v, q)) < 1e-12
+
+
+# ------------------------------------------------------- independent formulas
+
+def test_lhuilier_spherical_excess(orc):
+    """Per-triangle Omega equals L'Huilier's spherical excess of the projected triangle,
+    signed by det(e0, e1, e2)."""
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for _ in range(300):
+        v = rng.normal(size=(3, 3))
+        q = rng.normal(size=3) * 1.5
+        worst = max(worst, abs(orc.solid_angle(*v, q) - lhuilier_signed(v, q)))
+    assert worst < 1e-10
+
+
+def test_flux_quadrature_eq2(orc):
+    """Section 2.1, Eq. 2: the flux integral over a triangle, computed by quadrature,
+    converges to the closed-form solid angle for points not close to the triangle."""
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        v = rng.normal(size=(3, 3)) * 0.3
+        dirn = rng.normal(size=3)
+        q = v.mean(0) + dirn / np.linalg.norm(dirn) * rng.uniform(1.0, 3.0)
+        assert orc.solid_angle(*v, q) == pytest.approx(flux_quadrature(v, q), abs=1e-10)
+
+
+# ------------------------------------------------------------- Eq. 3 pins
+
+def test_closed_icosphere_is_occupancy(orc):
+    """Eq. 3: W of a closed surface is 1 inside and 0 outside.  The inside set comes
+    from an independent half-space test (the icosphere is convex)."""
+    V, F = wi.icosphere(2)
+    rng = np.random.default_rng(9)
+    Q = rng.uniform(-1.3, 1.3, size=(600, 3))
+    inside, outside = convex_inside(V, F, Q, eps=1e-6)
+    W = orc.winding(V, F, Q)
+    assert inside.sum() > 50 and outside.sum() > 50
+    np.testing.assert_allclose(W[inside], 1.0, atol=1e-12)
+    np.testing.assert_allclose(W[outside], 0.0, atol=1e-12)
+
+
+def test_nonconvex_closed_mesh_matches_ray_parity(orc):
+    """Eq. 3 on a non-convex closed mesh (heavily jittered icosphere): W equals the
+    crossing parity of a ray, an independent inside test."""
+    rng = np.random.default_rng(10)
+    V, F = wi.icosphere(2)
+    V = V * (1.0 + 0.25 * rng.uniform(-1, 1, size=(len(V), 1)))
+    Q = rng.uniform(-1.2, 1.2, size=(400, 3))
+    W = orc.winding(V, F, Q)
+    par = ray_parity(V, F, Q)
+    np.testing.assert_allclose(W, par, atol=1e-10)
+
+
+def test_overlapping_shells_count(orc):
+    """Overlapping closed shells (the union workload before face deletion): W counts
+    how many shells contain the point; each shell is convex, so a half-space test per
+    shell gives the count independently."""
+    rng = np.random.default_rng(12)
+    V, F, ells = wi.ellipsoid_union(rng, 4, 200, axes=(0.15, 0.4), centres=(-0.15, 0.15))
+    Q = rng.uniform(-0.5, 0.5, size=(500, 3))
+    W = orc.winding(V, F, Q)
+    faces_per = len(F) // 4
+    count = np.zeros(len(Q))
+    sure = np.ones(len(Q), dtype=bool)
+    for s in range(4):
+        Fs = F[s * faces_per:(s + 1) * faces_per]
+        ins, outs = convex_inside(V, Fs, Q, eps=1e-9)
+        count += ins
+        sure &= ins | outs
+    assert W.max() > 1.5  # some points really are inside several shells
+    np.testing.assert_allclose(W[sure], count[sure], atol=1e-10)
+
+
+def test_orientation_flip_negates(orc):
+    """Reversing every face reverses the normal in Eq. 2, so W -> -W."""
+    c1 = wi.config1_icosphere()
+    rng = np.random.default_rng(13)
+    Q = rng.uniform(-0.5, 0.5, size=(300, 3))
+    W = orc.winding(c1.V, c1.F, Q)
+    Wr = orc.winding(c1.V, wi.reverse_faces(c1.F), Q)
+    np.testing.assert_allclose(Wr, -W, atol=1e-12)
+
+
+def test_rigid_and_scale_invariance_and_mirror(orc):
+    """W is invariant under a joint rotation, translation and positive scaling of mesh
+    and points; a mirror reverses orientation, so W -> -W."""
+    rng = np.random.default_rng(14)
+    V, F, _ = wi.ellipsoid_union(rng, 3, 300)
+    Q = rng.uniform(-0.5, 0.5, size=(200, 3))
+    W = orc.winding(V, F, Q)
+    R = wi.random_rotation(rng)
+    t = rng.normal(size=3)
+    s = 2.7
+    W2 = orc.winding(s * V @ R.T + t, F, s * Q @ R.T + t)
+    np.testing.assert_allclose(W2, W, atol=1e-11)
+    M = np.diag([-1.0, 1.0, 1.0])
+    W3 = orc.winding(V @ M, F, Q @ M)
+    np.testing.assert_allclose(W3, -W, atol=1e-11)
+
+
+def test_open_mesh_is_fractional(orc):
+    """A single hemisphere shell: points on the axis see the fraction of the sphere it
+    covers; far below the opening W -> 0; at the centre exactly 1/2 (half of the sphere)."""
+    V, F = wi.uv_ellipsoid(64, 32)
+    cen = (V[F].mean(1))
+    Fh = F[cen[:, 2] > 0]  # upper hemisphere (latitude bands split evenly at the equator)
+    W = orc.winding(V, Fh, [[0, 0, 0]])
+    assert W[0] == pytest.approx(0.5, abs=1e-12)
+
+
+def test_grid_point_layout(orc):
+    """Voxel centres lo + (idx + 1/2)(hi - lo)/n in C order (z fastest)."""
+    g = wi.Grid((-1.0, 0.0, 2.0), (1.0, 4.0, 3.0), (4, 2, 8))
+    Q = orc.grid_points(g)
+    assert Q.shape == (64, 3)
+    idx = wi.grid_flat_index(g, 3, 1, 5)
+    np.testing.assert_allclose(Q[idx], [-1 + 3.5 * 0.5, 0 + 1.5 * 2.0, 2 + 5.5 / 8])
+    np.testing.assert_allclose(Q[1] - Q[0], [0, 0, 1 / 8])
+
+
+# ------------------------------------------------------------------ gradient
+
+def test_gradient_vs_central_differences(orc):
+    """Analytic dOmega/dv_j against FP64 central differences of the oracle's Omega
+    and of L'Huilier's (independent) Omega."""
+    rng = np.random.default_rng(15)
+    h = 1e-6
+    for _ in range(60):
+        v = rng.normal(size=(3, 3))
+        q = rng.normal(size=3)
+        G = orc.solid_angle_grad(*v, q)
+        fd = np.zeros((3, 3))
+        fd2 = np.zeros((3, 3))
+        for j in range(3):
+            for c in range(3):
+                vp, vm = v.copy(), v.copy()
+                vp[j, c] += h
+                vm[j, c] -= h
+                fd[j, c] = (orc.solid_angle(*vp, q) - orc.solid_angle(*vm, q)) / (2 * h)
+                fd2[j, c] = (lhuilier_signed(vp, q) - lhuilier_signed(vm, q)) / (2 * h)
+        scale = max(1.0, np.abs(fd).max())
+        assert np.abs(G - fd).max() < 1e-6 * scale
+        assert np.abs(G - fd2).max() < 1e-6 * scale
+
+
+def test_gradient_translation_identity_biot_savart(orc):
+    """Moving all three vertices by d equals moving q by -d, so sum_j dOmega/dv_j =
+    -grad_q Omega, and grad_q Omega is the Biot-Savart sum over the boundary edges."""
+    rng = np.random.default_rng(16)
+    for _ in range(100):
+        v = rng.normal(size=(3, 3))
+        q = rng.normal(size=3)
+        G = orc.solid_angle_grad(*v, q)
+        np.testing.assert_allclose(G.sum(0), -biot_savart_grad_q(v, q), atol=1e-11, rtol=1e-9)
+
+
+def test_gradient_special_cases_zero(orc):
+    """q at a vertex or on an edge: the face contributes 0 to the gradient."""
+    rng = np.random.default_rng(17)
+    v = rng.normal(size=(3, 3))
+    assert np.all(orc.solid_angle_grad(*v, v[1]) == 0.0)
+    a = np.array([0.25, 0.5, -0.75])
+    b = a + np.array([0.0, 0.5, 0.0])
+    assert np.all(orc.solid_angle_grad(a, b, rng.normal(size=3), (a + b) / 2) == 0.0)
+
+
+def test_closed_mesh_vertex_gradient_vanishes(orc):
+    """W of a surface depends only on its boundary curve, so for a closed mesh every
+    vertex gradient is 0 (the paper notes the vanishing gradients of the binary field,
+    Section 2.4), while per-corner terms are not."""
+    c = wi.config1_icosphere()
+    rng = np.random.default_rng(18)
+    Q = rng.uniform(-0.5, 0.5, size=(64, 3))
+    g = rng.normal(size=64)
+    T, D = orc.grad(c.V, c.F, Q, g)
+    corner_scale = np.zeros((len(c.V), 3))
+    np.add.at(corner_scale, c.F.reshape(-1), np.abs(T.reshape(-1, 3)))
+    assert np.abs(T).max() > 1e-3
+    assert np.all(np.abs(D) <= 1e-9 * corner_scale + 1e-14)
+
+
+def test_open_mesh_gradient_vs_finite_differences(orc):
+    """Open mesh: dL/dV of L = sum_q g_q W_q matches central differences of the oracle's
+    W, and only vertices on the hole rims carry gradient."""
+    rng = np.random.default_rng(19)
+    V, F = wi.icosphere(1)
+    F = wi.delete_faces(F, 6, rng)
+    Q = rng.uniform(-1.2, 1.2, size=(40, 3))
+    g = rng.normal(size=40)
+    _, D = orc.grad(V, F, Q, g)
+    h = 1e-6
+    fd = np.zeros_like(V)
+    for i in range(len(V)):
+        for c in range(3):
+            Vp, Vm = V.copy(), V.copy()
+            Vp[i, c] += h
+            Vm[i, c] -= h
+            fd[i, c] = (g @ orc.winding(Vp, F, Q) - g @ orc.winding(Vm, F, Q)) / (2 * h)
+    np.testing.assert_allclose(D, fd, atol=1e-6)
+    # boundary (rim) vertices: those on an edge used by exactly one face
+    from collections import Counter
+    cnt = Counter()
+    for f in F:
+        for j in range(3):
+            a, b = f[j], f[(j + 1) % 3]
+            cnt[(min(a, b), max(a, b))] += 1
+    rim = set()
+    for (a, b), n in cnt.items():
+        if n == 1:
+            rim |= {a, b}
+    interior = np.array([i for i in range(len(V)) if i not in rim and i in set(F.reshape(-1))])
+    assert np.abs(D[interior]).max() < 1e-9
+    assert np.abs(D[sorted(rim)]).max() > 1e-3
+
+
+# ------------------------------------------------------------ guard distances
+
+def test_distance_functions(orc):
+    """Point-to-edge and point-to-face distances against closed forms and dense sampling."""
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+    F = np.array([[0, 1, 2]])
+    de, df = orc.min_dist(V, F, [[0.2, 0.2, 0.5], [2, 0, 0], [0.5, 0.5, 0.0], [-1, -1, 0]])
+    np.testing.assert_allclose(df, [0.5, 1.0, 0.0, math.sqrt(2)], atol=1e-15)
+    np.testing.assert_allclose(de, [math.sqrt(0.04 + 0.25), 1.0, 0.0, math.sqrt(2)], atol=1e-15)
+    rng = np.random.default_rng(20)
+    v = rng.normal(size=(3, 3))
+    u = rng.uniform(size=(200000, 2))
+    u = np.where(u.sum(1, keepdims=True) > 1, 1 - u, u)
+    S = v[0] + u[:, :1] * (v[1] - v[0]) + u[:, 1:] * (v[2] - v[0])
+    for q in rng.normal(size=(10, 3)):
+        _, d = orc.min_dist(v, F, [q])
+        ds = np.linalg.norm(S - q, axis=1).min()
+        assert d[0] <= ds + 1e-12 and ds - d[0] < 5e-3
+
+
+# ---------------------------------------------------------------- occupancy
+
+def test_occupancy_maps(orc):
+    """Hard map is strict (W = tau -> 0); the soft map is 1/2 at tau; sigmoid-MSE
+    gradient against central differences."""
+    W = np.array([0.0, 0.5, 0.5000001, 1.0, 2.0, -1.0])
+    np.testing.assert_array_equal(orc.occupancy_threshold(W), [0, 0, 1, 1, 1, 0])
+    assert orc.occupancy_sigmoid([0.5])[0] == 0.5
+    rng = np.random.default_rng(21)
+    W = rng.uniform(0.3, 0.7, 50)
+    t = (rng.uniform(size=50) > 0.5).astype(float)
+    _, g = orc.sigmoid_mse(W, t, 0.5, 50.0)
+    h = 1e-6
+    for i in range(0, 50, 7):
+        Wp, Wm = W.copy(), W.copy()
+        Wp[i] += h
+        Wm[i] -= h
+        fd = (orc.sigmoid_mse(Wp, t)[0] - orc.sigmoid_mse(Wm, t)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=5e-3, abs=1e-12)
+
+
+def test_thread_count_does_not_change_results(orc):
+    c = wi.config1_icosphere()
+    rng = np.random.default_rng(22)
+    Q = rng.uniform(-0.5, 0.5, size=(100, 3))
+    a = orc.winding(c.V, c.F, Q, threads=1)
+    b = orc.winding(c.V, c.F, Q, threads=4)
+    np.testing.assert_array_equal(a, b)
