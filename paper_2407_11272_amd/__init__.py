@@ -1,0 +1,22 @@
+"""MI355X (gfx950) generalized-winding-number voxelization (arXiv 2407.11272).
+
+The compute path is the HIP library ``libwn.so`` (C ABI in ``include/wn.h``);
+this package only marshals torch tensors and streams into it.  Importing the
+package does not load the library; the first call does, and raises if it has
+not been built (there is no CPU fallback).
+"""
+from .api import (  # noqa: F401
+    Grid,
+    Workspace,
+    as_mesh,
+    voxelize,
+    wn_backward,
+    wn_get_device_error,
+    wn_occupancy,
+    wn_sigmoid_mse,
+    wn_version,
+    wn_voxelize,
+    wn_workspace_size,
+)
+from ._lib import WnError  # noqa: F401
+from .autograd import SigmoidOccupancy, WindingNumber, soft_occupancy, winding_number  # noqa: F401

@@ -1,0 +1,219 @@
+"""Thin torch-facing binding of the C ABI: argument marshalling only.
+
+Each ``wn_*`` function here has the name and meaning of the C entry point in
+``include/wn.h``; every step of the computation runs in the HIP library.  PyTorch
+provides device memory (tensors, workspaces) and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_OCC_MODES = {None: L.WN_OCC_NONE, "none": L.WN_OCC_NONE, "threshold": L.WN_OCC_THRESHOLD,
+              "sigmoid": L.WN_OCC_SIGMOID}
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Voxel grid: ``n[d]`` cells spanning ``[lo[d], hi[d]]`` (centres at idx + 1/2)."""
+
+    lo: tuple = (-0.5, -0.5, -0.5)
+    hi: tuple = (0.5, 0.5, 0.5)
+    n: tuple = (32, 32, 32)
+
+    @staticmethod
+    def cube(res: int, lo: float = -0.5, hi: float = 0.5) -> "Grid":
+        return Grid((lo, lo, lo), (hi, hi, hi), (res, res, res))
+
+    @staticmethod
+    def of(g) -> "Grid":
+        return g if isinstance(g, Grid) else Grid(tuple(g.lo), tuple(g.hi), tuple(g.n))
+
+    @property
+    def size(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    def to_c(self) -> L.WnGrid:
+        g = L.WnGrid()
+        for d in range(3):
+            g.lo[d] = float(self.lo[d])
+            g.hi[d] = float(self.hi[d])
+            g.n[d] = int(self.n[d])
+        return g
+
+
+def _stream_handle(device: torch.device | None = None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Workspace:
+    """Grow-only device workspace per (device, stream), 256-byte aligned.
+
+    Calls on one stream run in order, so they may share its workspace."""
+
+    _cache: dict = {}
+
+    @classmethod
+    def get(cls, nbytes: int, device: torch.device) -> tuple[ctypes.c_void_p, int]:
+        key = (device.index, torch.cuda.current_stream(device).cuda_stream)
+        buf = cls._cache.get(key)
+        if buf is None or buf.numel() < nbytes + 256:
+            cap = max(nbytes + 256, 1 << 20, 0 if buf is None else int(buf.numel() * 1.5))
+            buf = torch.zeros(cap, dtype=torch.uint8, device=device)
+            cls._cache[key] = buf
+        base = buf.data_ptr()
+        off = (-base) % 256
+        return ctypes.c_void_p(base + off), int(buf.numel() - off)
+
+    @classmethod
+    def clear(cls):
+        cls._cache.clear()
+
+
+def _check_mesh(V: torch.Tensor, F: torch.Tensor):
+    if not V.is_cuda or not F.is_cuda:
+        raise ValueError("V and F must be device tensors (there is no CPU path)")
+    if V.dtype != torch.float32 or V.dim() != 2 or V.shape[1] != 3 or not V.is_contiguous():
+        raise ValueError("V must be a contiguous float32 [nV, 3] tensor")
+    if F.dtype != torch.int32 or F.dim() != 2 or F.shape[1] != 3 or not F.is_contiguous():
+        raise ValueError("F must be a contiguous int32 [nF, 3] tensor")
+
+
+def as_mesh(V: torch.Tensor, F: torch.Tensor, device=None):
+    """Cast a mesh to the library's layout (float32 vertices, int32 faces, contiguous)."""
+    device = torch.device(device) if device is not None else (V.device if V.is_cuda else torch.device("cuda"))
+    V = torch.as_tensor(V).to(device=device, dtype=torch.float32).contiguous()
+    F = torch.as_tensor(F).to(device=device, dtype=torch.int32).contiguous()
+    return V, F
+
+
+# ------------------------------------------------------------ C-ABI mirrors
+
+def wn_workspace_size(op: int, nV: int, nF: int, nQ: int) -> int:
+    return int(L.load().wn_workspace_size(op, nV, nF, nQ))
+
+
+def wn_voxelize(V, F, grid: Grid | None = None, Q: torch.Tensor | None = None, W: torch.Tensor | None = None,
+                occupancy: str | None = None, tau: float = 0.5, k: float = 50.0, occ: torch.Tensor | None = None):
+    """Winding number at the voxel centres of ``grid`` (or at the rows of ``Q``),
+    plus the occupancy map when ``occupancy`` is 'threshold' or 'sigmoid'.
+    Returns ``W`` or ``(W, occ)``; outputs may be passed in to avoid allocation."""
+    lib = L.load()
+    _check_mesh(V, F)
+    if (grid is None) == (Q is None):
+        raise ValueError("pass exactly one of grid or Q")
+    dev = V.device
+    if grid is not None:
+        grid = Grid.of(grid)
+        P, nQ, gptr, qptr = grid.size, 0, ctypes.byref(grid.to_c()), ctypes.c_void_p(0)
+        shape = tuple(int(x) for x in grid.n)
+    else:
+        if Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != 3 or not Q.is_contiguous() or not Q.is_cuda:
+            raise ValueError("Q must be a contiguous float32 [nQ, 3] device tensor")
+        P = nQ = Q.shape[0]
+        gptr, qptr = None, _ptr(Q)
+        shape = (P,)
+    mode = _OCC_MODES[occupancy]
+    if W is None:
+        W = torch.empty(shape, dtype=torch.float32, device=dev)
+    if mode != L.WN_OCC_NONE and occ is None:
+        occ = torch.empty(shape, dtype=torch.uint8 if mode == L.WN_OCC_THRESHOLD else torch.float32, device=dev)
+    need = wn_workspace_size(L.WN_OP_VOXELIZE, V.shape[0], F.shape[0], P)
+    ws, wsb = Workspace.get(need, dev)
+    st = lib.wn_voxelize(_ptr(V), V.shape[0], _ptr(F), F.shape[0], gptr, qptr, nQ, _ptr(W), mode, tau, k,
+                         _ptr(occ if mode != L.WN_OCC_NONE else None), ws, wsb, _stream_handle(dev))
+    L.check("wn_voxelize", st)
+    return W if mode == L.WN_OCC_NONE else (W, occ)
+
+
+def wn_occupancy(W: torch.Tensor, mode: str = "threshold", tau: float = 0.5, k: float = 50.0,
+                 occ: torch.Tensor | None = None) -> torch.Tensor:
+    m = _OCC_MODES[mode]
+    if m == L.WN_OCC_NONE:
+        raise ValueError("mode must be 'threshold' or 'sigmoid'")
+    if not W.is_contiguous() or W.dtype != torch.float32 or not W.is_cuda:
+        raise ValueError("W must be a contiguous float32 device tensor")
+    if occ is None:
+        occ = torch.empty(W.shape, dtype=torch.uint8 if m == L.WN_OCC_THRESHOLD else torch.float32, device=W.device)
+    st = L.load().wn_occupancy(_ptr(W), W.numel(), m, tau, k, _ptr(occ), _stream_handle(W.device))
+    L.check("wn_occupancy", st)
+    return occ
+
+
+def wn_sigmoid_mse(W: torch.Tensor, target: torch.Tensor, tau: float = 0.5, k: float = 50.0,
+                   want_loss: bool = True, want_grad: bool = True, loss: torch.Tensor | None = None,
+                   dLdW: torch.Tensor | None = None):
+    """(loss [1], dL/dW) of L = mean (sigmoid(k (W - tau)) - target)^2."""
+    if W.dtype != torch.float32 or target.dtype != torch.float32 or W.numel() != target.numel():
+        raise ValueError("W and target must be float32 tensors of equal size")
+    if not (W.is_contiguous() and target.is_contiguous() and W.is_cuda and target.is_cuda):
+        raise ValueError("W and target must be contiguous device tensors")
+    dev = W.device
+    if want_loss and loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    if want_grad and dLdW is None:
+        dLdW = torch.empty_like(W)
+    need = wn_workspace_size(L.WN_OP_LOSS, 0, 0, W.numel())
+    ws, wsb = Workspace.get(need, dev)
+    st = L.load().wn_sigmoid_mse(_ptr(W), _ptr(target), W.numel(), tau, k, _ptr(loss if want_loss else None),
+                                 _ptr(dLdW if want_grad else None), ws, wsb, _stream_handle(dev))
+    L.check("wn_sigmoid_mse", st)
+    return loss, dLdW
+
+
+def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None,
+                want_dLdT: bool = False, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None):
+    """dL/dV [nV, 3] (and dL/dT [nF, 3, 3] if requested) for the given dL/dW."""
+    lib = L.load()
+    _check_mesh(V, F)
+    if (grid is None) == (Q is None):
+        raise ValueError("pass exactly one of grid or Q")
+    dev = V.device
+    if grid is not None:
+        grid = Grid.of(grid)
+        P, nQ, gptr, qptr = grid.size, 0, ctypes.byref(grid.to_c()), ctypes.c_void_p(0)
+    else:
+        P = nQ = Q.shape[0]
+        gptr, qptr = None, _ptr(Q)
+    dLdW = dLdW.contiguous()
+    if dLdW.dtype != torch.float32 or dLdW.numel() != P or not dLdW.is_cuda:
+        raise ValueError("dLdW must be a float32 device tensor with one entry per query point")
+    if dLdV is None:
+        dLdV = torch.empty_like(V)
+    if want_dLdT and dLdT is None:
+        dLdT = torch.empty((F.shape[0], 3, 3), dtype=torch.float32, device=dev)
+    need = wn_workspace_size(L.WN_OP_BACKWARD, V.shape[0], F.shape[0], P)
+    ws, wsb = Workspace.get(need, dev)
+    st = lib.wn_backward(_ptr(V), V.shape[0], _ptr(F), F.shape[0], gptr, qptr, nQ, _ptr(dLdW), _ptr(dLdV),
+                         _ptr(dLdT if want_dLdT else None), ws, wsb, _stream_handle(dev))
+    L.check("wn_backward", st)
+    return (dLdV, dLdT) if want_dLdT else dLdV
+
+
+def wn_get_device_error(device=None) -> int:
+    """Status of the last call on the current stream's workspace (synchronises)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    ws, _ = Workspace.get(0, dev)
+    return int(L.load().wn_get_device_error(ws, _stream_handle(dev)))
+
+
+def wn_version() -> str:
+    return L.load().wn_version().decode()
+
+
+# ------------------------------------------------------------ conveniences
+
+def voxelize(V, F, grid=None, Q=None, occupancy: str | None = None, tau: float = 0.5, k: float = 50.0):
+    """Cast (V, F) to the library layout on the GPU and run :func:`wn_voxelize`."""
+    V, F = as_mesh(V, F)
+    if Q is not None:
+        Q = torch.as_tensor(Q).to(device=V.device, dtype=torch.float32).contiguous()
+    return wn_voxelize(V, F, grid=grid, Q=Q, occupancy=occupancy, tau=tau, k=k)

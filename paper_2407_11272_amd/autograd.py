@@ -1,0 +1,51 @@
+"""Differentiable voxelization: ``torch.autograd.Function`` wrappers whose forward
+and backward both run in the HIP library (Section 2.4 of arXiv 2407.11272 uses the
+gradient of the voxelization with respect to the mesh vertices)."""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class WindingNumber(torch.autograd.Function):
+    """W = winding number of (V, F) at the centres of ``grid`` (or the rows of ``Q``);
+    differentiable in V.  Backward recomputes solid angles per tile (no stored
+    point x face matrix) and returns dL/dV."""
+
+    @staticmethod
+    def forward(ctx, V, F, grid=None, Q=None):
+        ctx.save_for_backward(V, F, Q)
+        ctx.grid = grid
+        return api.wn_voxelize(V, F, grid=grid, Q=Q)
+
+    @staticmethod
+    def backward(ctx, gW):
+        V, F, Q = ctx.saved_tensors
+        g = gW.contiguous().reshape(-1).to(torch.float32)
+        dLdV = api.wn_backward(V, F, g, grid=ctx.grid, Q=Q)
+        return dLdV, None, None, None
+
+
+class SigmoidOccupancy(torch.autograd.Function):
+    """occ = sigmoid(k (W - tau)) on the device; backward k occ (1 - occ) g."""
+
+    @staticmethod
+    def forward(ctx, W, tau: float = 0.5, k: float = 50.0):
+        occ = api.wn_occupancy(W.contiguous(), "sigmoid", tau, k)
+        ctx.save_for_backward(occ)
+        ctx.k = k
+        return occ
+
+    @staticmethod
+    def backward(ctx, g):
+        (occ,) = ctx.saved_tensors
+        return g * ctx.k * occ * (1.0 - occ), None, None
+
+
+def winding_number(V, F, grid=None, Q=None):
+    return WindingNumber.apply(V, F, grid, Q)
+
+
+def soft_occupancy(V, F, grid=None, Q=None, tau: float = 0.5, k: float = 50.0):
+    return SigmoidOccupancy.apply(WindingNumber.apply(V, F, grid, Q), tau, k)

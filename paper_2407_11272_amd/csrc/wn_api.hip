@@ -1,0 +1,179 @@
+// C ABI entry points declared in include/wn.h: argument checks, workspace
+// layout and the launch sequence of each call.  No entry point allocates device
+// memory or synchronises (except wn_get_device_error).
+#include <string.h>
+
+#include "wn_internal.hpp"
+
+using namespace wn;
+
+namespace {
+
+constexpr int64_t kMaxCount = 2147483647LL;  // 2^31 - 1
+
+bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+wn_status hip_status(hipError_t e) { return e == hipSuccess ? WN_OK : WN_ERR_HIP; }
+
+// Number of query points described by (grid, Q, nQ), or -1 when inconsistent.
+int64_t query_count(const wn_grid *grid, const float *Q, int64_t nQ) {
+    if ((grid == nullptr) == (Q == nullptr)) return -1;
+    if (nQ < 0) return -1;
+    if (!grid) return nQ <= kMaxCount ? nQ : -1;
+    int64_t p = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (grid->n[d] < 0) return -1;
+        p *= grid->n[d];
+        if (p > kMaxCount) return -1;
+    }
+    if (nQ != 0 && nQ != p) return -1;
+    return p;
+}
+
+bool mesh_ok(const float *V, int64_t nV, const int32_t *F, int64_t nF) {
+    if (nV < 0 || nF < 0 || nV > kMaxCount || nF > kMaxCount) return false;
+    if (nF > 0 && (V == nullptr || F == nullptr || nV == 0)) return false;
+    return true;
+}
+
+size_t voxelize_ws(int64_t nF, int64_t nQ) {
+    const int split = fwd_split_count(nF, nQ);
+    size_t b = kWsHeader + align_up((size_t)nF * sizeof(FaceRec));
+    if (split > 1) b += align_up((size_t)split * (size_t)nQ * sizeof(float));
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
+    if (nV < 0 || nF < 0 || nQ < 0) return 0;
+    switch (op) {
+        case WN_OP_VOXELIZE:
+            return voxelize_ws(nF, nQ);
+        case WN_OP_BACKWARD:
+            return bwd_workspace(nV, nF, nQ);
+        case WN_OP_BATCHED:
+            return batched_workspace(nV, nF, nQ);
+        case WN_OP_LOSS:
+            return kWsHeader + align_up((size_t)loss_blocks(nQ) * sizeof(float));
+        default:
+            return 0;
+    }
+}
+
+wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                      const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
+                      void *ws, size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
+    const int64_t P = query_count(grid, Q, nQ);
+    if (P < 0) return WN_ERR_INVALID_ARG;
+    if (occ_mode != WN_OCC_NONE && occ_mode != WN_OCC_THRESHOLD && occ_mode != WN_OCC_SIGMOID)
+        return WN_ERR_INVALID_ARG;
+    if (P > 0 && W == nullptr) return WN_ERR_INVALID_ARG;
+    if (P > 0 && occ_mode != WN_OCC_NONE && occ == nullptr) return WN_ERR_INVALID_ARG;
+    if (grid)
+        for (int d = 0; d < 3; ++d)
+            if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
+    const size_t need = voxelize_ws(nF, P);
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
+    if (P == 0) return WN_OK;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(base);
+    FaceRec *soup = reinterpret_cast<FaceRec *>(base + kWsHeader);
+    float *partials = reinterpret_cast<float *>(base + kWsHeader + align_up((size_t)nF * sizeof(FaceRec)));
+    const int split = fwd_split_count(nF, P);
+    OccParams op{occ, occ_mode, tau, k};
+
+    hipError_t e = launch_ws_reset(hdr, s);
+    if (e == hipSuccess) e = launch_pack(V, nV, F, nF, soup, hdr, s);
+    if (e == hipSuccess) e = launch_fwd(soup, nF, make_point_src(grid, Q), P, split, W, partials, op, s);
+    return hip_status(e);
+}
+
+wn_status wn_occupancy(const float *W, int64_t n, int32_t mode, float tau, float k, void *occ, void *stream) {
+    if (n < 0) return WN_ERR_INVALID_ARG;
+    if (mode != WN_OCC_THRESHOLD && mode != WN_OCC_SIGMOID) return WN_ERR_INVALID_ARG;
+    if (n == 0) return WN_OK;
+    if (W == nullptr || occ == nullptr) return WN_ERR_INVALID_ARG;
+    OccParams op{occ, mode, tau, k};
+    return hip_status(launch_occ(W, n, op, static_cast<hipStream_t>(stream)));
+}
+
+wn_status wn_sigmoid_mse(const float *W, const float *target, int64_t n, float tau, float k, float *loss,
+                         float *dLdW, void *ws, size_t ws_bytes, void *stream) {
+    if (n < 0 || n > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (n > 0 && (W == nullptr || target == nullptr)) return WN_ERR_INVALID_ARG;
+    if (loss == nullptr && dLdW == nullptr) return WN_ERR_INVALID_ARG;
+    const size_t need = kWsHeader + align_up((size_t)loss_blocks(n) * sizeof(float));
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
+    float *scratch = reinterpret_cast<float *>(static_cast<char *>(ws) + kWsHeader);
+    return hip_status(launch_sigmoid_mse(W, target, n, tau, k, loss, dLdW, scratch, static_cast<hipStream_t>(stream)));
+}
+
+wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                      const float *Q, int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, void *ws,
+                      size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
+    const int64_t P = query_count(grid, Q, nQ);
+    if (P < 0) return WN_ERR_INVALID_ARG;
+    if (nV > 0 && dLdV == nullptr) return WN_ERR_INVALID_ARG;
+    if (P > 0 && nF > 0 && dLdW == nullptr) return WN_ERR_INVALID_ARG;
+    if (grid)
+        for (int d = 0; d < 3; ++d)
+            if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
+    const size_t need = bwd_workspace(nV, nF, P);
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
+    return run_backward(V, nV, F, nF, make_point_src(grid, Q), P, dLdW, dLdV, dLdT, static_cast<char *>(ws),
+                        ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+wn_status wn_voxelize_batched(const wn_mesh_desc *desc, int32_t n, int32_t flags, void *ws, size_t ws_bytes,
+                              void *stream) {
+    if (n < 0 || (n > 0 && desc == nullptr)) return WN_ERR_INVALID_ARG;
+    if (flags & ~WN_BATCH_NO_GRAPH) return WN_ERR_INVALID_ARG;
+    if (n == 0) return WN_OK;
+    if (ws == nullptr || !aligned256(ws)) return WN_ERR_WORKSPACE;
+    return run_batched(desc, n, flags, static_cast<char *>(ws), ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+wn_status wn_get_device_error(void *ws, void *stream) {
+    if (ws == nullptr || !aligned256(ws)) return WN_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WsHeader *hdr = static_cast<WsHeader *>(ws);
+    int32_t flag = 0;
+    if (hipMemcpyAsync(&flag, &hdr->bad_index, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return WN_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return WN_ERR_HIP;
+    if (flag != 0) {
+        if (launch_ws_reset(hdr, s) != hipSuccess) return WN_ERR_HIP;
+        return WN_ERR_BAD_INDEX;
+    }
+    return WN_OK;
+}
+
+const char *wn_status_string(wn_status st) {
+    switch (st) {
+        case WN_OK:
+            return "ok";
+        case WN_ERR_INVALID_ARG:
+            return "invalid argument";
+        case WN_ERR_HIP:
+            return "HIP runtime error";
+        case WN_ERR_WORKSPACE:
+            return "workspace missing, misaligned or too small";
+        case WN_ERR_BAD_INDEX:
+            return "face index out of range (replaced by 0 on the device)";
+        case WN_ERR_UNSUPPORTED:
+            return "unsupported";
+        default:
+            return "unknown status";
+    }
+}
+
+const char *wn_version(void) { return "wn-gfx950 0.1"; }
+
+}  // extern "C"

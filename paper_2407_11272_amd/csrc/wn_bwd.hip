@@ -1,0 +1,275 @@
+// Adjoint of the winding number with respect to the mesh vertices.
+//
+// The paper (arXiv 2407.11272, Section 2.4) relies on the voxelization being
+// differentiable in the vertices but gives no gradient formula.  With
+// t = ATAN2(alpha, beta) the half solid angle of Eq. 7/8 and e_j = R_j / |R_j|:
+//   dt = (beta dalpha - alpha dbeta) / (alpha^2 + beta^2)
+//   dalpha/de_j = e_k x e_l,  dbeta/de_j = e_k + e_l        ((j, k, l) cyclic)
+//   de_j/dv_j = (I - e_j e_j^T) / |R_j|
+// so dt/dv_j = P_j (beta u_j - alpha s_j) / (|R_j| (alpha^2 + beta^2)) with
+// u_j = e_k x e_l, s_j = e_k + e_l, P_j the projector orthogonal to e_j, and
+// dW/dv_j = dt/dv_j / (2 pi) (W = sum t / (2 pi)).
+//
+// Layout of the work (this library's own design):
+//   * one lane owns one face and keeps its 9 gradient sums in registers;
+//   * query points (with their dL/dW) stream through LDS and are read by every
+//     lane (broadcast), solid angles are recomputed per pair, nothing of size
+//     points x faces is stored;
+//   * the points are split over workgroups; the per-split partial sums are added
+//     in a fixed order, then corners are grouped per vertex by a stable radix sort
+//     of their vertex ids and summed in face order -- deterministic throughout.
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "wn_internal.hpp"
+
+namespace wn {
+
+constexpr int kPointTile = kBlock;  // points staged per tile (one per thread)
+
+// dL/dv partial sums of one face over a range of points.  Grid: x = face blocks,
+// y = point splits.  partials layout: [split][9][nF].
+__global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ soup, int32_t nF, PointSrc ps,
+                                                   int64_t nQ, int64_t chunkP, const float *__restrict__ dLdW,
+                                                   float *__restrict__ partials) {
+    __shared__ float4 pts[kPointTile];
+    const int tid = threadIdx.x;
+    int32_t f = (int32_t)blockIdx.x * kBlock + tid;
+    const bool live = f < nF;
+    f = live ? f : nF - 1;
+    const FaceRec r = soup[f];
+    const float v[3][3] = {{r.a.x, r.a.y, r.a.z}, {r.a.w, r.b.x, r.b.y}, {r.b.z, r.b.w, r.c.x}};
+
+    float s[9], c[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s[i] = c[i] = 0.0f;
+
+    const int64_t p0 = (int64_t)blockIdx.y * chunkP;
+    const int64_t p1 = min(nQ, p0 + chunkP);
+    for (int64_t t0 = p0; t0 < p1; t0 += kPointTile) {
+        const int nt = (int)min((int64_t)kPointTile, p1 - t0);
+        __syncthreads();
+        if (tid < nt) {
+            float x, y, z;
+            ps.get(t0 + tid, x, y, z);
+            pts[tid] = make_float4(x, y, z, dLdW[t0 + tid]);
+        }
+        __syncthreads();
+        float ts[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ts[i] = 0.0f;
+        for (int i = 0; i < nt; ++i) {
+            const float4 q = pts[i];
+            float e[3][3], ri[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const float rx = v[j][0] - q.x, ry = v[j][1] - q.y, rz = v[j][2] - q.z;
+                const float l2 = rx * rx + ry * ry + rz * rz;
+                ri[j] = (l2 > 0.0f) ? __builtin_amdgcn_rsqf(l2) : 0.0f;
+                e[j][0] = rx * ri[j];
+                e[j][1] = ry * ri[j];
+                e[j][2] = rz * ri[j];
+            }
+            float u[3][3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int k = (j + 1) % 3, l = (j + 2) % 3;
+                u[j][0] = e[k][1] * e[l][2] - e[k][2] * e[l][1];
+                u[j][1] = e[k][2] * e[l][0] - e[k][0] * e[l][2];
+                u[j][2] = e[k][0] * e[l][1] - e[k][1] * e[l][0];
+            }
+            const float alpha = e[0][0] * u[0][0] + e[0][1] * u[0][1] + e[0][2] * u[0][2];
+            const float d01 = e[0][0] * e[1][0] + e[0][1] * e[1][1] + e[0][2] * e[1][2];
+            const float d12 = e[1][0] * e[2][0] + e[1][1] * e[2][1] + e[1][2] * e[2][2];
+            const float d20 = e[2][0] * e[0][0] + e[2][1] * e[0][1] + e[2][2] * e[0][2];
+            const float beta = 1.0f + d01 + d12 + d20;
+            const float den = alpha * alpha + beta * beta;
+            const float gk = (den > 0.0f) ? q.w * __builtin_amdgcn_rcpf(den) : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int k = (j + 1) % 3, l = (j + 2) % 3;
+                float w[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) w[d] = beta * u[j][d] - alpha * (e[k][d] + e[l][d]);
+                const float we = w[0] * e[j][0] + w[1] * e[j][1] + w[2] * e[j][2];
+                const float coef = gk * ri[j];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ts[3 * j + d] += coef * (w[d] - we * e[j][d]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) neumaier_add(s[i], c[i], ts[i]);
+    }
+    if (live) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) partials[((int64_t)blockIdx.y * 9 + i) * nF + f] = s[i] + c[i];
+    }
+}
+
+// T[f][i] = sum over splits (fixed order) / (2 pi).
+__global__ __launch_bounds__(kBlock) void k_bwd_reduce(const float *__restrict__ partials, int32_t split, int32_t nF,
+                                                       float *__restrict__ T) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nF * 9) return;
+    const int32_t i = (int32_t)(t / nF);
+    const int32_t f = (int32_t)(t - (int64_t)i * nF);
+    float s = 0.0f, c = 0.0f;
+    for (int32_t k = 0; k < split; ++k) neumaier_add(s, c, partials[((int64_t)k * 9 + i) * nF + f]);
+    T[(int64_t)f * 9 + i] = (s + c) * kInv2Pi;
+}
+
+// Sort keys: the vertex of each corner (out-of-range ids read as 0, as in packing).
+__global__ __launch_bounds__(kBlock) void k_corner_keys(const int32_t *__restrict__ F, int64_t nC, int64_t nV,
+                                                        int32_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nC) return;
+    const int32_t v = F[c];
+    keys[c] = (v < 0 || (int64_t)v >= nV) ? 0 : v;
+    vals[c] = (int32_t)c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t value) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// Run boundaries of the sorted vertex ids.
+__global__ __launch_bounds__(kBlock) void k_bounds(const int32_t *__restrict__ keys, int64_t nC,
+                                                   int32_t *__restrict__ vstart, int32_t *__restrict__ vend) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nC) return;
+    const int32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) vstart[k] = (int32_t)i;
+    if (i == nC - 1 || keys[i + 1] != k) vend[k] = (int32_t)(i + 1);
+}
+
+// dL/dV[v] = sum of the corner gradients of v in increasing corner order.
+__global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ T, const int32_t *__restrict__ corners,
+                                                   const int32_t *__restrict__ vstart,
+                                                   const int32_t *__restrict__ vend, int64_t nV,
+                                                   float *__restrict__ dLdV) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nV) return;
+    float s[3] = {0.0f, 0.0f, 0.0f}, c[3] = {0.0f, 0.0f, 0.0f};
+    for (int32_t i = vstart[v]; i < vend[v]; ++i) {
+        const int64_t cn = corners[i];
+        for (int d = 0; d < 3; ++d) neumaier_add(s[d], c[d], T[3 * cn + d]);
+    }
+    for (int d = 0; d < 3; ++d) dLdV[3 * v + d] = s[d] + c[d];
+}
+
+// ------------------------------------------------------------------ host
+
+namespace {
+
+struct BwdPlan {
+    int split;
+    int64_t chunkP;
+    unsigned bits;
+    size_t sort_tmp;
+    size_t off_soup, off_part, off_T, off_keys, off_vals, off_keys2, off_vals2, off_tmp, off_vs, off_ve, total;
+};
+
+BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ) {
+    BwdPlan p{};
+    const int64_t face_waves = (nF + 63) / 64;
+    int64_t sp = (8192 + face_waves - 1) / (face_waves > 0 ? face_waves : 1);
+    if (sp > 512) sp = 512;
+    const int64_t max_by_points = (nQ + kPointTile - 1) / kPointTile;
+    if (sp > max_by_points) sp = max_by_points;
+    if (sp < 1) sp = 1;
+    int64_t chunk = (nQ + sp - 1) / sp;
+    chunk = (chunk + kPointTile - 1) / kPointTile * kPointTile;
+    if (chunk < kPointTile) chunk = kPointTile;
+    p.chunkP = chunk;
+    p.split = (int)((nQ + chunk - 1) / chunk);
+    if (p.split < 1) p.split = 1;
+    unsigned bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < nV) ++bits;
+    p.bits = bits;
+    const int64_t nC = 3 * nF;
+    size_t tmp = 0;
+    if (nC > 0)
+        (void)rocprim::radix_sort_pairs(nullptr, tmp, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
+                                  (int32_t *)nullptr, (size_t)nC, 0u, bits);
+    p.sort_tmp = tmp;
+    size_t o = kWsHeader;
+    p.off_soup = o;
+    o += align_up((size_t)nF * sizeof(FaceRec));
+    p.off_part = o;
+    o += align_up((size_t)p.split * 9 * (size_t)nF * sizeof(float));
+    p.off_T = o;
+    o += align_up((size_t)nF * 9 * sizeof(float));
+    p.off_keys = o;
+    o += align_up((size_t)nC * 4);
+    p.off_vals = o;
+    o += align_up((size_t)nC * 4);
+    p.off_keys2 = o;
+    o += align_up((size_t)nC * 4);
+    p.off_vals2 = o;
+    o += align_up((size_t)nC * 4);
+    p.off_tmp = o;
+    o += align_up(tmp);
+    p.off_vs = o;
+    o += align_up((size_t)nV * 4);
+    p.off_ve = o;
+    o += align_up((size_t)nV * 4);
+    p.total = o;
+    return p;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ) { return plan_backward(nV, nF, nQ).total; }
+
+wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps, int64_t nQ,
+                       const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes, hipStream_t s) {
+    const BwdPlan p = plan_backward(nV, nF, nQ);
+    if (ws_bytes < p.total) return WN_ERR_WORKSPACE;
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+    FaceRec *soup = reinterpret_cast<FaceRec *>(ws + p.off_soup);
+    float *partials = reinterpret_cast<float *>(ws + p.off_part);
+    float *T = dLdT ? dLdT : reinterpret_cast<float *>(ws + p.off_T);
+    int32_t *keys = reinterpret_cast<int32_t *>(ws + p.off_keys);
+    int32_t *vals = reinterpret_cast<int32_t *>(ws + p.off_vals);
+    int32_t *keys2 = reinterpret_cast<int32_t *>(ws + p.off_keys2);
+    int32_t *vals2 = reinterpret_cast<int32_t *>(ws + p.off_vals2);
+    int32_t *vs = reinterpret_cast<int32_t *>(ws + p.off_vs);
+    int32_t *ve = reinterpret_cast<int32_t *>(ws + p.off_ve);
+
+    hipError_t e = launch_ws_reset(hdr, s);
+    if (e != hipSuccess) return WN_ERR_HIP;
+    if (nV == 0) return WN_OK;
+    if (nF == 0) {
+        k_fill_i32<<<blocks_for(3 * nV), kBlock, 0, s>>>(reinterpret_cast<int32_t *>(dLdV), 3 * nV, 0);
+        return hipGetLastError() == hipSuccess ? WN_OK : WN_ERR_HIP;
+    }
+    e = launch_pack(V, nV, F, nF, soup, hdr, s);
+    if (e != hipSuccess) return WN_ERR_HIP;
+    if (nQ > 0) {
+        k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)p.split), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.chunkP,
+                                                                              dLdW, partials);
+        if ((e = hipGetLastError()) != hipSuccess) return WN_ERR_HIP;
+        k_bwd_reduce<<<blocks_for(9 * nF), kBlock, 0, s>>>(partials, p.split, (int32_t)nF, T);
+    } else {
+        k_fill_i32<<<blocks_for(9 * nF), kBlock, 0, s>>>(reinterpret_cast<int32_t *>(T), 9 * nF, 0);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return WN_ERR_HIP;
+
+    const int64_t nC = 3 * nF;
+    k_corner_keys<<<blocks_for(nC), kBlock, 0, s>>>(F, nC, nV, keys, vals);
+    if ((e = hipGetLastError()) != hipSuccess) return WN_ERR_HIP;
+    size_t tmp = p.sort_tmp;
+    e = rocprim::radix_sort_pairs(ws + p.off_tmp, tmp, keys, keys2, vals, vals2, (size_t)nC, 0u, p.bits, s);
+    if (e != hipSuccess) return WN_ERR_HIP;
+    k_fill_i32<<<blocks_for(nV), kBlock, 0, s>>>(vs, nV, 0);
+    k_fill_i32<<<blocks_for(nV), kBlock, 0, s>>>(ve, nV, 0);
+    k_bounds<<<blocks_for(nC), kBlock, 0, s>>>(keys2, nC, vs, ve);
+    k_gather<<<blocks_for(nV), kBlock, 0, s>>>(T, vals2, vs, ve, nV, dLdV);
+    return hipGetLastError() == hipSuccess ? WN_OK : WN_ERR_HIP;
+}
+
+}  // namespace wn

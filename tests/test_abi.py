@@ -1,0 +1,57 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/wn.h declares, and answers the host-only queries (no GPU calls)."""
+import os
+import re
+
+import pytest
+
+import paper_2407_11272_amd as wn
+from paper_2407_11272_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "wn.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"WN_API\s+[\w\s\*]*?\b(wn_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_expected_entry_points():
+    assert declared_symbols() == sorted(L.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    out = os.popen(f"nm -D --defined-only {L.LIB_PATH}").read()
+    exported = set(re.findall(r" T (wn_\w+)", out))
+    assert set(declared_symbols()) <= exported
+    # nothing else leaks out of the library under the wn_ prefix
+    assert exported == set(declared_symbols())
+
+
+def test_status_strings_and_version():
+    for s in (L.WN_OK, L.WN_ERR_INVALID_ARG, L.WN_ERR_HIP, L.WN_ERR_WORKSPACE, L.WN_ERR_BAD_INDEX,
+              L.WN_ERR_UNSUPPORTED):
+        assert L.status_string(s) and L.status_string(s) != "unknown status"
+    assert L.status_string(12345) == "unknown status"
+    assert "gfx950" in wn.wn_version()
+
+
+def test_workspace_sizes_are_host_only_and_monotone():
+    s1 = wn.wn_workspace_size(L.WN_OP_VOXELIZE, 642, 1280, 32 ** 3)
+    s2 = wn.wn_workspace_size(L.WN_OP_VOXELIZE, 10016, 19000, 128 ** 3)
+    assert s1 >= 256 + 48 * 1280 and s2 >= 256 + 48 * 19000
+    assert wn.wn_workspace_size(L.WN_OP_VOXELIZE, 0, 0, 0) == 256
+    b = wn.wn_workspace_size(L.WN_OP_BACKWARD, 2562, 5120, 64 ** 3)
+    assert b >= 256 + 48 * 5120 + 9 * 4 * 5120
+    assert wn.wn_workspace_size(L.WN_OP_LOSS, 0, 0, 1000) >= 256 + 4
+    assert wn.wn_workspace_size(99, 1, 1, 1) == 0
+    assert wn.wn_workspace_size(L.WN_OP_VOXELIZE, -1, 1, 1) == 0
+
+
+def test_no_cpu_fallback_on_host_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        wn.wn_voxelize(torch.zeros((3, 3)), torch.zeros((1, 3), dtype=torch.int32), grid=wn.Grid.cube(2))

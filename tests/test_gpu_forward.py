@@ -1,0 +1,237 @@
+"""GPU forward parity: the HIP library through its C ABI against the FP64 oracle.
+
+Tolerances (stated by the method's target): |W_gpu - W_ref| <= 1e-4 at every point
+outside the guard band E (within 1e-4 of an edge or vertex, or 1e-6 of a face, where
+FP32 cannot resolve the field; Section 2.2 notes the field is binary except on the
+surface), and hard occupancy bit-identical where additionally |W_ref - 0.5| > 1e-3.
+Sigmoid occupancy (k = 50): |docc| <= (k/4) 1e-4 + 1e-6 = 1.25e-3.
+"""
+import numpy as np
+import pytest
+
+import wn_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+TOL_W = 1e-4
+BAND = 1e-3
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_11272_amd as wn
+    wn.wn_version()  # loads libwn.so or raises
+    return torch.device("cuda", 0)
+
+
+def _gpu_w(V, F, grid=None, Q=None, occupancy=None, **kw):
+    import torch
+    import paper_2407_11272_amd as wn
+    Vt = torch.as_tensor(np.asarray(V, np.float32)).cuda()
+    Ft = torch.as_tensor(np.asarray(F, np.int32)).cuda()
+    Qt = None if Q is None else torch.as_tensor(np.asarray(Q, np.float32)).cuda()
+    g = None if grid is None else wn.Grid.of(grid)
+    out = wn.wn_voxelize(Vt, Ft, grid=g, Q=Qt, occupancy=occupancy, **kw)
+    torch.cuda.synchronize()
+    if occupancy is None:
+        return out.cpu().numpy().reshape(-1)
+    return out[0].cpu().numpy().reshape(-1), out[1].cpu().numpy().reshape(-1)
+
+
+def _f32(V):
+    """The GPU sees float32 vertices; the oracle is given the same rounded values."""
+    return np.asarray(V, np.float32).astype(np.float64)
+
+
+def _compare(orc, V, F, Q, Wg, label, occ_g=None, tau=0.5):
+    V64 = _f32(V)
+    Wr = orc.winding(V64, F, Q)
+    guard = orc.guard_mask(V64, F, Q)
+    err = np.abs(Wg.astype(np.float64) - Wr)
+    ok = ~guard
+    print(f"[{label}] points={len(Q)} guard={int(guard.sum())} max|dW| off-guard={err[ok].max() if ok.any() else 0:.3e}"
+          f" on-guard={err[guard].max() if guard.any() else 0:.3e}", flush=True)
+    assert guard.sum() <= max(2, 1e-3 * len(Q)), "guard band unexpectedly large"
+    assert np.all(err[ok] <= TOL_W), f"{label}: max |dW| {err[ok].max():.3e}"
+    if occ_g is not None:
+        m = ok & (np.abs(Wr - tau) > BAND)
+        ref = orc.occupancy_threshold(Wr, tau)
+        np.testing.assert_array_equal(occ_g[m], ref[m])
+    return Wr, guard
+
+
+def test_config1_full_grid(dev, orc):
+    """Plain forward on the 1280-face jittered icosphere at 32^3: every voxel."""
+    c = wi.config1_icosphere()
+    Q = orc.grid_points(c.grid)
+    Wg, occ = _gpu_w(c.V, c.F, grid=c.grid, occupancy="threshold")
+    Wr, _ = _compare(orc, c.V, c.F, Q, Wg, "C1", occ_g=occ)
+    assert 0.05 < (Wr > 0.5).mean() < 0.5
+
+
+def test_config2_full_size_sampled(dev, orc):
+    """Non-watertight union (19 000 faces) at 128^3 in the benchmark's launch
+    configuration; the oracle checks 3000 seeded voxels plus the first and last."""
+    c = wi.config2_ellipsoid_union()
+    Wg, occ = _gpu_w(c.V, c.F, grid=c.grid, occupancy="threshold")
+    assert Wg.shape == (128 ** 3,)
+    rng = np.random.default_rng(100)
+    idx = np.unique(np.concatenate([rng.integers(0, len(Wg), 3000), [0, len(Wg) - 1]]))
+    Qall = orc.grid_points(c.grid)
+    _compare(orc, c.V, c.F, Qall[idx], Wg[idx], "C2-sampled", occ_g=occ[idx])
+    assert np.isfinite(Wg).all()
+
+
+def test_config3_mesh_full_grid(dev, orc):
+    """The 5120-face icosphere of the differentiable workload at 64^3 (forward)."""
+    c = wi.config3_differentiable()
+    Q = orc.grid_points(c.grid)
+    rng = np.random.default_rng(101)
+    idx = rng.choice(len(Q), 20000, replace=False)
+    Wg = _gpu_w(c.V, c.F, grid=c.grid)
+    _compare(orc, c.V, c.F, Q[idx], Wg[idx], "C3")
+
+
+@pytest.mark.parametrize("nF", [1, 2, 5, 16, 63, 64, 65, 129, 300])
+def test_random_small_meshes_point_list(dev, orc, nF):
+    """Random triangles (tile boundaries at 64 faces) and random points in list mode,
+    a ragged point count, and the face-split path (few points)."""
+    rng = np.random.default_rng(1000 + nF)
+    V = rng.uniform(-0.6, 0.6, size=(3 * nF, 3))
+    F = rng.permutation(3 * nF).reshape(nF, 3)
+    Q = rng.uniform(-0.7, 0.7, size=(1000 + nF, 3)).astype(np.float32).astype(np.float64)
+    Wg = _gpu_w(V, F, Q=Q)
+    _compare(orc, V, F, Q, Wg, f"random nF={nF}")
+
+
+@pytest.mark.parametrize("shape", [(7, 9, 11), (1, 1, 1), (3, 64, 5), (33, 17, 2)])
+def test_ragged_grids(dev, orc, shape):
+    """Non-cubic grids with odd sizes and a non-symmetric extent."""
+    c = wi.config1_icosphere()
+    g = wi.Grid((-0.45, -0.5, -0.41), (0.47, 0.43, 0.5), shape)
+    Q = orc.grid_points(g)
+    Wg = _gpu_w(c.V, c.F, grid=g)
+    assert Wg.shape == (int(np.prod(shape)),)
+    # the fp32 voxel centres differ from the fp64 ones by rounding only
+    _compare(orc, c.V, c.F, Q, Wg, f"grid {shape}")
+
+
+def test_orientation_flip_and_determinism(dev, orc):
+    c = wi.config1_icosphere()
+    W1 = _gpu_w(c.V, c.F, grid=c.grid)
+    W2 = _gpu_w(c.V, c.F, grid=c.grid)
+    np.testing.assert_array_equal(W1, W2)  # bit-identical reruns
+    Wr = _gpu_w(c.V, wi.reverse_faces(c.F), grid=c.grid)
+    np.testing.assert_allclose(Wr, -W1, atol=2e-6)
+
+
+def test_cube_closed_forms(dev, orc):
+    """Closed unit cube: centre 1, vertices 1/8 (the faces at the vertex give 0), far 0."""
+    V, F = wi.cube_mesh(0.0, 1.0)
+    Q = np.array([[0.5, 0.5, 0.5], [0, 0, 0], [1, 1, 1], [1, 0, 1], [3, 3, 3], [-1, 0.5, 0.5], [0.25, 0.75, 0.5]])
+    Wg = _gpu_w(V, F, Q=Q)
+    np.testing.assert_allclose(Wg, [1, 1 / 8, 1 / 8, 1 / 8, 0, 0, 1], atol=1e-6)
+
+
+def test_empty_inputs(dev):
+    import torch
+    import paper_2407_11272_amd as wn
+    V = torch.zeros((4, 3), device="cuda")
+    F = torch.zeros((0, 3), dtype=torch.int32, device="cuda")
+    W = wn.wn_voxelize(V, F, grid=wn.Grid.cube(8))
+    torch.cuda.synchronize()
+    assert torch.all(W == 0)
+    W, occ = wn.wn_voxelize(V, F, grid=wn.Grid.cube(4), occupancy="sigmoid", k=10.0)
+    torch.cuda.synchronize()
+    assert torch.allclose(occ, torch.full_like(occ, 1.0 / (1.0 + np.exp(5.0))), atol=1e-6)
+    Q = torch.zeros((0, 3), device="cuda")
+    W = wn.wn_voxelize(V, torch.zeros((2, 3), dtype=torch.int32, device="cuda"), Q=Q)
+    assert W.numel() == 0
+    W = wn.wn_voxelize(V, F, grid=wn.Grid((0, 0, 0), (1, 1, 1), (0, 4, 4)))
+    assert W.numel() == 0
+
+
+def test_bad_face_index_is_reported_not_read(dev, orc):
+    """Out-of-range indices are replaced by 0 on the device and reported."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere()
+    F = c.F.copy()
+    F[5, 1] = 10 ** 6
+    F[9, 0] = -3
+    Vt = torch.as_tensor(c.V, dtype=torch.float32).cuda()
+    Ft = torch.as_tensor(F, dtype=torch.int32).cuda()
+    W = wn.wn_voxelize(Vt, Ft, grid=c.grid)
+    assert wn.wn_get_device_error() == wn._lib.WN_ERR_BAD_INDEX
+    assert wn.wn_get_device_error() == 0  # cleared by the read
+    F2 = F.copy()
+    F2[5, 1] = 0
+    F2[9, 0] = 0
+    W2 = wn.wn_voxelize(Vt, torch.as_tensor(F2, dtype=torch.int32).cuda(), grid=c.grid)
+    assert wn.wn_get_device_error() == 0
+    torch.testing.assert_close(W, W2, rtol=0, atol=0)
+
+
+def test_argument_errors(dev):
+    import ctypes
+    import torch
+    import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd import _lib as L
+    lib = L.load()
+    V = torch.zeros((3, 3), device="cuda")
+    F = torch.tensor([[0, 1, 2]], dtype=torch.int32, device="cuda")
+    W = torch.empty(8, device="cuda")
+    g = wn.Grid.cube(2).to_c()
+    ws = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
+    base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = ctypes.c_void_p
+    ok = lib.wn_voxelize(p(V.data_ptr()), 3, p(F.data_ptr()), 1, ctypes.byref(g), None, 0, p(W.data_ptr()), 0, 0.5,
+                         50.0, None, p(base), 1 << 19, s)
+    assert ok == L.WN_OK
+    # both grid and Q
+    assert lib.wn_voxelize(p(V.data_ptr()), 3, p(F.data_ptr()), 1, ctypes.byref(g), p(V.data_ptr()), 3,
+                           p(W.data_ptr()), 0, 0.5, 50.0, None, p(base), 1 << 19, s) == L.WN_ERR_INVALID_ARG
+    # negative count, null mesh with faces, bad occupancy mode, nQ inconsistent with the grid
+    assert lib.wn_voxelize(p(V.data_ptr()), -1, p(F.data_ptr()), 1, ctypes.byref(g), None, 0, p(W.data_ptr()), 0,
+                           0.5, 50.0, None, p(base), 1 << 19, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_voxelize(None, 3, p(F.data_ptr()), 1, ctypes.byref(g), None, 0, p(W.data_ptr()), 0, 0.5, 50.0,
+                           None, p(base), 1 << 19, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_voxelize(p(V.data_ptr()), 3, p(F.data_ptr()), 1, ctypes.byref(g), None, 0, p(W.data_ptr()), 7, 0.5,
+                           50.0, None, p(base), 1 << 19, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_voxelize(p(V.data_ptr()), 3, p(F.data_ptr()), 1, ctypes.byref(g), None, 5, p(W.data_ptr()), 0, 0.5,
+                           50.0, None, p(base), 1 << 19, s) == L.WN_ERR_INVALID_ARG
+    # workspace: missing, misaligned, too small
+    assert lib.wn_voxelize(p(V.data_ptr()), 3, p(F.data_ptr()), 1, ctypes.byref(g), None, 0, p(W.data_ptr()), 0, 0.5,
+                           50.0, None, None, 0, s) == L.WN_ERR_WORKSPACE
+    assert lib.wn_voxelize(p(V.data_ptr()), 3, p(F.data_ptr()), 1, ctypes.byref(g), None, 0, p(W.data_ptr()), 0, 0.5,
+                           50.0, None, p(base + 4), 1 << 19, s) == L.WN_ERR_WORKSPACE
+    assert lib.wn_voxelize(p(V.data_ptr()), 3, p(F.data_ptr()), 1, ctypes.byref(g), None, 0, p(W.data_ptr()), 0, 0.5,
+                           50.0, None, p(base), 16, s) == L.WN_ERR_WORKSPACE
+    assert lib.wn_occupancy(p(W.data_ptr()), 8, 9, 0.5, 1.0, p(W.data_ptr()), s) == L.WN_ERR_INVALID_ARG
+    with pytest.raises(wn.WnError):
+        L.check("wn_occupancy", lib.wn_occupancy(p(W.data_ptr()), -2, 1, 0.5, 1.0, p(W.data_ptr()), s))
+    torch.cuda.synchronize()
+
+
+def test_occupancy_maps_and_loss(dev, orc):
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable(res=32)
+    c_t = torch.as_tensor(c.target).cuda()
+    Vt, Ft = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    W, occ = wn.wn_voxelize(Vt, Ft, grid=c.grid, occupancy="sigmoid", k=50.0)
+    occ2 = wn.wn_occupancy(W, "sigmoid", 0.5, 50.0)
+    thr = wn.wn_occupancy(W, "threshold", 0.5)
+    loss, g = wn.wn_sigmoid_mse(W.reshape(-1), c_t)
+    torch.cuda.synchronize()
+    Wn = W.cpu().numpy().reshape(-1).astype(np.float64)
+    torch.testing.assert_close(occ, occ2, rtol=0, atol=0)
+    np.testing.assert_allclose(occ.cpu().numpy().reshape(-1), orc.occupancy_sigmoid(Wn, 0.5, 50.0), atol=1e-6)
+    np.testing.assert_array_equal(thr.cpu().numpy().reshape(-1), orc.occupancy_threshold(Wn))
+    Lr, gr = orc.sigmoid_mse(Wn, c.target, 0.5, 50.0)
+    assert float(loss.item()) == pytest.approx(Lr, rel=1e-5)
+    np.testing.assert_allclose(g.cpu().numpy().reshape(-1), gr, rtol=1e-4, atol=1e-12)

@@ -19,6 +19,10 @@ from .meshgen import (  # noqa: F401
     octahedron_mesh,
     ellipsoid_inside,
     grid_flat_index,
+    ellipsoid_target_on_grid,
+    Ellipsoid,
+    random_ellipsoid,
+    signed_volume,
 )
 from .configs import (  # noqa: F401
     config1_icosphere,
