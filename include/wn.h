@@ -20,7 +20,8 @@
  *    pointers read only during the call.
  *  - V: float [nV][3] vertex positions.  F: int32 [nF][3] vertex indices.
  *    Q: float [nQ][3] query points.  All row-major and densely packed.
- *  - Exactly one of `grid` (host) or `Q` (device) is non-NULL.  With a grid the
+ *  - Exactly one of `grid` (host) or `Q` (device) is non-NULL (both may be NULL
+ *    when nQ = 0, an empty point list).  With a grid the
  *    query points are the voxel centres lo + (idx + 1/2) (hi - lo) / n, flat index
  *    (i * n[1] + j) * n[2] + k (x slowest, z fastest), and nQ must be 0 or
  *    n[0] n[1] n[2].

@@ -17,8 +17,9 @@ wn_status hip_status(hipError_t e) { return e == hipSuccess ? WN_OK : WN_ERR_HIP
 
 // Number of query points described by (grid, Q, nQ), or -1 when inconsistent.
 int64_t query_count(const wn_grid *grid, const float *Q, int64_t nQ) {
-    if ((grid == nullptr) == (Q == nullptr)) return -1;
     if (nQ < 0) return -1;
+    if (grid == nullptr && Q == nullptr) return nQ == 0 ? 0 : -1;  // empty point list
+    if (grid != nullptr && Q != nullptr) return -1;
     if (!grid) return nQ <= kMaxCount ? nQ : -1;
     int64_t p = 1;
     for (int d = 0; d < 3; ++d) {
