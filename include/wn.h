@@ -85,9 +85,9 @@ typedef struct {
     int32_t n[3];
 } wn_grid;
 
-/* Bytes of device workspace an operation needs.  For WN_OP_BATCHED pass the
- * number of meshes as nV, the total face count as nF and the total point count
- * as nQ.  Returns 0 for an unknown op. */
+/* Bytes of device workspace an operation needs (WN_OP_VOXELIZE, WN_OP_BACKWARD,
+ * WN_OP_LOSS; a batched launch uses wn_workspace_size_batched).  Returns 0 for an
+ * unknown op or negative sizes. */
 WN_API size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ);
 
 /*
@@ -151,12 +151,33 @@ typedef struct {
  * persistent workgroups; the launch sequence is captured once as a HIP graph per
  * workspace and replayed.  Each mesh's result is bit-identical to the same mesh
  * alone in a batched call (its chunking depends only on its own size).
- * Workspace: wn_workspace_size(WN_OP_BATCHED, n, sum nF, sum points).
+ * Workspace: wn_workspace_size_batched(desc, n).  The table describing the batch is
+ * copied from library-owned pinned host memory on `stream`; a later call on the same
+ * workspace waits (on the host) until that copy has finished.
  * flags: 0, or WN_BATCH_NO_GRAPH to launch without graph capture.
+ * Every mesh needs W non-NULL and a grid with n[d] >= 1 and hi > lo.
  */
 #define WN_BATCH_NO_GRAPH 1
 WN_API wn_status wn_voxelize_batched(const wn_mesh_desc *desc, int32_t n, int32_t flags,
                               void *ws, size_t ws_bytes, void *stream);
+
+/* Exact workspace bytes for wn_voxelize_batched of these meshes (0 if a descriptor
+ * is invalid). */
+WN_API size_t wn_workspace_size_batched(const wn_mesh_desc *desc, int32_t n);
+
+/*
+ * Launch autotuner.  Times each candidate launch configuration (query points per
+ * lane 1/2/4; for WN_OP_BATCHED also persistent workgroups per CU) on the given
+ * work -- desc[0] alone for WN_OP_VOXELIZE, all n meshes for WN_OP_BATCHED -- and
+ * records the fastest for that shape bucket (floor(log2) of faces and points, or of
+ * total pairs and mesh count).  Later calls of that op and bucket use it.  A
+ * configuration never changes results, only speed.  With the environment variable
+ * WN_AUTOTUNE_CACHE naming a file, choices persist there as JSON lines.  Writes the
+ * outputs of desc as a side effect, synchronises `stream`, and writes a JSON report of
+ * the timings to `report` (optional, NUL-terminated, truncated to report_len).
+ */
+WN_API wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws, size_t ws_bytes,
+                             void *stream, char *report, size_t report_len);
 
 /*
  * Reads and clears the device-side error record that the most recent call using

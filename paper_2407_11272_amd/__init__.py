@@ -7,6 +7,10 @@ not been built (there is no CPU fallback).
 """
 from .api import (  # noqa: F401
     Grid,
+    MeshJob,
+    wn_autotune,
+    wn_voxelize_batched,
+    wn_workspace_size_batched,
     Workspace,
     as_mesh,
     voxelize,

@@ -37,6 +37,8 @@ EXPORTED = (
     "wn_sigmoid_mse",
     "wn_backward",
     "wn_voxelize_batched",
+    "wn_workspace_size_batched",
+    "wn_autotune",
     "wn_get_device_error",
     "wn_status_string",
     "wn_version",
@@ -94,6 +96,10 @@ def load():
     lib.wn_backward.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, vp, vp, vp, sz, vp]
     lib.wn_voxelize_batched.restype = i32
     lib.wn_voxelize_batched.argtypes = [ctypes.POINTER(WnMeshDesc), i32, i32, vp, sz, vp]
+    lib.wn_workspace_size_batched.restype = sz
+    lib.wn_workspace_size_batched.argtypes = [ctypes.POINTER(WnMeshDesc), i32]
+    lib.wn_autotune.restype = i32
+    lib.wn_autotune.argtypes = [i32, ctypes.POINTER(WnMeshDesc), i32, vp, sz, vp, ctypes.c_char_p, sz]
     lib.wn_get_device_error.restype = i32
     lib.wn_get_device_error.argtypes = [vp, vp]
     lib.wn_status_string.restype = ctypes.c_char_p

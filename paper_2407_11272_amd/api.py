@@ -217,3 +217,98 @@ def voxelize(V, F, grid=None, Q=None, occupancy: str | None = None, tau: float =
     if Q is not None:
         Q = torch.as_tensor(Q).to(device=V.device, dtype=torch.float32).contiguous()
     return wn_voxelize(V, F, grid=grid, Q=Q, occupancy=occupancy, tau=tau, k=k)
+
+
+# ------------------------------------------------------------ batched launch
+
+@dataclass
+class MeshJob:
+    """One mesh of a batched launch: device mesh, grid, outputs (allocated if None)."""
+
+    V: torch.Tensor
+    F: torch.Tensor
+    grid: Grid
+    occupancy: str | None = None
+    tau: float = 0.5
+    k: float = 50.0
+    W: torch.Tensor | None = None
+    occ: torch.Tensor | None = None
+
+    def prepare(self):
+        _check_mesh(self.V, self.F)
+        self.grid = Grid.of(self.grid)
+        shape = tuple(int(x) for x in self.grid.n)
+        if self.W is None:
+            self.W = torch.empty(shape, dtype=torch.float32, device=self.V.device)
+        mode = _OCC_MODES[self.occupancy]
+        if mode != L.WN_OCC_NONE and self.occ is None:
+            self.occ = torch.empty(shape, dtype=torch.uint8 if mode == L.WN_OCC_THRESHOLD else torch.float32,
+                                   device=self.V.device)
+        return self
+
+    def desc(self) -> L.WnMeshDesc:
+        d = L.WnMeshDesc()
+        d.V = self.V.data_ptr()
+        d.nV = self.V.shape[0]
+        d.F = self.F.data_ptr()
+        d.nF = self.F.shape[0]
+        d.grid = self.grid.to_c()
+        d.W = self.W.data_ptr()
+        mode = _OCC_MODES[self.occupancy]
+        d.occ = self.occ.data_ptr() if mode != L.WN_OCC_NONE else None
+        d.occ_mode = mode
+        d.tau = self.tau
+        d.k = self.k
+        return d
+
+
+def _descs(jobs):
+    arr = (L.WnMeshDesc * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j.prepare().desc()
+    return arr
+
+
+def wn_workspace_size_batched(jobs) -> int:
+    arr = _descs(jobs)
+    return int(L.load().wn_workspace_size_batched(arr, len(jobs)))
+
+
+def wn_voxelize_batched(jobs, graph: bool = True, workspace: tuple | None = None):
+    """Forward pass for every MeshJob in one persistent launch; fills job.W / job.occ.
+
+    ``workspace`` = (pointer, bytes) of a caller-owned 256-byte-aligned device buffer;
+    by default the per-stream workspace is used."""
+    if not jobs:
+        return jobs
+    lib = L.load()
+    arr = _descs(jobs)
+    dev = jobs[0].V.device
+    need = int(lib.wn_workspace_size_batched(arr, len(jobs)))
+    if need == 0:
+        raise ValueError("invalid mesh job in batch")
+    ws, wsb = workspace if workspace is not None else Workspace.get(need, dev)
+    flags = 0 if graph else L.WN_BATCH_NO_GRAPH
+    st = lib.wn_voxelize_batched(arr, len(jobs), flags, ws, wsb, _stream_handle(dev))
+    L.check("wn_voxelize_batched", st)
+    return jobs
+
+
+def wn_autotune(op: str, jobs) -> dict:
+    """Time the launch candidates for ``op`` ('voxelize' uses jobs[0], 'batched' all
+    jobs) and record the fastest; returns the report (synchronises)."""
+    import json
+    lib = L.load()
+    code = {"voxelize": L.WN_OP_VOXELIZE, "batched": L.WN_OP_BATCHED}[op]
+    arr = _descs(jobs)
+    dev = jobs[0].V.device
+    if code == L.WN_OP_BATCHED:
+        need = int(lib.wn_workspace_size_batched(arr, len(jobs)))
+    else:
+        j = jobs[0]
+        need = wn_workspace_size(L.WN_OP_VOXELIZE, j.V.shape[0], j.F.shape[0], j.grid.size)
+    ws, wsb = Workspace.get(need, dev)
+    buf = ctypes.create_string_buffer(4096)
+    st = lib.wn_autotune(code, arr, len(jobs), ws, wsb, _stream_handle(dev), buf, len(buf))
+    L.check("wn_autotune", st)
+    return json.loads(buf.value.decode())

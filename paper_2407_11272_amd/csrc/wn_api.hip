@@ -1,7 +1,11 @@
 // C ABI entry points declared in include/wn.h: argument checks, workspace
 // layout and the launch sequence of each call.  No entry point allocates device
 // memory or synchronises (except wn_get_device_error).
+#include <stdio.h>
 #include <string.h>
+
+#include <string>
+#include <vector>
 
 #include "wn_internal.hpp"
 
@@ -55,8 +59,6 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
             return voxelize_ws(nF, nQ);
         case WN_OP_BACKWARD:
             return bwd_workspace(nV, nF, nQ);
-        case WN_OP_BATCHED:
-            return batched_workspace(nV, nF, nQ);
         case WN_OP_LOSS:
             return kWsHeader + align_up((size_t)loss_blocks(nQ) * sizeof(float));
         default:
@@ -64,9 +66,13 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
     }
 }
 
-wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
-                      const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
-                      void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                        const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
+                        void *ws, size_t ws_bytes, void *stream, int ppl) {
     if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
     const int64_t P = query_count(grid, Q, nQ);
     if (P < 0) return WN_ERR_INVALID_ARG;
@@ -89,10 +95,21 @@ wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64_t nF, 
     const int split = fwd_split_count(nF, P);
     OccParams op{occ, occ_mode, tau, k};
 
+    if (!valid_ppl(ppl)) ppl = lookup_config(WN_OP_VOXELIZE, nF, P).ppl;
     hipError_t e = launch_ws_reset(hdr, s);
     if (e == hipSuccess) e = launch_pack(V, nV, F, nF, soup, hdr, s);
-    if (e == hipSuccess) e = launch_fwd(soup, nF, make_point_src(grid, Q), P, split, W, partials, op, s);
+    if (e == hipSuccess) e = launch_fwd(soup, nF, make_point_src(grid, Q), P, split, W, partials, op, ppl, s);
     return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                      const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
+                      void *ws, size_t ws_bytes, void *stream) {
+    return voxelize_impl(V, nV, F, nF, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes, stream, 0);
 }
 
 wn_status wn_occupancy(const float *W, int64_t n, int32_t mode, float tau, float k, void *occ, void *stream) {
@@ -138,7 +155,80 @@ wn_status wn_voxelize_batched(const wn_mesh_desc *desc, int32_t n, int32_t flags
     if (flags & ~WN_BATCH_NO_GRAPH) return WN_ERR_INVALID_ARG;
     if (n == 0) return WN_OK;
     if (ws == nullptr || !aligned256(ws)) return WN_ERR_WORKSPACE;
-    return run_batched(desc, n, flags, static_cast<char *>(ws), ws_bytes, static_cast<hipStream_t>(stream));
+    return run_batched(desc, n, flags, static_cast<char *>(ws), ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+}
+
+size_t wn_workspace_size_batched(const wn_mesh_desc *desc, int32_t n) {
+    if (n < 0 || (n > 0 && desc == nullptr)) return 0;
+    return batched_workspace(desc, n);
+}
+
+wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws, size_t ws_bytes, void *stream,
+                      char *report, size_t report_len) {
+    if (desc == nullptr || n < 1) return WN_ERR_INVALID_ARG;
+    if (op != WN_OP_VOXELIZE && op != WN_OP_BATCHED) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws)) return WN_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<TuneConfig> cands;
+    for (int ppl : {1, 2, 4}) {
+        cands.push_back(TuneConfig{ppl, 0});
+        if (op == WN_OP_BATCHED) cands.push_back(TuneConfig{ppl, 2});
+    }
+    int64_t a = 0, b = 0;
+    if (op == WN_OP_VOXELIZE) {
+        a = desc[0].nF;
+        b = (int64_t)desc[0].grid.n[0] * desc[0].grid.n[1] * desc[0].grid.n[2];
+    } else {
+        for (int32_t m = 0; m < n; ++m)
+            a += desc[m].nF * ((int64_t)desc[m].grid.n[0] * desc[m].grid.n[1] * desc[m].grid.n[2]);
+        b = n;
+    }
+    auto run = [&](const TuneConfig &c) -> wn_status {
+        if (op == WN_OP_VOXELIZE) {
+            const wn_mesh_desc &d = desc[0];
+            return voxelize_impl(d.V, d.nV, d.F, d.nF, &d.grid, nullptr, 0, d.W, d.occ_mode, d.tau, d.k, d.occ, ws,
+                                 ws_bytes, stream, c.ppl);
+        }
+        return run_batched(desc, n, WN_BATCH_NO_GRAPH, static_cast<char *>(ws), ws_bytes, s, &c);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return WN_ERR_HIP;
+    std::string rep = "{\"op\": " + std::to_string(op) + ", \"candidates\": [";
+    float best_ms = 0.0f;
+    TuneConfig best = cands[0];
+    wn_status st = WN_OK;
+    for (size_t i = 0; i < cands.size() && st == WN_OK; ++i) {
+        st = run(cands[i]);  // warm-up (and code-object load)
+        if (st != WN_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = WN_ERR_HIP; break; }
+        for (int r = 0; r < 2 && st == WN_OK; ++r) st = run(cands[i]);
+        if (st != WN_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = WN_ERR_HIP; break; }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = WN_ERR_HIP; break; }
+        ms *= 0.5f;
+        char buf[128];
+        snprintf(buf, sizeof buf, "%s{\"ppl\": %d, \"wg\": %d, \"ms\": %.4f}", i ? ", " : "", cands[i].ppl,
+                 cands[i].wg_per_cu, ms);
+        rep += buf;
+        if (i == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != WN_OK) return st;
+    store_config(op, a, b, best);
+    char buf[128];
+    snprintf(buf, sizeof buf, "], \"chosen\": {\"ppl\": %d, \"wg\": %d, \"ms\": %.4f}}", best.ppl, best.wg_per_cu,
+             best_ms);
+    rep += buf;
+    if (report && report_len > 0) {
+        strncpy(report, rep.c_str(), report_len - 1);
+        report[report_len - 1] = 0;
+    }
+    return WN_OK;
 }
 
 wn_status wn_get_device_error(void *ws, void *stream) {

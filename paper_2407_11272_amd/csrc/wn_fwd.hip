@@ -18,7 +18,7 @@ namespace wn {
 __global__ void k_ws_reset(WsHeader *hdr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         hdr->bad_index = 0;
-        hdr->cursor = 0;
+        hdr->cursor = 0ull;
     }
 }
 
@@ -77,24 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_wn_fwd(const FaceRec *__restrict__ s
         s[p] = 0.0f;
         c[p] = 0.0f;
     }
-    const float4 *src = reinterpret_cast<const float4 *>(soup);
-    for (int32_t t0 = f0; t0 < f1; t0 += kFaceTile) {
-        const int nt = min(kFaceTile, f1 - t0);
-        __syncthreads();
-        if (tid < 3 * nt) tile[tid] = src[3 * (int64_t)t0 + tid];
-        __syncthreads();
-        float ts[PPL];
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
-#pragma unroll 2
-        for (int i = 0; i < nt; ++i) {
-            const float4 a = tile[3 * i], b = tile[3 * i + 1], cc = tile[3 * i + 2];
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) ts[p] += half_solid_angle(a, b, cc, qx[p], qy[p], qz[p]);
-        }
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) neumaier_add(s[p], c[p], ts[p]);
-    }
+    sum_faces<PPL>(reinterpret_cast<const float4 *>(soup), f0, f1, tile, qx, qy, qz, s, c);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int64_t idx = base + (int64_t)p * kBlock;
@@ -168,8 +151,6 @@ __global__ __launch_bounds__(kBlock) void k_loss_final(const float *__restrict__
 
 // ---------------------------------------------------------------- launchers
 
-constexpr int kPPL = 2;  // query points per lane in the plain forward kernel
-
 int fwd_split_count(int64_t nF, int64_t nQ) {
     // Aim for about 8192 wave64s; never give a split fewer than 2 tiles of faces.
     const int64_t waves = (nQ + 63) / 64;
@@ -179,6 +160,12 @@ int fwd_split_count(int64_t nF, int64_t nQ) {
     if (s > 64) s = 64;
     if (s < 1) s = 1;
     return (int)s;
+}
+
+int32_t fwd_split_chunk(int64_t nF, int split) {
+    const int64_t per = (nF + split - 1) / (split > 0 ? split : 1);
+    const int64_t chunk = (per + kFaceTile - 1) / kFaceTile * kFaceTile;
+    return (int32_t)(chunk > 0 ? chunk : kFaceTile);
 }
 
 PointSrc make_point_src(const wn_grid *grid, const float *Q) {
@@ -208,15 +195,26 @@ hipError_t launch_pack(const float *V, int64_t nV, const int32_t *F, int64_t nF,
     return hipGetLastError();
 }
 
-hipError_t launch_fwd(const FaceRec *soup, int64_t nF, const PointSrc &ps, int64_t nQ, int split, float *W,
-                      float *partials, const OccParams &occ, hipStream_t s) {
-    if (nQ <= 0) return hipSuccess;
-    const int64_t pblocks = (nQ + kBlock * kPPL - 1) / (kBlock * kPPL);
-    const int32_t chunk = (int32_t)(((nF + split - 1) / split + kFaceTile - 1) / kFaceTile * kFaceTile);
+template <int PPL>
+static hipError_t launch_fwd_ppl(const FaceRec *soup, int64_t nF, const PointSrc &ps, int64_t nQ, int split, float *W,
+                                 float *partials, const OccParams &occ, hipStream_t s) {
+    const int64_t pblocks = (nQ + kBlock * PPL - 1) / (kBlock * PPL);
+    const int32_t chunk = fwd_split_chunk(nF, split);
     dim3 g((unsigned)pblocks, (unsigned)split);
-    k_wn_fwd<kPPL><<<g, kBlock, 0, s>>>(soup, (int32_t)nF, chunk > 0 ? chunk : kFaceTile, ps, nQ, W,
-                                         split > 1 ? partials : nullptr, occ);
-    hipError_t e = hipGetLastError();
+    k_wn_fwd<PPL><<<g, kBlock, 0, s>>>(soup, (int32_t)nF, chunk, ps, nQ, W, split > 1 ? partials : nullptr, occ);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd(const FaceRec *soup, int64_t nF, const PointSrc &ps, int64_t nQ, int split, float *W,
+                      float *partials, const OccParams &occ, int ppl, hipStream_t s) {
+    if (nQ <= 0) return hipSuccess;
+    hipError_t e;
+    if (ppl == 1)
+        e = launch_fwd_ppl<1>(soup, nF, ps, nQ, split, W, partials, occ, s);
+    else if (ppl == 4)
+        e = launch_fwd_ppl<4>(soup, nF, ps, nQ, split, W, partials, occ, s);
+    else
+        e = launch_fwd_ppl<2>(soup, nF, ps, nQ, split, W, partials, occ, s);
     if (e != hipSuccess || split <= 1) return e;
     const int64_t rblocks = (nQ + kBlock - 1) / kBlock;
     k_wn_reduce<<<dim3((unsigned)rblocks), kBlock, 0, s>>>(partials, split, nQ, W, occ);

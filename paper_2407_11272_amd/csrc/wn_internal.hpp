@@ -38,12 +38,10 @@ struct FaceRec {
 
 // Header at the start of each workspace.
 struct WsHeader {
-    int32_t bad_index;   // set to non-zero by the pack kernel on an out-of-range face index
-    int32_t cursor;      // work-list cursor of the persistent kernel
-    int32_t n_units;     // work units in the current batched launch
-    int32_t n_meshes;    // meshes in the current batched launch
-    int32_t n_reduce;    // reduction items in the current batched launch
-    int32_t pad[59];
+    int32_t bad_index;            // set to non-zero by a pack kernel on an out-of-range face index
+    int32_t pad0;
+    unsigned long long cursor;    // work-unit cursor of the persistent kernel
+    int32_t pad[60];
 };
 static_assert(sizeof(WsHeader) == kWsHeader, "header size");
 
@@ -133,6 +131,35 @@ struct PointSrc {
     }
 };
 
+// Sum over faces [f0, f1) of the half solid angles at PPL points per lane.  The whole
+// workgroup stages kFaceTile face records at a time through `tile` (LDS, kFaceTile * 3
+// float4) and every lane reads each record (broadcast).  Each tile's per-point sum is
+// folded into the Neumaier pair (s, c), so the summation order -- and the result --
+// depends only on the face order and the tile boundaries, not on PPL or the launch.
+template <int PPL>
+__device__ __forceinline__ void sum_faces(const float4 *__restrict__ src, int32_t f0, int32_t f1, float4 *tile,
+                                          const float (&qx)[PPL], const float (&qy)[PPL], const float (&qz)[PPL],
+                                          float (&s)[PPL], float (&c)[PPL]) {
+    const int tid = threadIdx.x;
+    for (int32_t t0 = f0; t0 < f1; t0 += kFaceTile) {
+        const int nt = min(kFaceTile, f1 - t0);
+        __syncthreads();
+        if (tid < 3 * nt) tile[tid] = src[3 * (int64_t)t0 + tid];
+        __syncthreads();
+        float ts[PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
+#pragma unroll 2
+        for (int i = 0; i < nt; ++i) {
+            const float4 a = tile[3 * i], b = tile[3 * i + 1], cc = tile[3 * i + 2];
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) ts[p] += half_solid_angle(a, b, cc, qx[p], qy[p], qz[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) neumaier_add(s[p], c[p], ts[p]);
+    }
+}
+
 struct OccParams {
     void *occ;
     int32_t mode;
@@ -156,6 +183,7 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // Partition of the faces over workgroups when there are too few point blocks to
 // fill the GPU.  A pure function of (nF, nQ): results never depend on tuning.
 int fwd_split_count(int64_t nF, int64_t nQ);
+int32_t fwd_split_chunk(int64_t nF, int split);
 
 PointSrc make_point_src(const wn_grid *grid, const float *Q);
 
@@ -164,7 +192,7 @@ hipError_t launch_ws_reset(WsHeader *hdr, hipStream_t s);
 hipError_t launch_pack(const float *V, int64_t nV, const int32_t *F, int64_t nF, FaceRec *soup,
                        WsHeader *hdr, hipStream_t s);
 hipError_t launch_fwd(const FaceRec *soup, int64_t nF, const PointSrc &ps, int64_t nQ, int split,
-                      float *W, float *partials, const OccParams &occ, hipStream_t s);
+                      float *W, float *partials, const OccParams &occ, int ppl, hipStream_t s);
 hipError_t launch_occ(const float *W, int64_t n, const OccParams &occ, hipStream_t s);
 hipError_t launch_sigmoid_mse(const float *W, const float *target, int64_t n, float tau, float k,
                               float *loss, float *dLdW, float *scratch, hipStream_t s);
@@ -177,8 +205,20 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
                        hipStream_t s);
 
 // Batched pieces (wn_batched.hip).
-size_t batched_workspace(int64_t n_meshes, int64_t total_faces, int64_t total_points);
+size_t batched_workspace(const wn_mesh_desc *d, int32_t n);
 wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws, size_t ws_bytes,
-                      hipStream_t s);
+                      hipStream_t s, const struct TuneConfig *force);
+
+// Launch tuning (wn_tune.hip).  A configuration changes only how work is mapped to
+// lanes and workgroups, never the per-point summation order, so results do not
+// depend on it.
+struct TuneConfig {
+    int32_t ppl;        // query points per lane: 1, 2 or 4
+    int32_t wg_per_cu;  // persistent workgroups per CU (0 = as many as fit)
+};
+TuneConfig default_config(int32_t op);
+TuneConfig lookup_config(int32_t op, int64_t a, int64_t b);
+void store_config(int32_t op, int64_t a, int64_t b, const TuneConfig &c);
+bool valid_ppl(int32_t ppl);
 
 }  // namespace wn
