@@ -77,7 +77,7 @@ def time_steps(fn, steps, warmup, stream):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
-def bench_forward(steps, warmup):
+def bench_forward(steps, warmup, autotune=True):
     import torch
     import paper_2407_11272_amd as wn
     import wn_inputs as wi
@@ -87,6 +87,8 @@ def bench_forward(steps, warmup):
     W = torch.empty(tuple(grid.n), dtype=torch.float32, device="cuda")
     occ = torch.empty(tuple(grid.n), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    if autotune:
+        wn.wn_autotune("voxelize", [wn.MeshJob(V, F, grid, "threshold", W=W, occ=occ)])
 
     def step():
         wn.wn_voxelize(V, F, grid=grid, W=W, occupancy="threshold", occ=occ)
@@ -135,6 +137,89 @@ def bench_adjoint(steps, warmup):
     }
 
 
+def bench_batched(reps: int, autotune: bool):
+    """64 meshes of uneven size in one persistent launch vs one mesh per launch."""
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    ws = wi.config4_batch()
+    jobs = []
+    for w in ws:
+        V, F = wn.as_mesh(torch.as_tensor(w.V), torch.as_tensor(w.F))
+        jobs.append(wn.MeshJob(V, F, wn.Grid.of(w.grid), "threshold").prepare())
+    pairs = sum(int(j.grid.size) * int(j.F.shape[0]) for j in jobs)
+    report = wn.wn_autotune("batched", jobs) if autotune else None
+    stream = torch.cuda.current_stream()
+    b_s, _ = time_steps(lambda: wn.wn_voxelize_batched(jobs), reps, 1, stream)
+
+    def plain():
+        for j in jobs:
+            wn.wn_voxelize(j.V, j.F, grid=j.grid, W=j.W, occupancy="threshold", occ=j.occ)
+
+    p_s, _ = time_steps(plain, 1, 1, stream)
+    rate = pairs * reps / b_s
+    return {
+        "workload": "64 ellipsoid-union meshes, 500-50k faces log-uniform, grids 32^3/64^3/128^3",
+        "pairs_per_launch": pairs,
+        "batched_ms": b_s / reps * 1e3,
+        "batched_pairs_per_s": rate,
+        "batched_frac_fp32_peak": rate * FLOP_FWD / PEAK_FP32,
+        "plain_one_mesh_per_launch_ms": p_s * 1e3,
+        "plain_pairs_per_s": pairs / p_s,
+        "batched_over_plain": (pairs * reps / b_s) / (pairs / p_s),
+        "autotune": report["chosen"] if report else None,
+    }
+
+
+def bench_served(n_requests: int, load: float, pairs_per_s: float):
+    """Poisson trace through the continuous-batching server and through the plain FIFO
+    one-mesh-per-launch loop; p50/p99 latency and throughput of both."""
+    import numpy as np
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    from paper_2407_11272_amd.serve import (GpuExecutor, Server, ServeRequest, latency_stats,
+                                            run_plain_fifo)
+    base = wi.config5_trace(n_requests, 1.0)
+    mean_pairs = float(np.mean([r.faces * r.res ** 3 * (2 if r.wants_grad else 1) for r in base]))
+    rate = load * pairs_per_s / mean_pairs
+    trace = wi.config5_trace(n_requests, rate)
+    reqs = []
+    for r in trace:
+        w = r.build()
+        reqs.append(ServeRequest(r.rid, w.V.astype(np.float32), w.F.astype(np.int32), w.grid, r.arrival,
+                                 w.occ_mode, w.target))
+    total_pairs = sum(r.pairs for r in reqs)
+
+    def summary(out):
+        st = latency_stats(out)
+        span = max(o.done for o in out) - min(o.arrival for o in out)
+        st["throughput_pairs_per_s"] = total_pairs / span
+        st["makespan_s"] = span
+        return st
+
+    srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
+                 slots=16, quantum_pairs=2e10)
+    served = srv.run_trace(reqs)
+    s_stats = summary(served)
+    s_stats["steps"] = srv.steps
+    s_stats["peak_active"] = srv.peak_active
+    del served
+    torch.cuda.synchronize()
+    p_stats = summary(run_plain_fifo(reqs))
+    return {
+        "workload": f"{n_requests} Poisson requests, 1k-100k faces log-uniform, grids 64^3/128^3/256^3, "
+                    f"30% with dL/dV (sigmoid-MSE)",
+        "rate_req_per_s": rate,
+        "load": load,
+        "mean_pairs_per_request": mean_pairs,
+        "served": s_stats,
+        "plain_fifo": p_stats,
+        "p50_speedup": p_stats["p50_ms"] / s_stats["p50_ms"],
+        "p99_speedup": p_stats["p99_ms"] / s_stats["p99_ms"],
+    }
+
+
 def cpu_baseline(c, budget_s: float = 15.0):
     """FP64 oracle on a deterministic stride subsample of the workload's voxels."""
     import numpy as np
@@ -178,6 +263,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="headline step only")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=48)
+    ap.add_argument("--served-load", type=float, default=0.8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -191,7 +279,7 @@ def main():
     import paper_2407_11272_amd as wn
     wn.wn_version()
     print(f"# bench: forward, {args.steps} steps after {args.warmup} warm-up", file=sys.stderr, flush=True)
-    c, pairs, dev_s, wall_s = bench_forward(args.steps, args.warmup)
+    c, pairs, dev_s, wall_s = bench_forward(args.steps, args.warmup, not args.no_autotune)
     ms = dev_s / args.steps * 1e3
     value = pairs * args.steps / dev_s
     launch_s = dev_s / args.steps
@@ -234,7 +322,14 @@ def main():
     }
     if not args.no_rows:
         print("# bench: adjoint row", file=sys.stderr, flush=True)
-        out["rows"] = {"adjoint": bench_adjoint(max(2, args.steps // 2), 1)}
+        rows = {"adjoint": bench_adjoint(max(2, args.steps // 2), 1)}
+        print("# bench: batched row", file=sys.stderr, flush=True)
+        rows["batched"] = bench_batched(3, not args.no_autotune)
+        if args.served_requests > 0:
+            print("# bench: served row", file=sys.stderr, flush=True)
+            rows["served"] = bench_served(args.served_requests, args.served_load,
+                                          rows["batched"]["batched_pairs_per_s"])
+        out["rows"] = rows
     if not args.no_cpu_baseline:
         print("# bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)

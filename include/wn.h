@@ -131,7 +131,11 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
                       const float *dLdW, float *dLdV, float *dLdT,
                       void *ws, size_t ws_bytes, void *stream);
 
-/* One mesh of a batched forward launch (host struct; pointers are device memory). */
+/* One mesh of a batched forward launch (host struct; pointers are device memory).
+ * The launch evaluates the voxel centres with flat indices
+ * [point_begin, point_begin + point_count) of the grid (point_count = 0: to the end of
+ * the grid) and writes W and occ at those same flat indices of the full-grid arrays, so
+ * a grid can be processed in slices.  A voxel's value does not depend on the slice. */
 typedef struct {
     const float *V;
     int64_t nV;
@@ -143,6 +147,8 @@ typedef struct {
     int32_t occ_mode;  /* WN_OCC_*                                           */
     float tau;
     float k;
+    int64_t point_begin;
+    int64_t point_count;
 } wn_mesh_desc;
 
 /*

@@ -61,6 +61,8 @@ class WnMeshDesc(ctypes.Structure):
         ("occ_mode", ctypes.c_int32),
         ("tau", ctypes.c_float),
         ("k", ctypes.c_float),
+        ("point_begin", ctypes.c_int64),
+        ("point_count", ctypes.c_int64),
     ]
 
 

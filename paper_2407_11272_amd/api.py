@@ -233,6 +233,8 @@ class MeshJob:
     k: float = 50.0
     W: torch.Tensor | None = None
     occ: torch.Tensor | None = None
+    point_begin: int = 0
+    point_count: int = 0   # 0: to the end of the grid
 
     def prepare(self):
         _check_mesh(self.V, self.F)
@@ -259,6 +261,8 @@ class MeshJob:
         d.occ_mode = mode
         d.tau = self.tau
         d.k = self.k
+        d.point_begin = int(self.point_begin)
+        d.point_count = int(self.point_count)
         return d
 
 

@@ -180,7 +180,9 @@ wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws,
         b = (int64_t)desc[0].grid.n[0] * desc[0].grid.n[1] * desc[0].grid.n[2];
     } else {
         for (int32_t m = 0; m < n; ++m)
-            a += desc[m].nF * ((int64_t)desc[m].grid.n[0] * desc[m].grid.n[1] * desc[m].grid.n[2]);
+            a += desc[m].nF * (desc[m].point_count > 0
+                                   ? desc[m].point_count
+                                   : (int64_t)desc[m].grid.n[0] * desc[m].grid.n[1] * desc[m].grid.n[2]);
         b = n;
     }
     auto run = [&](const TuneConfig &c) -> wn_status {

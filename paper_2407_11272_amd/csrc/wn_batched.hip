@@ -35,7 +35,8 @@ struct BMesh {
     float *W;
     void *occ;
     int64_t nV;
-    int64_t P;          // points (voxel centres)
+    int64_t p0;         // first flat voxel index of this slice
+    int64_t P;          // voxels in this slice
     int64_t soup_off;   // first face record of this mesh in the batch soup
     int64_t part_off;   // first partial-sum float of this mesh (chunks > 1)
     PointSrc ps;
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_persistent(char *ws) {
         for (int p = 0; p < PPL; ++p) {
             int64_t idx = base + (int64_t)p * kBlock;
             idx = idx < mh.P ? idx : mh.P - 1;
-            mh.ps.get(idx, qx[p], qy[p], qz[p]);
+            mh.ps.get(mh.p0 + idx, qx[p], qy[p], qz[p]);
             s[p] = 0.0f;
             c[p] = 0.0f;
         }
@@ -183,8 +184,8 @@ __global__ __launch_bounds__(kBlock) void k_batched_persistent(char *ws) {
                 part[mh.part_off + (int64_t)gr.chunk * mh.P + idx] = tot;
             } else {
                 const float w = tot * kInv2Pi;
-                mh.W[idx] = w;
-                write_occ(OccParams{mh.occ, mh.occ_mode, mh.tau, mh.k}, idx, w);
+                mh.W[mh.p0 + idx] = w;
+                write_occ(OccParams{mh.occ, mh.occ_mode, mh.tau, mh.k}, mh.p0 + idx, w);
             }
         }
     }
@@ -206,8 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_batched_reduce(char *ws) {
         float s = 0.0f, c = 0.0f;
         for (int32_t k = 0; k < mh.chunks; ++k) neumaier_add(s, c, part[mh.part_off + (int64_t)k * mh.P + idx]);
         const float w = (s + c) * kInv2Pi;
-        mh.W[idx] = w;
-        write_occ(OccParams{mh.occ, mh.occ_mode, mh.tau, mh.k}, idx, w);
+        mh.W[mh.p0 + idx] = w;
+        write_occ(OccParams{mh.occ, mh.occ_mode, mh.tau, mh.k}, mh.p0 + idx, w);
     }
 }
 
@@ -234,6 +235,9 @@ bool desc_ok(const wn_mesh_desc &d) {
         if (p > 2147483647LL) return false;
     }
     if (d.W == nullptr) return false;
+    if (d.point_begin < 0 || d.point_count < 0 || d.point_begin > p) return false;
+    if (d.point_count > p - d.point_begin) return false;
+    if (d.point_count == 0 && d.point_begin == p) return false;  // empty slice
     if (d.occ_mode != WN_OCC_NONE && d.occ_mode != WN_OCC_THRESHOLD && d.occ_mode != WN_OCC_SIGMOID) return false;
     if (d.occ_mode != WN_OCC_NONE && d.occ == nullptr) return false;
     return true;
@@ -276,7 +280,9 @@ bool make_plan(const wn_mesh_desc *d, int32_t n, int32_t ppl, Plan &plan) {
         b.W = d[m].W;
         b.occ = d[m].occ_mode == WN_OCC_NONE ? nullptr : d[m].occ;
         b.nV = d[m].nV;
-        b.P = (int64_t)d[m].grid.n[0] * d[m].grid.n[1] * d[m].grid.n[2];
+        const int64_t full = (int64_t)d[m].grid.n[0] * d[m].grid.n[1] * d[m].grid.n[2];
+        b.p0 = d[m].point_begin;
+        b.P = d[m].point_count > 0 ? d[m].point_count : full - d[m].point_begin;
         b.soup_off = fpre[(size_t)m];
         b.ps = make_point_src(&d[m].grid, nullptr);
         b.nF = (int32_t)d[m].nF;
@@ -392,7 +398,8 @@ wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws,
                       const TuneConfig *force) {
     int64_t tot_pairs = 0;
     for (int32_t m = 0; m < n; ++m) {
-        tot_pairs += d[m].nF * ((int64_t)d[m].grid.n[0] * d[m].grid.n[1] * d[m].grid.n[2]);
+        tot_pairs += d[m].nF * (d[m].point_count > 0 ? d[m].point_count
+                                                        : (int64_t)d[m].grid.n[0] * d[m].grid.n[1] * d[m].grid.n[2]);
     }
     const TuneConfig cfg = force ? *force : lookup_config(WN_OP_BATCHED, tot_pairs, n);
     const int ppl = valid_ppl(cfg.ppl) ? cfg.ppl : 2;

@@ -1,0 +1,103 @@
+"""GPU tests of the served path: continuous batching of a seeded request trace.
+
+Each request's W (and dL/dV for gradient requests) must be bit-identical to the same
+request served alone, and within 2e-6 of the plain one-mesh-per-launch path (whose
+face partition differs); one request is also held to the FP64 oracle (1e-4).
+"""
+import numpy as np
+import pytest
+
+import wn_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_11272_amd as wn
+    wn.wn_version()
+    return torch.device("cuda", 0)
+
+
+def _trace(n=14, rate=40.0):
+    from paper_2407_11272_amd.serve import ServeRequest
+    reqs = wi.config5_trace(n, rate, face_lo=1000, face_hi=20000, resolutions=(32, 48, 64))
+    out = []
+    for r in reqs:
+        w = r.build()
+        out.append(ServeRequest(r.rid, w.V.astype(np.float32), w.F.astype(np.int32), w.grid, r.arrival,
+                                w.occ_mode, w.target))
+    return out
+
+
+def _serve(reqs, **kw):
+    import torch
+    from paper_2407_11272_amd.serve import GpuExecutor, Server
+    srv = Server(GpuExecutor(), **kw)
+    out = srv.run_trace(reqs)
+    torch.cuda.synchronize()
+    return srv, out
+
+
+def test_mix_equals_alone_and_plain(dev, orc):
+    import torch
+    import paper_2407_11272_amd as wn
+    reqs = _trace()
+    assert any(r.wants_grad for r in reqs) and not all(r.wants_grad for r in reqs)
+    srv, mix = _serve(reqs, slots=6, quantum_pairs=2e8)
+    print(f"steps={srv.steps} peak_active={srv.peak_active} mixed steps="
+          f"{sum(1 for n, _ in srv.step_log if n > 1)}", flush=True)
+    assert srv.peak_active > 1 and any(n > 1 for n, _ in srv.step_log)
+    for r, m in zip(reqs, mix):
+        assert np.isfinite(m.done) and not m.rejected
+        _, alone = _serve([r], slots=1, quantum_pairs=5e8)
+        a = alone[0]
+        torch.testing.assert_close(m.W, a.W, rtol=0, atol=0)
+        torch.testing.assert_close(m.occ, a.occ, rtol=0, atol=0)
+        if r.wants_grad:
+            torch.testing.assert_close(m.dLdV, a.dLdV, rtol=0, atol=0)
+            torch.testing.assert_close(m.loss, a.loss, rtol=0, atol=0)
+        V, F = wn.as_mesh(torch.as_tensor(r.V), torch.as_tensor(r.F))
+        Wp = wn.wn_voxelize(V, F, grid=wn.Grid.of(r.grid))
+        assert float((Wp - m.W).abs().max()) <= 2e-6
+    # one request against the oracle
+    r, m = reqs[0], mix[0]
+    Q = orc.grid_points(r.grid)
+    idx = np.random.default_rng(0).choice(len(Q), 400, replace=False)
+    V64 = r.V.astype(np.float64)
+    Wr = orc.winding(V64, r.F, Q[idx])
+    guard = orc.guard_mask(V64, r.F, Q[idx])
+    Wg = m.W.cpu().numpy().reshape(-1)[idx]
+    assert np.abs(Wg - Wr)[~guard].max() <= 1e-4
+
+
+def test_plain_fifo_baseline_matches(dev):
+    import torch
+    from paper_2407_11272_amd.serve import latency_stats, run_plain_fifo
+    reqs = _trace(8, 30.0)
+    plain = run_plain_fifo(reqs, keep_results=True)
+    _, served = _serve(reqs, slots=4, quantum_pairs=2e8)
+    for p, s in zip(plain, served):
+        assert np.isfinite(p.done) and p.done >= p.arrival
+        assert float((p.W - s.W).abs().max()) <= 2e-6
+        if p.dLdV is not None:
+            scale = float(p.dLdV.abs().max()) + 1e-30
+            assert float((p.dLdV - s.dLdV).abs().max()) <= 1e-4 * scale
+    print("plain", latency_stats(plain), "served", latency_stats(served), flush=True)
+    torch.cuda.synchronize()
+
+
+def test_budget_rejection_on_device(dev):
+    from paper_2407_11272_amd.serve import footprint_bytes
+    reqs = _trace(4, 100.0)
+    budget = max(footprint_bytes(r, 10 ** 9) for r in reqs[1:]) + 1
+    big = reqs[0]
+    big.grid = wi.Grid.cube(200)
+    big.target = None
+    srv, out = _serve(reqs, hbm_budget=budget, slots=4, quantum_pairs=2e8)
+    assert out[0].rejected
+    assert all(np.isfinite(o.done) for o in out[1:])
+    assert srv.peak_in_use <= budget
