@@ -78,24 +78,42 @@ def time_steps(fn, steps, warmup, stream):
 
 
 def bench_forward(steps, warmup, autotune=True):
+    """Headline: the forward step with the mesh's triangle-strip record stream (built on
+    the host from F before timing, like the mesh itself); also the same step with the
+    default three records per face."""
     import torch
     import paper_2407_11272_amd as wn
     import wn_inputs as wi
     c = wi.config2_ellipsoid_union()
     V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    t0 = time.perf_counter()
+    Rh = wn.wn_build_strips(c.F, len(c.V))
+    strip_ms = (time.perf_counter() - t0) * 1e3
+    R = torch.as_tensor(Rh).cuda()
     grid = wn.Grid.of(c.grid)
     W = torch.empty(tuple(grid.n), dtype=torch.float32, device="cuda")
     occ = torch.empty(tuple(grid.n), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    tune = None
     if autotune:
-        wn.wn_autotune("voxelize", [wn.MeshJob(V, F, grid, "threshold", W=W, occ=occ)])
+        tune = wn.wn_autotune("voxelize", [wn.MeshJob(V, F, grid, "threshold", W=W, occ=occ, strips=R)])
 
     def step():
+        wn.wn_voxelize_strips(V, F, R, grid=grid, W=W, occupancy="threshold", occ=occ)
+
+    def step_plain():
         wn.wn_voxelize(V, F, grid=grid, W=W, occupancy="threshold", occ=occ)
 
     dev_s, wall_s = time_steps(step, steps, warmup, stream)
+    plain_s, _ = time_steps(step_plain, max(2, steps // 2), 1, stream)
     pairs = grid.size * len(c.F)
-    return c, pairs, dev_s, wall_s
+    extra = {
+        "strip_records_per_face": len(Rh) / len(c.F),
+        "strip_build_ms_host": strip_ms,
+        "three_records_per_face_pairs_per_s": pairs * max(2, steps // 2) / plain_s,
+        "autotune": tune["chosen"] if tune else None,
+    }
+    return c, pairs, dev_s, wall_s, extra
 
 
 def bench_adjoint(steps, warmup):
@@ -146,7 +164,8 @@ def bench_batched(reps: int, autotune: bool):
     jobs = []
     for w in ws:
         V, F = wn.as_mesh(torch.as_tensor(w.V), torch.as_tensor(w.F))
-        jobs.append(wn.MeshJob(V, F, wn.Grid.of(w.grid), "threshold").prepare())
+        R = torch.as_tensor(wn.wn_build_strips(w.F, len(w.V))).cuda()
+        jobs.append(wn.MeshJob(V, F, wn.Grid.of(w.grid), "threshold", strips=R).prepare())
     pairs = sum(int(j.grid.size) * int(j.F.shape[0]) for j in jobs)
     report = wn.wn_autotune("batched", jobs) if autotune else None
     stream = torch.cuda.current_stream()
@@ -154,12 +173,12 @@ def bench_batched(reps: int, autotune: bool):
 
     def plain():
         for j in jobs:
-            wn.wn_voxelize(j.V, j.F, grid=j.grid, W=j.W, occupancy="threshold", occ=j.occ)
+            wn.wn_voxelize_strips(j.V, j.F, j.strips, grid=j.grid, W=j.W, occupancy="threshold", occ=j.occ)
 
     p_s, _ = time_steps(plain, 1, 1, stream)
     rate = pairs * reps / b_s
     return {
-        "workload": "64 ellipsoid-union meshes, 500-50k faces log-uniform, grids 32^3/64^3/128^3",
+        "workload": "64 ellipsoid-union meshes, 500-50k faces log-uniform, grids 32^3/64^3/128^3, strip order",
         "pairs_per_launch": pairs,
         "batched_ms": b_s / reps * 1e3,
         "batched_pairs_per_s": rate,
@@ -279,7 +298,7 @@ def main():
     import paper_2407_11272_amd as wn
     wn.wn_version()
     print(f"# bench: forward, {args.steps} steps after {args.warmup} warm-up", file=sys.stderr, flush=True)
-    c, pairs, dev_s, wall_s = bench_forward(args.steps, args.warmup, not args.no_autotune)
+    c, pairs, dev_s, wall_s, fwd_extra = bench_forward(args.steps, args.warmup, not args.no_autotune)
     ms = dev_s / args.steps * 1e3
     value = pairs * args.steps / dev_s
     launch_s = dev_s / args.steps
@@ -307,6 +326,8 @@ def main():
             "points": int(c.grid.size),
             "pairs_per_step": int(pairs),
             "occupancy": "threshold 0.5",
+            "face_order": "triangle strips (host-built from F, resident in HBM)",
+            **fwd_extra,
         },
         "roofline": {
             "bound": "alu",

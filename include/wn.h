@@ -102,6 +102,34 @@ WN_API wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64
                       void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Triangle-strip order of a mesh, built on the host from HOST face indices F
+ * (int32 [nF][3], every index in [0, nV)).  The result is a stream of records, int32
+ * pairs (vertex id, face id or -1): a record with a face id completes that face
+ * together with the vertices of the two records before it; consecutive faces of a
+ * strip share an edge, so the forward kernels evaluate one new vertex per face
+ * instead of three.  It depends only on F (a mesh whose vertices move keeps it).
+ * Every face appears exactly once; n_records <= 3 nF.  With records == NULL only
+ * *n_records is set; otherwise capacity (in records) must be >= *n_records, else
+ * WN_ERR_WORKSPACE.  Invalid indices return WN_ERR_INVALID_ARG.
+ */
+WN_API wn_status wn_build_strips(const int32_t *F, int64_t nF, int64_t nV, int32_t *records, int64_t capacity,
+                                 int64_t *n_records);
+
+/*
+ * wn_voxelize with a strip stream from wn_build_strips (device int32 [n_records][2])
+ * in place of the default three records per face.  Same outputs and conventions; W
+ * agrees with wn_voxelize to rounding (the face order differs) and is deterministic
+ * for a given stream.  Face ids in the stream must be < nF and vertex ids < nV (out of
+ * range entries are replaced and recorded, as for F).  The workspace is
+ * wn_workspace_size(WN_OP_VOXELIZE, nV, nF, nQ) for any stream of at most 3 nF records.
+ */
+WN_API wn_status wn_voxelize_strips(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                                    const int32_t *strips, int64_t n_records,
+                                    const wn_grid *grid, const float *Q, int64_t nQ,
+                                    float *W, int32_t occ_mode, float tau, float k, void *occ,
+                                    void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Occupancy map alone (Eq. 3): occ[i] = (W[i] > tau) as uint8 for
  * WN_OCC_THRESHOLD, or sigmoid(k (W[i] - tau)) as float for WN_OCC_SIGMOID.
  */
@@ -149,6 +177,8 @@ typedef struct {
     float k;
     int64_t point_begin;
     int64_t point_count;
+    const int32_t *strips;    /* device strip stream from wn_build_strips, or NULL */
+    int64_t n_strip_records;  /* records in strips (0 when strips is NULL)         */
 } wn_mesh_desc;
 
 /*

@@ -15,6 +15,8 @@ from .api import (  # noqa: F401
     as_mesh,
     voxelize,
     wn_backward,
+    wn_build_strips,
+    wn_voxelize_strips,
     wn_get_device_error,
     wn_occupancy,
     wn_sigmoid_mse,

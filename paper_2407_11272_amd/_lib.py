@@ -33,6 +33,8 @@ WN_BATCH_NO_GRAPH = 1
 EXPORTED = (
     "wn_workspace_size",
     "wn_voxelize",
+    "wn_build_strips",
+    "wn_voxelize_strips",
     "wn_occupancy",
     "wn_sigmoid_mse",
     "wn_backward",
@@ -63,6 +65,8 @@ class WnMeshDesc(ctypes.Structure):
         ("k", ctypes.c_float),
         ("point_begin", ctypes.c_int64),
         ("point_count", ctypes.c_int64),
+        ("strips", ctypes.c_void_p),
+        ("n_strip_records", ctypes.c_int64),
     ]
 
 
@@ -90,6 +94,10 @@ def load():
     lib.wn_workspace_size.argtypes = [i32, i64, i64, i64]
     lib.wn_voxelize.restype = i32
     lib.wn_voxelize.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i32, f32, f32, vp, vp, sz, vp]
+    lib.wn_build_strips.restype = i32
+    lib.wn_build_strips.argtypes = [vp, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_int64)]
+    lib.wn_voxelize_strips.restype = i32
+    lib.wn_voxelize_strips.argtypes = [vp, i64, vp, i64, vp, i64, gp, vp, i64, vp, i32, f32, f32, vp, vp, sz, vp]
     lib.wn_occupancy.restype = i32
     lib.wn_occupancy.argtypes = [vp, i64, i32, f32, f32, vp, vp]
     lib.wn_sigmoid_mse.restype = i32

@@ -134,6 +134,55 @@ def wn_voxelize(V, F, grid: Grid | None = None, Q: torch.Tensor | None = None, W
     return W if mode == L.WN_OCC_NONE else (W, occ)
 
 
+def wn_build_strips(F, nV: int | None = None):
+    """Triangle-strip record stream of host faces F ([nF, 3]) as an int32 numpy array
+    [n_records, 2] of (vertex id, face id or -1).  Depends only on F."""
+    import numpy as np
+    lib = L.load()
+    Fh = np.ascontiguousarray(torch.as_tensor(F).cpu().numpy(), dtype=np.int32).reshape(-1, 3)
+    nV = int(Fh.max()) + 1 if nV is None and len(Fh) else int(nV or 0)
+    n = ctypes.c_int64(0)
+    L.check("wn_build_strips", lib.wn_build_strips(Fh.ctypes.data, len(Fh), nV, None, 0, ctypes.byref(n)))
+    out = np.empty((n.value, 2), dtype=np.int32)
+    L.check("wn_build_strips", lib.wn_build_strips(Fh.ctypes.data, len(Fh), nV, out.ctypes.data, n.value,
+                                                   ctypes.byref(n)))
+    return out
+
+
+def wn_voxelize_strips(V, F, strips: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None,
+                       W: torch.Tensor | None = None, occupancy: str | None = None, tau: float = 0.5,
+                       k: float = 50.0, occ: torch.Tensor | None = None):
+    """wn_voxelize with a device strip stream from :func:`wn_build_strips`."""
+    lib = L.load()
+    _check_mesh(V, F)
+    if strips.dtype != torch.int32 or strips.dim() != 2 or strips.shape[1] != 2 or not strips.is_cuda \
+            or not strips.is_contiguous():
+        raise ValueError("strips must be a contiguous int32 [n, 2] device tensor")
+    if (grid is None) == (Q is None):
+        raise ValueError("pass exactly one of grid or Q")
+    dev = V.device
+    if grid is not None:
+        grid = Grid.of(grid)
+        P, nQ, gptr, qptr = grid.size, 0, ctypes.byref(grid.to_c()), ctypes.c_void_p(0)
+        shape = tuple(int(x) for x in grid.n)
+    else:
+        P = nQ = Q.shape[0]
+        gptr, qptr = None, _ptr(Q)
+        shape = (P,)
+    mode = _OCC_MODES[occupancy]
+    if W is None:
+        W = torch.empty(shape, dtype=torch.float32, device=dev)
+    if mode != L.WN_OCC_NONE and occ is None:
+        occ = torch.empty(shape, dtype=torch.uint8 if mode == L.WN_OCC_THRESHOLD else torch.float32, device=dev)
+    need = wn_workspace_size(L.WN_OP_VOXELIZE, V.shape[0], max(F.shape[0], (strips.shape[0] + 2) // 3), P)
+    ws, wsb = Workspace.get(need, dev)
+    st = lib.wn_voxelize_strips(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(strips), strips.shape[0], gptr,
+                                qptr, nQ, _ptr(W), mode, tau, k, _ptr(occ if mode != L.WN_OCC_NONE else None), ws,
+                                wsb, _stream_handle(dev))
+    L.check("wn_voxelize_strips", st)
+    return W if mode == L.WN_OCC_NONE else (W, occ)
+
+
 def wn_occupancy(W: torch.Tensor, mode: str = "threshold", tau: float = 0.5, k: float = 50.0,
                  occ: torch.Tensor | None = None) -> torch.Tensor:
     m = _OCC_MODES[mode]
@@ -235,6 +284,7 @@ class MeshJob:
     occ: torch.Tensor | None = None
     point_begin: int = 0
     point_count: int = 0   # 0: to the end of the grid
+    strips: torch.Tensor | None = None   # device strip stream (wn_build_strips) or None
 
     def prepare(self):
         _check_mesh(self.V, self.F)
@@ -263,6 +313,9 @@ class MeshJob:
         d.k = self.k
         d.point_begin = int(self.point_begin)
         d.point_count = int(self.point_count)
+        if self.strips is not None:
+            d.strips = self.strips.data_ptr()
+            d.n_strip_records = int(self.strips.shape[0])
         return d
 
 

@@ -41,9 +41,9 @@ bool mesh_ok(const float *V, int64_t nV, const int32_t *F, int64_t nF) {
     return true;
 }
 
-size_t voxelize_ws(int64_t nF, int64_t nQ) {
-    const int split = fwd_split_count(nF, nQ);
-    size_t b = kWsHeader + align_up((size_t)nF * sizeof(FaceRec));
+size_t voxelize_ws(int64_t nR, int64_t nQ) {
+    const int split = fwd_split_count(nR, nQ);
+    size_t b = kWsHeader + align_up((size_t)nR * sizeof(VRec));
     if (split > 1) b += align_up((size_t)split * (size_t)nQ * sizeof(float));
     return b;
 }
@@ -56,7 +56,7 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
     if (nV < 0 || nF < 0 || nQ < 0) return 0;
     switch (op) {
         case WN_OP_VOXELIZE:
-            return voxelize_ws(nF, nQ);
+            return voxelize_ws(3 * nF, nQ);
         case WN_OP_BACKWARD:
             return bwd_workspace(nV, nF, nQ);
         case WN_OP_LOSS:
@@ -70,10 +70,16 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
 
 namespace {
 
-wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
-                        const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
-                        void *ws, size_t ws_bytes, void *stream, int ppl) {
+wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *R, int64_t nR,
+                        const wn_grid *grid, const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau,
+                        float k, void *occ, void *ws, size_t ws_bytes, void *stream, int ppl) {
     if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
+    if (R == nullptr) {
+        if (nR != 0) return WN_ERR_INVALID_ARG;
+        nR = 3 * nF;
+    } else if (nR < 0 || nR > kMaxCount || nF == 0) {
+        return WN_ERR_INVALID_ARG;
+    }
     const int64_t P = query_count(grid, Q, nQ);
     if (P < 0) return WN_ERR_INVALID_ARG;
     if (occ_mode != WN_OCC_NONE && occ_mode != WN_OCC_THRESHOLD && occ_mode != WN_OCC_SIGMOID)
@@ -83,22 +89,22 @@ wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF
     if (grid)
         for (int d = 0; d < 3; ++d)
             if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
-    const size_t need = voxelize_ws(nF, P);
+    const size_t need = voxelize_ws(nR, P);
     if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
     if (P == 0) return WN_OK;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(base);
-    FaceRec *soup = reinterpret_cast<FaceRec *>(base + kWsHeader);
-    float *partials = reinterpret_cast<float *>(base + kWsHeader + align_up((size_t)nF * sizeof(FaceRec)));
-    const int split = fwd_split_count(nF, P);
+    VRec *recs = reinterpret_cast<VRec *>(base + kWsHeader);
+    float *partials = reinterpret_cast<float *>(base + kWsHeader + align_up((size_t)nR * sizeof(VRec)));
+    const int split = fwd_split_count(nR, P);
     OccParams op{occ, occ_mode, tau, k};
 
     if (!valid_ppl(ppl)) ppl = lookup_config(WN_OP_VOXELIZE, nF, P).ppl;
     hipError_t e = launch_ws_reset(hdr, s);
-    if (e == hipSuccess) e = launch_pack(V, nV, F, nF, soup, hdr, s);
-    if (e == hipSuccess) e = launch_fwd(soup, nF, make_point_src(grid, Q), P, split, W, partials, op, ppl, s);
+    if (e == hipSuccess) e = launch_pack_records(V, nV, F, nF, R, nR, recs, hdr, s);
+    if (e == hipSuccess) e = launch_fwd(recs, nR, make_point_src(grid, Q), P, split, W, partials, op, ppl, s);
     return hip_status(e);
 }
 
@@ -109,7 +115,31 @@ extern "C" {
 wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
                       const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
                       void *ws, size_t ws_bytes, void *stream) {
-    return voxelize_impl(V, nV, F, nF, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes, stream, 0);
+    return voxelize_impl(V, nV, F, nF, nullptr, 0, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes, stream, 0);
+}
+
+wn_status wn_voxelize_strips(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *strips,
+                             int64_t n_records, const wn_grid *grid, const float *Q, int64_t nQ, float *W,
+                             int32_t occ_mode, float tau, float k, void *occ, void *ws, size_t ws_bytes,
+                             void *stream) {
+    if (strips == nullptr) return WN_ERR_INVALID_ARG;
+    return voxelize_impl(V, nV, F, nF, strips, n_records, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes,
+                         stream, 0);
+}
+
+wn_status wn_build_strips(const int32_t *F, int64_t nF, int64_t nV, int32_t *records, int64_t capacity,
+                          int64_t *n_records) {
+    if (n_records == nullptr || nF < 0 || nV < 0 || nF > kMaxCount || nV > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (nF > 0 && F == nullptr) return WN_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < 3 * nF; ++i)
+        if (F[i] < 0 || (int64_t)F[i] >= nV) return WN_ERR_INVALID_ARG;
+    std::vector<int32_t> out;
+    const int64_t n = build_strips(F, nF, out);
+    *n_records = n;
+    if (records == nullptr) return WN_OK;
+    if (capacity < n) return WN_ERR_WORKSPACE;
+    if (n > 0) memcpy(records, out.data(), sizeof(int32_t) * 2 * (size_t)n);
+    return WN_OK;
 }
 
 wn_status wn_occupancy(const float *W, int64_t n, int32_t mode, float tau, float k, void *occ, void *stream) {
@@ -188,8 +218,8 @@ wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws,
     auto run = [&](const TuneConfig &c) -> wn_status {
         if (op == WN_OP_VOXELIZE) {
             const wn_mesh_desc &d = desc[0];
-            return voxelize_impl(d.V, d.nV, d.F, d.nF, &d.grid, nullptr, 0, d.W, d.occ_mode, d.tau, d.k, d.occ, ws,
-                                 ws_bytes, stream, c.ppl);
+            return voxelize_impl(d.V, d.nV, d.F, d.nF, d.strips, d.strips ? d.n_strip_records : 0, &d.grid, nullptr,
+                                 0, d.W, d.occ_mode, d.tau, d.k, d.occ, ws, ws_bytes, stream, c.ppl);
         }
         return run_batched(desc, n, WN_BATCH_NO_GRAPH, static_cast<char *>(ws), ws_bytes, s, &c);
     };

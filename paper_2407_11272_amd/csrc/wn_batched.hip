@@ -3,12 +3,12 @@
 //
 // The cost of a mesh is points x faces (the paper observes time linear in the face
 // count and cubic in the resolution), so work is cut into units of one point block
-// (kBlock * PPL voxel centres) against one face chunk (kChunkFaces faces).  Units of
-// the same (mesh, chunk) form a group; groups are ordered by chunk size, largest
-// first, and persistent workgroups take units from a device cursor until none are
+// (kBlock * PPL voxel centres) against one chunk of the mesh's vertex-record stream
+// (kChunkRecords records; see wn_internal.hpp).  Units of the same (mesh, chunk) form a
+// group; groups are ordered by chunk size, largest first, and persistent workgroups take units from a device cursor until none are
 // left.  A mesh with several chunks writes per-chunk partial sums to fixed slots and
-// a reduction adds them in chunk order, so each mesh's result depends only on its
-// own size -- never on the rest of the batch or on the launch configuration.
+// a reduction adds them in chunk order, so each mesh's result depends only on its own
+// record stream -- never on the rest of the batch or on the launch configuration.
 //
 // Everything the kernels need (mesh table, groups, offsets) lives in the workspace,
 // copied there from a pinned staging buffer before each launch; the kernels take only
@@ -26,18 +26,20 @@
 
 namespace wn {
 
-constexpr int32_t kChunkFaces = 4096;  // faces per work unit (a multiple of kFaceTile)
-static_assert(kChunkFaces % kFaceTile == 0, "chunk must hold whole tiles");
+constexpr int64_t kChunkRecords = 4095;  // records per work unit (a multiple of kRecTile)
+static_assert(kChunkRecords % kRecTile == 0, "chunk must hold whole tiles");
 
 struct BMesh {
     const float *V;
     const int32_t *F;
+    const int32_t *R;   // strip stream or nullptr (three records per face)
     float *W;
     void *occ;
     int64_t nV;
     int64_t p0;         // first flat voxel index of this slice
     int64_t P;          // voxels in this slice
-    int64_t soup_off;   // first face record of this mesh in the batch soup
+    int64_t nR;         // records of this mesh
+    int64_t rec_off;    // first record of this mesh in the batch stream
     int64_t part_off;   // first partial-sum float of this mesh (chunks > 1)
     PointSrc ps;
     int32_t nF;
@@ -56,7 +58,7 @@ struct BGroup {
 
 struct BatchHeader {
     int64_t n_units;
-    int64_t total_faces;
+    int64_t total_records;
     int64_t total_reduce_points;
     int64_t off_meshes, off_groups, off_face_prefix, off_reduce_ids, off_reduce_prefix, off_soup, off_part;
     int32_t n_meshes;
@@ -95,55 +97,43 @@ __device__ __forceinline__ int32_t upper_index_group(const BGroup *g, int32_t n,
     return lo;
 }
 
-// Pack every mesh's faces into one soup (same record and index rule as k_pack).
+// Vertex records of every mesh into one stream (same record rule as k_pack_records).
 __global__ __launch_bounds__(kBlock) void k_batched_pack(char *ws) {
     const BatchHeader *bh = bheader(ws);
     const BMesh *meshes = reinterpret_cast<const BMesh *>(ws + bh->off_meshes);
-    const int64_t *fpre = reinterpret_cast<const int64_t *>(ws + bh->off_face_prefix);
-    FaceRec *soup = reinterpret_cast<FaceRec *>(ws + bh->off_soup);
+    const int64_t *rpre = reinterpret_cast<const int64_t *>(ws + bh->off_face_prefix);
+    VRec *recs = reinterpret_cast<VRec *>(ws + bh->off_soup);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
-    const int64_t total = bh->total_faces;
+    const int64_t total = bh->total_records;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t m = upper_index(fpre, bh->n_meshes, g);
+        const int32_t m = upper_index(rpre, bh->n_meshes, g);
         const BMesh &mh = meshes[m];
-        const int64_t f = g - fpre[m];
-        int32_t id[3];
-        bool bad = false;
-        for (int j = 0; j < 3; ++j) {
-            id[j] = mh.F[3 * f + j];
-            if (id[j] < 0 || (int64_t)id[j] >= mh.nV) {
-                bad = true;
-                id[j] = 0;
-            }
+        const int64_t r = g - rpre[m];
+        int32_t vid, fid;
+        if (mh.R) {
+            vid = mh.R[2 * r];
+            fid = mh.R[2 * r + 1];
+        } else {
+            const int64_t f = r / 3;
+            const int j = (int)(r - 3 * f);
+            vid = mh.F[3 * f + j];
+            fid = j == 2 ? (int32_t)f : -1;
         }
-        if (bad) atomicOr(&hdr->bad_index, 1);
-        float v[3][3];
-        for (int j = 0; j < 3; ++j)
-            for (int c = 0; c < 3; ++c) v[j][c] = mh.V[3 * (int64_t)id[j] + c];
-        const double e1x = (double)v[1][0] - v[0][0], e1y = (double)v[1][1] - v[0][1],
-                     e1z = (double)v[1][2] - v[0][2];
-        const double e2x = (double)v[2][0] - v[0][0], e2y = (double)v[2][1] - v[0][1],
-                     e2z = (double)v[2][2] - v[0][2];
-        FaceRec r;
-        r.a = make_float4(v[0][0], v[0][1], v[0][2], v[1][0]);
-        r.b = make_float4(v[1][1], v[1][2], v[2][0], v[2][1]);
-        r.c = make_float4(v[2][2], (float)(e1y * e2z - e1z * e2y), (float)(e1z * e2x - e1x * e2z),
-                          (float)(e1x * e2y - e1y * e2x));
-        soup[g] = r;
+        recs[g] = make_record(mh.V, mh.nV, mh.F, mh.nF, vid, fid, hdr);
     }
 }
 
 // Persistent workgroups: take units from the cursor until the list is exhausted.
 template <int PPL>
 __global__ __launch_bounds__(kBlock) void k_batched_persistent(char *ws) {
-    __shared__ float4 tile[kFaceTile * 3];
+    __shared__ float4 tile[kRecTile * 2];
     __shared__ int64_t s_unit;
     __shared__ int32_t s_group;
     const BatchHeader *bh = bheader(ws);
     const BMesh *meshes = reinterpret_cast<const BMesh *>(ws + bh->off_meshes);
     const BGroup *groups = reinterpret_cast<const BGroup *>(ws + bh->off_groups);
-    const float4 *soup = reinterpret_cast<const float4 *>(ws + bh->off_soup);
+    const float4 *recs = reinterpret_cast<const float4 *>(ws + bh->off_soup);
     float *part = reinterpret_cast<float *>(ws + bh->off_part);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
     const int64_t n_units = bh->n_units;
@@ -163,8 +153,8 @@ __global__ __launch_bounds__(kBlock) void k_batched_persistent(char *ws) {
         const BMesh &mh = meshes[gr.mesh];
         const int64_t pblock = u - gr.unit_begin;
         const int64_t base = pblock * (kBlock * PPL) + tid;
-        const int32_t f0 = gr.chunk * kChunkFaces;
-        const int32_t f1 = min(mh.nF, f0 + kChunkFaces);
+        const int64_t r0 = (int64_t)gr.chunk * kChunkRecords;
+        const int64_t r1 = min(mh.nR, r0 + kChunkRecords);
         float qx[PPL], qy[PPL], qz[PPL], s[PPL], c[PPL];
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
@@ -174,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_persistent(char *ws) {
             s[p] = 0.0f;
             c[p] = 0.0f;
         }
-        sum_faces<PPL>(soup + 3 * mh.soup_off, f0, f1, tile, qx, qy, qz, s, c);
+        sum_records<PPL>(recs + 2 * mh.rec_off, r0, r1, tile, qx, qy, qz, s, c);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             const int64_t idx = base + (int64_t)p * kBlock;
@@ -227,6 +217,9 @@ struct Plan {
 bool desc_ok(const wn_mesh_desc &d) {
     if (d.nV < 0 || d.nF < 0 || d.nV > 2147483647LL || d.nF > 2147483647LL) return false;
     if (d.nF > 0 && (d.V == nullptr || d.F == nullptr || d.nV == 0)) return false;
+    if (d.strips == nullptr ? d.n_strip_records != 0
+                            : (d.n_strip_records < 0 || d.n_strip_records > 2147483647LL || d.nF == 0))
+        return false;
     int64_t p = 1;
     for (int k = 0; k < 3; ++k) {
         if (d.grid.n[k] < 1) return false;
@@ -258,7 +251,9 @@ size_t tables_layout(int32_t n, int32_t n_groups, int32_t n_reduce, BatchHeader 
     return o;
 }
 
-int32_t mesh_chunks(int64_t nF) { return nF > 0 ? (int32_t)((nF + kChunkFaces - 1) / kChunkFaces) : 1; }
+int64_t mesh_records(const wn_mesh_desc &d) { return d.strips ? d.n_strip_records : 3 * d.nF; }
+
+int32_t mesh_chunks(int64_t nR) { return nR > 0 ? (int32_t)((nR + kChunkRecords - 1) / kChunkRecords) : 1; }
 
 // Build the tables; ppl only changes the unit count, not any result.
 bool make_plan(const wn_mesh_desc *d, int32_t n, int32_t ppl, Plan &plan) {
@@ -283,15 +278,17 @@ bool make_plan(const wn_mesh_desc *d, int32_t n, int32_t ppl, Plan &plan) {
         const int64_t full = (int64_t)d[m].grid.n[0] * d[m].grid.n[1] * d[m].grid.n[2];
         b.p0 = d[m].point_begin;
         b.P = d[m].point_count > 0 ? d[m].point_count : full - d[m].point_begin;
-        b.soup_off = fpre[(size_t)m];
+        b.R = d[m].strips;
+        b.nR = mesh_records(d[m]);
+        b.rec_off = fpre[(size_t)m];
         b.ps = make_point_src(&d[m].grid, nullptr);
         b.nF = (int32_t)d[m].nF;
-        b.chunks = mesh_chunks(d[m].nF);
+        b.chunks = mesh_chunks(b.nR);
         b.pblocks = (int32_t)((b.P + kBlock * ppl - 1) / (kBlock * ppl));
         b.occ_mode = d[m].occ_mode;
         b.tau = d[m].tau;
         b.k = d[m].k;
-        fpre[(size_t)m + 1] = fpre[(size_t)m] + d[m].nF;
+        fpre[(size_t)m + 1] = fpre[(size_t)m] + b.nR;
         if (b.chunks > 1) {
             b.part_off = part;
             part += (int64_t)b.chunks * b.P;
@@ -299,7 +296,7 @@ bool make_plan(const wn_mesh_desc *d, int32_t n, int32_t ppl, Plan &plan) {
             rpre.push_back(rpre.back() + b.P);
         }
         for (int32_t c = 0; c < b.chunks; ++c) {
-            const int32_t faces = (int32_t)std::min<int64_t>(kChunkFaces, d[m].nF - (int64_t)c * kChunkFaces);
+            const int32_t faces = (int32_t)std::min<int64_t>(kChunkRecords, b.nR - (int64_t)c * kChunkRecords);
             gs.push_back(G{faces, m, c, b.pblocks});
         }
     }
@@ -317,17 +314,17 @@ bool make_plan(const wn_mesh_desc *d, int32_t n, int32_t ppl, Plan &plan) {
     const int32_t n_reduce = (int32_t)rpre.size() - 1;
     const size_t tbytes = tables_layout(n, (int32_t)groups.size(), n_reduce, h);
     h.n_units = units;
-    h.total_faces = fpre[(size_t)n];
+    h.total_records = fpre[(size_t)n];
     h.total_reduce_points = rpre.back();
     h.n_meshes = n;
     h.n_groups = (int32_t)groups.size();
     h.n_reduce = n_reduce;
     h.ppl = ppl;
     h.off_soup = (int64_t)align_up(kWsHeader + tbytes);
-    h.off_part = h.off_soup + (int64_t)align_up((size_t)h.total_faces * sizeof(FaceRec));
+    h.off_part = h.off_soup + (int64_t)align_up((size_t)h.total_records * sizeof(VRec));
     plan.total_bytes = (size_t)h.off_part + align_up((size_t)part * sizeof(float));
     plan.n_units = units;
-    plan.total_faces = h.total_faces;
+    plan.total_faces = h.total_records;
     plan.total_reduce = h.total_reduce_points;
     plan.tables.assign(tbytes, 0);
     char *t = plan.tables.data();

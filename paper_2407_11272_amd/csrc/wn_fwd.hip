@@ -4,8 +4,9 @@
 // Section 2.2 of arXiv 2407.11272 (Eq. 5, 7, 8) and Algorithm 1 define the
 // arithmetic; the layout and launch shapes are this library's own:
 //   * one lane owns PPL query points and keeps their sums in registers;
-//   * faces stream through LDS in tiles of kFaceTile records, each record read by
-//     every lane of the workgroup (a broadcast read, no bank conflicts);
+//   * the mesh streams through LDS as vertex records (three per face, or triangle
+//     strips with one per face), each record read by every lane of the workgroup
+//     (a broadcast read, no bank conflicts);
 //   * each tile's per-point sum is folded into a Neumaier-compensated total;
 //   * when the point count alone cannot fill the GPU, the faces are split over
 //     workgroups and the partial sums are added in a fixed order afterwards.
@@ -55,18 +56,37 @@ __global__ __launch_bounds__(kBlock) void k_pack(const float *__restrict__ V, in
     soup[f] = r;
 }
 
-// All-pairs forward.  Grid: x = point blocks of kBlock * PPL points, y = face splits.
+__global__ __launch_bounds__(kBlock) void k_pack_records(const float *__restrict__ V, int64_t nV,
+                                                         const int32_t *__restrict__ F, int64_t nF,
+                                                         const int32_t *__restrict__ R, int64_t nR,
+                                                         VRec *__restrict__ recs, WsHeader *hdr) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nR) return;
+    int32_t vid, fid;
+    if (R) {
+        vid = R[2 * r];
+        fid = R[2 * r + 1];
+    } else {
+        const int64_t f = r / 3;
+        const int j = (int)(r - 3 * f);
+        vid = F[3 * f + j];
+        fid = j == 2 ? (int32_t)f : -1;
+    }
+    recs[r] = make_record(V, nV, F, nF, vid, fid, hdr);
+}
+
+// All-pairs forward.  Grid: x = point blocks of kBlock * PPL points, y = record splits.
 // With split == 1 the kernel writes W (scaled by 1 / 2 pi) and the occupancy map;
 // otherwise it writes the unscaled partial sum of split y to partials[y * nQ + idx].
 template <int PPL>
-__global__ __launch_bounds__(kBlock) void k_wn_fwd(const FaceRec *__restrict__ soup, int32_t nF, int32_t chunk,
+__global__ __launch_bounds__(kBlock) void k_wn_fwd(const VRec *__restrict__ recs, int64_t nR, int64_t chunk,
                                                    PointSrc ps, int64_t nQ, float *__restrict__ W,
                                                    float *__restrict__ partials, OccParams occ) {
-    __shared__ float4 tile[kFaceTile * 3];
+    __shared__ float4 tile[kRecTile * 2];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * (kBlock * PPL) + tid;
-    const int32_t f0 = (int32_t)blockIdx.y * chunk;
-    const int32_t f1 = min(nF, f0 + chunk);
+    const int64_t r0 = (int64_t)blockIdx.y * chunk;
+    const int64_t r1 = min(nR, r0 + chunk);
 
     float qx[PPL], qy[PPL], qz[PPL], s[PPL], c[PPL];
 #pragma unroll
@@ -77,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_wn_fwd(const FaceRec *__restrict__ s
         s[p] = 0.0f;
         c[p] = 0.0f;
     }
-    sum_faces<PPL>(reinterpret_cast<const float4 *>(soup), f0, f1, tile, qx, qy, qz, s, c);
+    sum_records<PPL>(reinterpret_cast<const float4 *>(recs), r0, r1, tile, qx, qy, qz, s, c);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int64_t idx = base + (int64_t)p * kBlock;
@@ -151,21 +171,21 @@ __global__ __launch_bounds__(kBlock) void k_loss_final(const float *__restrict__
 
 // ---------------------------------------------------------------- launchers
 
-int fwd_split_count(int64_t nF, int64_t nQ) {
-    // Aim for about 8192 wave64s; never give a split fewer than 2 tiles of faces.
+int fwd_split_count(int64_t nR, int64_t nQ) {
+    // Aim for about 8192 wave64s; never give a split fewer than 2 tiles of records.
     const int64_t waves = (nQ + 63) / 64;
     int64_t s = (8192 + waves - 1) / (waves > 0 ? waves : 1);
-    const int64_t max_by_faces = (nF + 2 * kFaceTile - 1) / (2 * kFaceTile);
+    const int64_t max_by_faces = (nR + 2 * kRecTile - 1) / (2 * kRecTile);
     if (s > max_by_faces) s = max_by_faces;
     if (s > 64) s = 64;
     if (s < 1) s = 1;
     return (int)s;
 }
 
-int32_t fwd_split_chunk(int64_t nF, int split) {
-    const int64_t per = (nF + split - 1) / (split > 0 ? split : 1);
-    const int64_t chunk = (per + kFaceTile - 1) / kFaceTile * kFaceTile;
-    return (int32_t)(chunk > 0 ? chunk : kFaceTile);
+int64_t fwd_split_chunk(int64_t nR, int split) {
+    const int64_t per = (nR + split - 1) / (split > 0 ? split : 1);
+    const int64_t chunk = (per + kRecTile - 1) / kRecTile * kRecTile;
+    return chunk > 0 ? chunk : kRecTile;
 }
 
 PointSrc make_point_src(const wn_grid *grid, const float *Q) {
@@ -195,26 +215,34 @@ hipError_t launch_pack(const float *V, int64_t nV, const int32_t *F, int64_t nF,
     return hipGetLastError();
 }
 
-template <int PPL>
-static hipError_t launch_fwd_ppl(const FaceRec *soup, int64_t nF, const PointSrc &ps, int64_t nQ, int split, float *W,
-                                 float *partials, const OccParams &occ, hipStream_t s) {
-    const int64_t pblocks = (nQ + kBlock * PPL - 1) / (kBlock * PPL);
-    const int32_t chunk = fwd_split_chunk(nF, split);
-    dim3 g((unsigned)pblocks, (unsigned)split);
-    k_wn_fwd<PPL><<<g, kBlock, 0, s>>>(soup, (int32_t)nF, chunk, ps, nQ, W, split > 1 ? partials : nullptr, occ);
+hipError_t launch_pack_records(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *R,
+                               int64_t nR, VRec *recs, WsHeader *hdr, hipStream_t s) {
+    if (nR <= 0) return hipSuccess;
+    const int64_t blocks = (nR + kBlock - 1) / kBlock;
+    k_pack_records<<<dim3((unsigned)blocks), kBlock, 0, s>>>(V, nV, F, nF, R, nR, recs, hdr);
     return hipGetLastError();
 }
 
-hipError_t launch_fwd(const FaceRec *soup, int64_t nF, const PointSrc &ps, int64_t nQ, int split, float *W,
+template <int PPL>
+static hipError_t launch_fwd_ppl(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t nQ, int split, float *W,
+                                 float *partials, const OccParams &occ, hipStream_t s) {
+    const int64_t pblocks = (nQ + kBlock * PPL - 1) / (kBlock * PPL);
+    const int64_t chunk = fwd_split_chunk(nR, split);
+    dim3 g((unsigned)pblocks, (unsigned)split);
+    k_wn_fwd<PPL><<<g, kBlock, 0, s>>>(recs, nR, chunk, ps, nQ, W, split > 1 ? partials : nullptr, occ);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t nQ, int split, float *W,
                       float *partials, const OccParams &occ, int ppl, hipStream_t s) {
     if (nQ <= 0) return hipSuccess;
     hipError_t e;
     if (ppl == 1)
-        e = launch_fwd_ppl<1>(soup, nF, ps, nQ, split, W, partials, occ, s);
+        e = launch_fwd_ppl<1>(recs, nR, ps, nQ, split, W, partials, occ, s);
     else if (ppl == 4)
-        e = launch_fwd_ppl<4>(soup, nF, ps, nQ, split, W, partials, occ, s);
+        e = launch_fwd_ppl<4>(recs, nR, ps, nQ, split, W, partials, occ, s);
     else
-        e = launch_fwd_ppl<2>(soup, nF, ps, nQ, split, W, partials, occ, s);
+        e = launch_fwd_ppl<2>(recs, nR, ps, nQ, split, W, partials, occ, s);
     if (e != hipSuccess || split <= 1) return e;
     const int64_t rblocks = (nQ + kBlock - 1) / kBlock;
     k_wn_reduce<<<dim3((unsigned)rblocks), kBlock, 0, s>>>(partials, split, nQ, W, occ);

@@ -5,17 +5,26 @@
 //   t_f(q) = ATAN2(alpha, beta)        (Section 2.2, Eq. 7 and Eq. 8)
 // in a scale-free form that needs no normalised vectors: with R_j = v_j - q,
 // r_j = |R_j|, and the face normal N = (v1 - v0) x (v2 - v0) computed once per face,
-//   alpha' = det(R0, R1, R2) = R0 . N
+//   alpha' = det(R0, R1, R2) = R_j . N   (the same for every vertex j of the face)
 //   beta'  = r0 r1 r2 + (R0.R1) r2 + (R1.R2) r0 + (R2.R0) r1
 // which are alpha and beta of Eq. 7 multiplied by the positive factor r0 r1 r2, so
 // ATAN2(alpha', beta') = ATAN2(alpha, beta).  W(q) = sum_f t_f(q) / (2 pi) (Eq. 5 with
 // Omega = 2 t).  A vertex that coincides with q makes r0 r1 r2 = 0; that face then
 // contributes 0, as a zero-length direction contributes no determinant.
+//
+// The forward kernels read the mesh as a stream of vertex records.  A record carries
+// one vertex position and, if it completes a face, that face's normal: the face is the
+// record's vertex with the vertices of the two records before it.  Three records per
+// face (the default) or triangle strips (consecutive faces sharing an edge, one new
+// vertex per face) describe the same faces; alpha' and beta' do not depend on the
+// order of a face's vertices, and N keeps the face's own winding.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+
+#include <vector>
 
 #include "wn.h"
 
@@ -30,7 +39,14 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kFaceTile = 64;    // faces staged in LDS per tile (3 float4 each)
 constexpr int kWsHeader = 256;   // bytes reserved at the start of every workspace
 
-// Face record in device memory: 12 floats = 3 float4.
+// Vertex record of the forward stream: p = (x, y, z, 1 if it completes a face else 0),
+// n = (N.x, N.y, N.z, 0) of the completed face.
+struct VRec {
+    float4 p, n;
+};
+constexpr int kRecTile = 63;  // records staged in LDS per tile (a multiple of 3)
+
+// Face record in device memory (adjoint): 12 floats = 3 float4.
 //   a = (v0.x, v0.y, v0.z, v1.x)  b = (v1.y, v1.z, v2.x, v2.y)  c = (v2.z, N.x, N.y, N.z)
 struct FaceRec {
     float4 a, b, c;
@@ -160,6 +176,139 @@ __device__ __forceinline__ void sum_faces(const float4 *__restrict__ src, int32_
     }
 }
 
+// One vertex of the record window, per query point: R = v - q, r = |R|, and the dot
+// product and length product with the previous record's vertex.
+template <int PPL>
+struct Slot {
+    float x[PPL], y[PPL], z[PPL], r[PPL], dprev[PPL], rprev[PPL];
+};
+
+// Record v enters slot C (after B, which follows A).  If it completes a face, that face
+// is (A, B, C); its half solid angle at each point is added to ts.
+template <int PPL>
+__device__ __forceinline__ void push_record(const float4 v, const bool face, const float4 n, const Slot<PPL> &A,
+                                            const Slot<PPL> &B, Slot<PPL> &C, const float (&qx)[PPL],
+                                            const float (&qy)[PPL], const float (&qz)[PPL], float (&ts)[PPL]) {
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        C.x[p] = v.x - qx[p];
+        C.y[p] = v.y - qy[p];
+        C.z[p] = v.z - qz[p];
+        C.r[p] = fast_sqrt(C.x[p] * C.x[p] + C.y[p] * C.y[p] + C.z[p] * C.z[p]);
+        C.dprev[p] = B.x[p] * C.x[p] + B.y[p] * C.y[p] + B.z[p] * C.z[p];
+        C.rprev[p] = B.r[p] * C.r[p];
+    }
+    if (face) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const float dca = C.x[p] * A.x[p] + C.y[p] * A.y[p] + C.z[p] * A.z[p];
+            const float pr = B.rprev[p] * C.r[p];  // r_A r_B r_C
+            const float beta = pr + B.dprev[p] * C.r[p] + C.dprev[p] * A.r[p] + dca * B.r[p];
+            float alpha = A.x[p] * n.x + A.y[p] * n.y + A.z[p] * n.z;
+            alpha = (pr == 0.0f) ? 0.0f : alpha;
+            ts[p] += atan2_eq8(alpha, beta);
+        }
+    }
+}
+
+__device__ __forceinline__ bool record_face(const float4 v) {
+    return __builtin_amdgcn_readfirstlane(__float_as_int(v.w)) != 0;
+}
+
+// Sum of the half solid angles of the faces completed by records [r0, r1), at PPL
+// points per lane.  The two records before r0 (if any) prime the vertex window, so a
+// range may start anywhere in the stream.  Records are staged through `tile` (LDS,
+// 2 * kRecTile float4) by the whole workgroup; each tile's per-point sum is folded into
+// the Neumaier pair (s, c).  The result depends only on the record stream and the tile
+// boundaries.  The window's three slots rotate statically (records are taken three at
+// a time; kRecTile is a multiple of three), so no register moves are needed.
+template <int PPL>
+__device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int64_t r0, int64_t r1, float4 *tile,
+                                            const float (&qx)[PPL], const float (&qy)[PPL], const float (&qz)[PPL],
+                                            float (&s)[PPL], float (&c)[PPL]) {
+    if (r0 >= r1) return;  // empty range: nothing to prime or sum (uniform)
+    const int tid = threadIdx.x;
+    Slot<PPL> S0, S1, S2;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        S0.x[p] = S0.y[p] = S0.z[p] = S0.r[p] = S0.dprev[p] = S0.rprev[p] = 0.0f;
+        S1.x[p] = S1.y[p] = S1.z[p] = S1.r[p] = S1.dprev[p] = S1.rprev[p] = 0.0f;
+        S2.x[p] = S2.y[p] = S2.z[p] = S2.r[p] = S2.dprev[p] = S2.rprev[p] = 0.0f;
+    }
+    {
+        float ts[PPL];
+        const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (r0 >= 2) push_record<PPL>(src[2 * (r0 - 2)], false, zero, S2, S0, S1, qx, qy, qz, ts);
+        if (r0 >= 1) push_record<PPL>(src[2 * (r0 - 1)], false, zero, S0, S1, S2, qx, qy, qz, ts);
+    }
+    // window now: A = S1, B = S2
+    for (int64_t t0 = r0; t0 < r1; t0 += kRecTile) {
+        const int nt = (int)min((int64_t)kRecTile, r1 - t0);
+        __syncthreads();
+        if (tid < 2 * nt) tile[tid] = src[2 * t0 + tid];
+        __syncthreads();
+        float ts[PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
+        int i = 0;
+        for (; i + 3 <= nt; i += 3) {
+            const float4 v0 = tile[2 * i], v1 = tile[2 * i + 2], v2 = tile[2 * i + 4];
+            push_record<PPL>(v0, record_face(v0), tile[2 * i + 1], S1, S2, S0, qx, qy, qz, ts);
+            push_record<PPL>(v1, record_face(v1), tile[2 * i + 3], S2, S0, S1, qx, qy, qz, ts);
+            push_record<PPL>(v2, record_face(v2), tile[2 * i + 5], S0, S1, S2, qx, qy, qz, ts);
+        }
+        // a partial group only occurs in the last tile of the range
+        if (i < nt) {
+            const float4 v0 = tile[2 * i];
+            push_record<PPL>(v0, record_face(v0), tile[2 * i + 1], S1, S2, S0, qx, qy, qz, ts);
+            if (i + 1 < nt) {
+                const float4 v1 = tile[2 * i + 2];
+                push_record<PPL>(v1, record_face(v1), tile[2 * i + 3], S2, S0, S1, qx, qy, qz, ts);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) neumaier_add(s[p], c[p], ts[p]);
+    }
+}
+
+// Vertex record r of the forward stream (see the header comment): vertex `vid` and,
+// if fid >= 0, the normal of face fid in its own winding, computed in FP64.  Ids outside
+// their ranges are replaced (vertex 0, "no face") and recorded in the workspace.
+__device__ __forceinline__ VRec make_record(const float *__restrict__ V, int64_t nV, const int32_t *__restrict__ F,
+                                            int64_t nF, int32_t vid, int32_t fid, WsHeader *hdr) {
+    bool bad = false;
+    if (vid < 0 || (int64_t)vid >= nV) {
+        bad = true;
+        vid = 0;
+    }
+    if (fid < -1 || (int64_t)fid >= nF) {
+        bad = true;
+        fid = -1;
+    }
+    VRec r;
+    r.p = make_float4(V[3 * (int64_t)vid], V[3 * (int64_t)vid + 1], V[3 * (int64_t)vid + 2], fid >= 0 ? 1.0f : 0.0f);
+    r.n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (fid >= 0) {
+        int32_t id[3];
+        for (int j = 0; j < 3; ++j) {
+            id[j] = F[3 * (int64_t)fid + j];
+            if (id[j] < 0 || (int64_t)id[j] >= nV) {
+                bad = true;
+                id[j] = 0;
+            }
+        }
+        double v[3][3];
+        for (int j = 0; j < 3; ++j)
+            for (int c = 0; c < 3; ++c) v[j][c] = V[3 * (int64_t)id[j] + c];
+        const double e1x = v[1][0] - v[0][0], e1y = v[1][1] - v[0][1], e1z = v[1][2] - v[0][2];
+        const double e2x = v[2][0] - v[0][0], e2y = v[2][1] - v[0][1], e2z = v[2][2] - v[0][2];
+        r.n = make_float4((float)(e1y * e2z - e1z * e2y), (float)(e1z * e2x - e1x * e2z),
+                          (float)(e1x * e2y - e1y * e2x), 0.0f);
+    }
+    if (bad) atomicOr(&hdr->bad_index, 1);
+    return r;
+}
+
 struct OccParams {
     void *occ;
     int32_t mode;
@@ -182,8 +331,11 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Partition of the faces over workgroups when there are too few point blocks to
 // fill the GPU.  A pure function of (nF, nQ): results never depend on tuning.
-int fwd_split_count(int64_t nF, int64_t nQ);
-int32_t fwd_split_chunk(int64_t nF, int split);
+int fwd_split_count(int64_t nR, int64_t nQ);
+int64_t fwd_split_chunk(int64_t nR, int split);
+
+// Host triangle-strip builder (wn_strips.hip): records as int32 pairs.
+int64_t build_strips(const int32_t *F, int64_t nF, std::vector<int32_t> &out);
 
 PointSrc make_point_src(const wn_grid *grid, const float *Q);
 
@@ -191,7 +343,11 @@ PointSrc make_point_src(const wn_grid *grid, const float *Q);
 hipError_t launch_ws_reset(WsHeader *hdr, hipStream_t s);
 hipError_t launch_pack(const float *V, int64_t nV, const int32_t *F, int64_t nF, FaceRec *soup,
                        WsHeader *hdr, hipStream_t s);
-hipError_t launch_fwd(const FaceRec *soup, int64_t nF, const PointSrc &ps, int64_t nQ, int split,
+// Vertex records from (V, F) and an optional strip stream R ([nR][2] = vertex, face or
+// -1); with R == nullptr the stream is three records per face (nR = 3 nF).
+hipError_t launch_pack_records(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *R,
+                               int64_t nR, VRec *recs, WsHeader *hdr, hipStream_t s);
+hipError_t launch_fwd(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t nQ, int split,
                       float *W, float *partials, const OccParams &occ, int ppl, hipStream_t s);
 hipError_t launch_occ(const float *W, int64_t n, const OccParams &occ, hipStream_t s);
 hipError_t launch_sigmoid_mse(const float *W, const float *target, int64_t n, float tau, float k,

@@ -1,0 +1,134 @@
+// Triangle-strip order of a mesh (host code).
+//
+// The forward kernels consume a mesh as a stream of vertex records: a record whose
+// face id is f completes face f together with the two records before it.  Along a
+// strip, consecutive faces share an edge, so each new face costs one new vertex
+// (one distance, one square root, two dot products) instead of three.  The order is
+// a pure function of F, built once per topology (a morphing loop that moves the
+// vertices keeps it).  Faces keep their own winding: the kernels take the face
+// normal from F, so strip parity does not matter.
+//
+// Greedy construction: faces are visited in index order; from the first face not yet
+// used, each of its three rotations is extended forward along unused neighbours
+// across the trailing edge, then the sequence is reversed and extended from the other
+// end; the longest of the three is kept.  Strips are capped at kMaxStrip faces.
+#include <string.h>
+
+#include <algorithm>
+#include <unordered_map>
+#include <vector>
+
+#include "wn_internal.hpp"
+
+namespace wn {
+
+namespace {
+
+constexpr int kMaxStrip = 1024;
+
+struct Builder {
+    const int32_t *F;
+    int64_t nF;
+    std::unordered_map<uint64_t, std::vector<int32_t>> edge_faces;
+    std::vector<uint8_t> done;   // face already placed in a strip
+    std::vector<int32_t> stamp;  // face used by the current trial (value = trial id)
+    int32_t trial = 0;
+
+    static uint64_t key(int32_t u, int32_t v) {
+        const uint32_t a = (uint32_t)(u < v ? u : v), b = (uint32_t)(u < v ? v : u);
+        return ((uint64_t)a << 32) | b;
+    }
+
+    void build_edges() {
+        edge_faces.reserve((size_t)nF * 2);
+        for (int64_t f = 0; f < nF; ++f)
+            for (int j = 0; j < 3; ++j) {
+                const int32_t u = F[3 * f + j], v = F[3 * f + (j + 1) % 3];
+                if (u != v) edge_faces[key(u, v)].push_back((int32_t)f);
+            }
+    }
+
+    // Unused face across edge (u, v) other than the ones already taken; -1 if none.
+    int32_t neighbour(int32_t u, int32_t v) const {
+        auto it = edge_faces.find(key(u, v));
+        if (it == edge_faces.end()) return -1;
+        for (int32_t g : it->second)
+            if (!done[(size_t)g] && stamp[(size_t)g] != trial) return g;
+        return -1;
+    }
+
+    // The vertex of face g that is neither u nor v (-1 if g is degenerate there).
+    int32_t third(int32_t g, int32_t u, int32_t v) const {
+        int32_t w = -1, count = 0;
+        for (int j = 0; j < 3; ++j) {
+            const int32_t x = F[3 * (int64_t)g + j];
+            if (x != u && x != v) {
+                w = x;
+                ++count;
+            }
+        }
+        return count == 1 ? w : -1;
+    }
+
+    void extend(std::vector<int32_t> &seq, std::vector<int32_t> &faces) {
+        while ((int)faces.size() < kMaxStrip) {
+            const int32_t u = seq[seq.size() - 2], v = seq[seq.size() - 1];
+            const int32_t g = neighbour(u, v);
+            if (g < 0) return;
+            const int32_t w = third(g, u, v);
+            if (w < 0) return;
+            seq.push_back(w);
+            faces.push_back(g);
+            stamp[(size_t)g] = trial;
+        }
+    }
+};
+
+}  // namespace
+
+// Writes the record stream as int32 pairs (vertex id, face id or -1).  Returns the
+// number of records; with out == nullptr only counts.
+int64_t build_strips(const int32_t *F, int64_t nF, std::vector<int32_t> &out) {
+    Builder b;
+    b.F = F;
+    b.nF = nF;
+    b.build_edges();
+    b.done.assign((size_t)nF, 0);
+    b.stamp.assign((size_t)nF, -1);
+    out.clear();
+    out.reserve((size_t)nF * 2 * 2 + 16);
+    std::vector<int32_t> seq, faces, best_seq, best_faces;
+    for (int64_t f = 0; f < nF; ++f) {
+        if (b.done[(size_t)f]) continue;
+        const int32_t *t = F + 3 * f;
+        best_faces.clear();
+        for (int r = 0; r < 3; ++r) {
+            ++b.trial;
+            seq.assign({t[r], t[(r + 1) % 3], t[(r + 2) % 3]});
+            faces.assign({(int32_t)f});
+            b.stamp[(size_t)f] = b.trial;
+            b.extend(seq, faces);
+            // reverse and extend the other end (faces keep their own winding)
+            std::reverse(seq.begin(), seq.end());
+            std::reverse(faces.begin(), faces.end());
+            b.extend(seq, faces);
+            if (faces.size() > best_faces.size()) {
+                best_faces = faces;
+                best_seq = seq;
+            }
+        }
+        for (int32_t g : best_faces) b.done[(size_t)g] = 1;
+        // records: two opening vertices, then one record per face
+        out.push_back(best_seq[0]);
+        out.push_back(-1);
+        out.push_back(best_seq[1]);
+        out.push_back(-1);
+        for (size_t i = 0; i < best_faces.size(); ++i) {
+            out.push_back(best_seq[i + 2]);
+            out.push_back(best_faces[i]);
+        }
+    }
+    return (int64_t)(out.size() / 2);
+}
+
+}  // namespace wn

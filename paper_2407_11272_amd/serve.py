@@ -244,9 +244,10 @@ class GpuExecutor:
     """Device side of the server: uploads, batched forward steps on one stream, loss
     and adjoint on a second stream, completion times from timing events."""
 
-    def __init__(self, device="cuda", graph: bool = True):
+    def __init__(self, device="cuda", graph: bool = True, strips: bool = True):
         import torch
         self.torch = torch
+        self.strips = strips
         self.dev = torch.device(device)
         self.fwd = torch.cuda.Stream(self.dev)
         self.aux = torch.cuda.Stream(self.dev)
@@ -273,7 +274,12 @@ class GpuExecutor:
             st["V"] = V.to(self.dev, non_blocking=True)
             st["F"] = F.to(self.dev, non_blocking=True)
             st["hold"] = (V, F)
-            job = wn.MeshJob(st["V"], st["F"], wn.Grid.of(req.grid), req.occupancy, req.tau, req.k)
+            R = None
+            if self.strips and len(req.F):
+                Rh = torch.from_numpy(wn.wn_build_strips(req.F, len(req.V))).pin_memory()
+                R = Rh.to(self.dev, non_blocking=True)
+                st["hold_strips"] = Rh
+            job = wn.MeshJob(st["V"], st["F"], wn.Grid.of(req.grid), req.occupancy, req.tau, req.k, strips=R)
             job.prepare()
             st["job"] = job
             if req.wants_grad:
@@ -293,7 +299,7 @@ class GpuExecutor:
         for st, req, p0, n in slices:
             base = st["job"]
             jobs.append(wn.MeshJob(base.V, base.F, base.grid, base.occupancy, base.tau, base.k, base.W, base.occ,
-                                   point_begin=p0, point_count=n))
+                                   point_begin=p0, point_count=n, strips=base.strips))
         with torch.cuda.stream(self.fwd):
             wn.wn_voxelize_batched(jobs, graph=self.graph)
             ev = torch.cuda.Event()
@@ -338,9 +344,10 @@ class GpuExecutor:
         self.torch.cuda.synchronize(self.dev)
 
 
-def run_plain_fifo(requests, device="cuda", keep_results: bool = False):
-    """Baseline: the same trace, FIFO, one mesh per launch (wn_voxelize, then the loss
-    and wn_backward for gradient requests), on one stream; completion from events."""
+def run_plain_fifo(requests, device="cuda", keep_results: bool = False, strips: bool = True):
+    """Baseline: the same trace, FIFO, one mesh per launch (the same forward kernel on
+    the same strip order, then the loss and wn_backward for gradient requests), on one
+    stream; completion from events."""
     import torch
     import paper_2407_11272_amd as wn
     dev = torch.device(device)
@@ -360,7 +367,12 @@ def run_plain_fifo(requests, device="cuda", keep_results: bool = False):
                 time.sleep(2e-4)
             V = torch.from_numpy(np.ascontiguousarray(r.V, dtype=np.float32)).pin_memory().to(dev, non_blocking=True)
             F = torch.from_numpy(np.ascontiguousarray(r.F, dtype=np.int32)).pin_memory().to(dev, non_blocking=True)
-            W, occ = wn.wn_voxelize(V, F, grid=wn.Grid.of(r.grid), occupancy=r.occupancy, tau=r.tau, k=r.k)
+            if strips and len(r.F):
+                R = torch.from_numpy(wn.wn_build_strips(r.F, len(r.V))).pin_memory().to(dev, non_blocking=True)
+                W, occ = wn.wn_voxelize_strips(V, F, R, grid=wn.Grid.of(r.grid), occupancy=r.occupancy, tau=r.tau,
+                                               k=r.k)
+            else:
+                W, occ = wn.wn_voxelize(V, F, grid=wn.Grid.of(r.grid), occupancy=r.occupancy, tau=r.tau, k=r.k)
             res = ServeResult(r.rid, r.arrival, admitted=r.arrival)
             if r.wants_grad:
                 T = torch.from_numpy(np.ascontiguousarray(r.target, dtype=np.float32)).pin_memory().to(

@@ -235,3 +235,64 @@ def test_occupancy_maps_and_loss(dev, orc):
     Lr, gr = orc.sigmoid_mse(Wn, c.target, 0.5, 50.0)
     assert float(loss.item()) == pytest.approx(Lr, rel=1e-5)
     np.testing.assert_allclose(g.cpu().numpy().reshape(-1), gr, rtol=1e-4, atol=1e-12)
+
+
+def _strips_dev(F, nV):
+    import torch
+    import paper_2407_11272_amd as wn
+    return torch.as_tensor(wn.wn_build_strips(F, nV)).cuda()
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c3", "open", "c2"])
+def test_strip_order_parity(dev, orc, cfg):
+    """Triangle-strip record streams give the same field (to rounding) as three records
+    per face, agree with the oracle, and are bit-reproducible."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = {"c1": wi.config1_icosphere, "c3": wi.config3_differentiable,
+         "open": lambda: wi.config3_differentiable(open_variant=True), "c2": wi.config2_ellipsoid_union}[cfg]()
+    Vt, Ft = wn.as_mesh(torch.as_tensor(np.asarray(c.V, np.float32)), torch.as_tensor(c.F))
+    R = _strips_dev(c.F, len(c.V))
+    Ws, occ = wn.wn_voxelize_strips(Vt, Ft, R, grid=c.grid, occupancy="threshold")
+    Ws2 = wn.wn_voxelize_strips(Vt, Ft, R, grid=c.grid)
+    Wp = wn.wn_voxelize(Vt, Ft, grid=c.grid)
+    torch.cuda.synchronize()
+    assert wn.wn_get_device_error() == 0
+    torch.testing.assert_close(Ws, Ws2, rtol=0, atol=0)
+    d = float((Ws - Wp).abs().max())
+    print(f"[strips {cfg}] records/face={R.shape[0] / len(c.F):.3f} max|strips - plain|={d:.2e}", flush=True)
+    assert d <= 2e-6
+    Wn = Ws.cpu().numpy().reshape(-1)
+    Q = orc.grid_points(c.grid)
+    idx = np.random.default_rng(9).choice(len(Q), 3000, replace=False)
+    _compare(orc, c.V, c.F, Q[idx], Wn[idx], f"strips {cfg}", occ_g=occ.cpu().numpy().reshape(-1)[idx])
+
+
+def test_strips_split_path_primes_windows(dev, orc):
+    """Few query points and many faces: the record stream is split over workgroups at
+    arbitrary records, so each split primes its vertex window from the two records
+    before it."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config2_ellipsoid_union()
+    Vt, Ft = wn.as_mesh(torch.as_tensor(np.asarray(c.V, np.float32)), torch.as_tensor(c.F))
+    R = _strips_dev(c.F, len(c.V))
+    rng = np.random.default_rng(11)
+    Q = rng.uniform(-0.5, 0.5, size=(333, 3)).astype(np.float32).astype(np.float64)
+    Qt = torch.as_tensor(Q, dtype=torch.float32).cuda()
+    Ws = wn.wn_voxelize_strips(Vt, Ft, R, Q=Qt).cpu().numpy()
+    _compare(orc, c.V, c.F, Q, Ws, "strips split")
+
+
+def test_bad_strip_records_are_reported(dev):
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere()
+    Vt, Ft = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    R = wn.wn_build_strips(c.F, len(c.V))
+    R[5, 0] = 10 ** 7
+    R[9, 1] = len(c.F) + 3
+    R[12, 1] = -7
+    W = wn.wn_voxelize_strips(Vt, Ft, torch.as_tensor(R).cuda(), grid=c.grid)
+    assert wn.wn_get_device_error() == wn._lib.WN_ERR_BAD_INDEX
+    assert torch.isfinite(W).all()

@@ -1,0 +1,67 @@
+"""CPU tests of the host triangle-strip builder (wn_build_strips): every face exactly
+once, each face record's vertices are the face's vertices, at most 3 records per face,
+deterministic, and long strips on regular meshes."""
+import numpy as np
+import pytest
+
+import paper_2407_11272_amd as wn
+import wn_inputs as wi
+from paper_2407_11272_amd import _lib as L
+
+
+def _check_stream(F, R):
+    F = np.asarray(F)
+    faces = R[:, 1]
+    assert sorted(faces[faces >= 0].tolist()) == list(range(len(F)))
+    for i in np.nonzero(faces >= 0)[0]:
+        assert i >= 2
+        assert sorted(R[i - 2:i + 1, 0].tolist()) == sorted(F[faces[i]].tolist())
+    assert len(R) <= 3 * len(F)
+    # every strip opens with two vertex-only records
+    assert len(R) == 0 or (R[0, 1] == -1 and R[1, 1] == -1)
+
+
+@pytest.mark.parametrize("mesh", ["ico3", "ico4", "c2", "open", "soup", "degenerate"])
+def test_strip_stream_is_valid(mesh):
+    rng = np.random.default_rng(3)
+    if mesh == "ico3":
+        V, F = wi.icosphere(3)
+    elif mesh == "ico4":
+        V, F = wi.icosphere(4)
+    elif mesh == "c2":
+        c = wi.config2_ellipsoid_union()
+        V, F = c.V, c.F
+    elif mesh == "open":
+        c = wi.config3_differentiable(open_variant=True)
+        V, F = c.V, c.F
+    elif mesh == "soup":
+        V = rng.normal(size=(90, 3))
+        F = rng.permutation(90).reshape(30, 3)
+    else:
+        V = rng.normal(size=(10, 3))
+        F = np.array([[0, 1, 2], [1, 1, 3], [2, 3, 3], [4, 5, 6], [5, 4, 7], [0, 0, 0]])
+    R = wn.wn_build_strips(F, len(V))
+    _check_stream(F, R)
+    R2 = wn.wn_build_strips(F, len(V))
+    np.testing.assert_array_equal(R, R2)
+
+
+def test_strips_are_long_on_regular_meshes():
+    V, F = wi.icosphere(4)
+    assert len(wn.wn_build_strips(F, len(V))) / len(F) < 1.1
+    c = wi.config2_ellipsoid_union()
+    assert len(wn.wn_build_strips(c.F, len(c.V))) / len(c.F) < 1.25
+
+
+def test_strip_builder_errors():
+    import ctypes
+    lib = L.load()
+    n = ctypes.c_int64(-1)
+    F = np.array([[0, 1, 5]], dtype=np.int32)
+    assert lib.wn_build_strips(F.ctypes.data, 1, 3, None, 0, ctypes.byref(n)) == L.WN_ERR_INVALID_ARG
+    F = np.array([[0, 1, 2]], dtype=np.int32)
+    assert lib.wn_build_strips(F.ctypes.data, 1, 3, None, 0, ctypes.byref(n)) == L.WN_OK and n.value == 3
+    out = np.zeros((2, 2), dtype=np.int32)
+    assert lib.wn_build_strips(F.ctypes.data, 1, 3, out.ctypes.data, 2, ctypes.byref(n)) == L.WN_ERR_WORKSPACE
+    assert lib.wn_build_strips(None, 0, 0, None, 0, ctypes.byref(n)) == L.WN_OK and n.value == 0
+    assert lib.wn_build_strips(F.ctypes.data, 1, 3, None, 0, None) == L.WN_ERR_INVALID_ARG
