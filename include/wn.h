@@ -77,6 +77,7 @@ typedef int32_t wn_status;
 #define WN_OP_BACKWARD 1
 #define WN_OP_BATCHED 2
 #define WN_OP_LOSS 3
+#define WN_OP_FLIP 4
 
 /* Axis-aligned voxel grid: n[d] cells spanning [lo[d], hi[d]]. */
 typedef struct {
@@ -86,7 +87,7 @@ typedef struct {
 } wn_grid;
 
 /* Bytes of device workspace an operation needs (WN_OP_VOXELIZE, WN_OP_BACKWARD,
- * WN_OP_LOSS; a batched launch uses wn_workspace_size_batched).  Returns 0 for an
+ * WN_OP_LOSS, WN_OP_FLIP; a batched launch uses wn_workspace_size_batched).  Returns 0 for an
  * unknown op or negative sizes. */
 WN_API size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ);
 
@@ -214,6 +215,19 @@ WN_API size_t wn_workspace_size_batched(const wn_mesh_desc *desc, int32_t n);
  */
 WN_API wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws, size_t ws_bytes,
                              void *stream, char *report, size_t report_len);
+
+/*
+ * Flipping duplication of an open mesh (Algorithm 2 of the paper): writes
+ *   V2 = [V ; V - eps * N]            (float [2 nV][3], N = unit vertex normals)
+ *   F2 = [F ; flip(F) + nV]           (int32 [2 nF][3], flip(a, b, c) = (a, c, b))
+ * so that (V2, F2) can be voxelized like a closed mesh; the slit between the two
+ * layers is eps thick.  A vertex normal is the normalised sum of the area-weighted
+ * normals (v1 - v0) x (v2 - v0) of the faces using the vertex (0 if none), summed in
+ * FP64 in face order.  Out-of-range face indices are replaced by 0 and recorded.
+ * Workspace: wn_workspace_size(WN_OP_FLIP, nV, nF, 0).
+ */
+WN_API wn_status wn_flip_duplicate(const float *V, int64_t nV, const int32_t *F, int64_t nF, float eps,
+                                   float *V2, int32_t *F2, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Reads and clears the device-side error record that the most recent call using

@@ -199,6 +199,38 @@ def guard_mask(V, F, Q, edge_tol: float = 1e-4, face_tol: float = 1e-6, threads:
     return (de < edge_tol) | (df < face_tol)
 
 
+# ------------------------------------------------------- flipping duplication ---
+
+def vertex_normals(V, F) -> np.ndarray:
+    """Unit vertex normals: the sum of the (area-weighted) face normals
+    (v1 - v0) x (v2 - v0) of the faces using the vertex, normalised; 0 for a vertex
+    no face uses or whose sum vanishes.  (Algorithm 2 asks for per-vertex normals
+    without fixing their weighting; area weighting is the reading taken.)"""
+    V = np.asarray(V, dtype=np.float64).reshape(-1, 3)
+    F = np.asarray(F, dtype=np.int64).reshape(-1, 3)
+    acc = np.zeros_like(V)
+    for f in F:  # in face order
+        n = np.cross(V[f[1]] - V[f[0]], V[f[2]] - V[f[0]])
+        for j in range(3):
+            acc[f[j]] += n
+    norm = np.linalg.norm(acc, axis=1, keepdims=True)
+    out = np.zeros_like(V)
+    ok = norm[:, 0] > 0
+    out[ok] = acc[ok] / norm[ok]
+    return out
+
+
+def flip_duplicate(V, F, eps: float = 0.01):
+    """Algorithm 2 (flipping duplication): V' = V - eps N (vertex normals), faces copied
+    onto V' with their orientation reversed, returned as (V | V', F | F')."""
+    V = np.asarray(V, dtype=np.float64).reshape(-1, 3)
+    F = np.asarray(F, dtype=np.int64).reshape(-1, 3)
+    N = vertex_normals(V, F)
+    V2 = np.concatenate([V, V - eps * N], axis=0)
+    Fp = F[:, [0, 2, 1]] + len(V)
+    return V2, np.concatenate([F, Fp], axis=0)
+
+
 # ------------------------------------------------------------ occupancy maps ---
 
 def occupancy_threshold(W, tau: float = 0.5) -> np.ndarray:

@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     voxelize,
     wn_backward,
     wn_build_strips,
+    wn_flip_duplicate,
     wn_voxelize_strips,
     wn_get_device_error,
     wn_occupancy,

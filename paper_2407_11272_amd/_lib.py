@@ -26,6 +26,7 @@ WN_OP_VOXELIZE = 0
 WN_OP_BACKWARD = 1
 WN_OP_BATCHED = 2
 WN_OP_LOSS = 3
+WN_OP_FLIP = 4
 
 WN_BATCH_NO_GRAPH = 1
 
@@ -41,6 +42,7 @@ EXPORTED = (
     "wn_voxelize_batched",
     "wn_workspace_size_batched",
     "wn_autotune",
+    "wn_flip_duplicate",
     "wn_get_device_error",
     "wn_status_string",
     "wn_version",
@@ -110,6 +112,8 @@ def load():
     lib.wn_workspace_size_batched.argtypes = [ctypes.POINTER(WnMeshDesc), i32]
     lib.wn_autotune.restype = i32
     lib.wn_autotune.argtypes = [i32, ctypes.POINTER(WnMeshDesc), i32, vp, sz, vp, ctypes.c_char_p, sz]
+    lib.wn_flip_duplicate.restype = i32
+    lib.wn_flip_duplicate.argtypes = [vp, i64, vp, i64, f32, vp, vp, vp, sz, vp]
     lib.wn_get_device_error.restype = i32
     lib.wn_get_device_error.argtypes = [vp, vp]
     lib.wn_status_string.restype = ctypes.c_char_p

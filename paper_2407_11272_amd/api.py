@@ -247,6 +247,21 @@ def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Ten
     return (dLdV, dLdT) if want_dLdT else dLdV
 
 
+def wn_flip_duplicate(V, F, eps: float = 0.01):
+    """Algorithm 2 (flipping duplication) on the device: returns (V2 [2nV, 3], F2 [2nF, 3])."""
+    lib = L.load()
+    _check_mesh(V, F)
+    dev = V.device
+    V2 = torch.empty((2 * V.shape[0], 3), dtype=torch.float32, device=dev)
+    F2 = torch.empty((2 * F.shape[0], 3), dtype=torch.int32, device=dev)
+    need = wn_workspace_size(L.WN_OP_FLIP, V.shape[0], F.shape[0], 0)
+    ws, wsb = Workspace.get(need, dev)
+    st = lib.wn_flip_duplicate(_ptr(V), V.shape[0], _ptr(F), F.shape[0], eps, _ptr(V2), _ptr(F2), ws, wsb,
+                               _stream_handle(dev))
+    L.check("wn_flip_duplicate", st)
+    return V2, F2
+
+
 def wn_get_device_error(device=None) -> int:
     """Status of the last call on the current stream's workspace (synchronises)."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())

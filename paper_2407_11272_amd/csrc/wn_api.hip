@@ -61,6 +61,8 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
             return bwd_workspace(nV, nF, nQ);
         case WN_OP_LOSS:
             return kWsHeader + align_up((size_t)loss_blocks(nQ) * sizeof(float));
+        case WN_OP_FLIP:
+            return flip_workspace(nV, nF);
         default:
             return 0;
     }
@@ -261,6 +263,17 @@ wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws,
         report[report_len - 1] = 0;
     }
     return WN_OK;
+}
+
+wn_status wn_flip_duplicate(const float *V, int64_t nV, const int32_t *F, int64_t nF, float eps, float *V2,
+                            int32_t *F2, void *ws, size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
+    if (2 * nV > kMaxCount || 2 * nF > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (nV > 0 && V2 == nullptr) return WN_ERR_INVALID_ARG;
+    if (nF > 0 && F2 == nullptr) return WN_ERR_INVALID_ARG;
+    if (!(eps == eps)) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < flip_workspace(nV, nF)) return WN_ERR_WORKSPACE;
+    return run_flip(V, nV, F, nF, eps, V2, F2, static_cast<char *>(ws), ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 wn_status wn_get_device_error(void *ws, void *stream) {

@@ -159,6 +159,79 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ T, 
     for (int d = 0; d < 3; ++d) dLdV[3 * v + d] = s[d] + c[d];
 }
 
+// ------------------------------------------------- flipping duplication ---
+//
+// Algorithm 2 of the paper turns an open mesh into an almost closed one: each vertex is
+// copied and moved by -eps along its vertex normal, and each face is copied onto the
+// moved vertices with its orientation reversed.  The vertex normal is the normalised
+// sum of the area-weighted face normals (v1 - v0) x (v2 - v0) of the faces that use
+// the vertex (the paper does not fix the weighting), summed in FP64 in face order
+// through the same stable corner sort as the adjoint, so the result is deterministic.
+
+__global__ __launch_bounds__(kBlock) void k_face_normals(const float *__restrict__ V, int64_t nV,
+                                                         const int32_t *__restrict__ F, int64_t nF,
+                                                         double *__restrict__ Nf, WsHeader *hdr) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nF) return;
+    int32_t id[3];
+    bool bad = false;
+    for (int j = 0; j < 3; ++j) {
+        id[j] = F[3 * f + j];
+        if (id[j] < 0 || (int64_t)id[j] >= nV) {
+            bad = true;
+            id[j] = 0;
+        }
+    }
+    if (bad) atomicOr(&hdr->bad_index, 1);
+    double v[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int c = 0; c < 3; ++c) v[j][c] = V[3 * (int64_t)id[j] + c];
+    const double e1x = v[1][0] - v[0][0], e1y = v[1][1] - v[0][1], e1z = v[1][2] - v[0][2];
+    const double e2x = v[2][0] - v[0][0], e2y = v[2][1] - v[0][1], e2z = v[2][2] - v[0][2];
+    Nf[3 * f + 0] = e1y * e2z - e1z * e2y;
+    Nf[3 * f + 1] = e1z * e2x - e1x * e2z;
+    Nf[3 * f + 2] = e1x * e2y - e1y * e2x;
+}
+
+// V2[v] = V[v];  V2[nV + v] = V[v] - eps * unit(sum of the normals of v's faces).
+__global__ __launch_bounds__(kBlock) void k_flip_vertices(const double *__restrict__ Nf,
+                                                          const int32_t *__restrict__ corners,
+                                                          const int32_t *__restrict__ vstart,
+                                                          const int32_t *__restrict__ vend,
+                                                          const float *__restrict__ V, int64_t nV, float eps,
+                                                          float *__restrict__ V2) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nV) return;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int32_t i = vstart[v]; i < vend[v]; ++i) {
+        const int64_t f = corners[i] / 3;
+        for (int d = 0; d < 3; ++d) a[d] += Nf[3 * f + d];
+    }
+    const double len = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (int d = 0; d < 3; ++d) {
+        const double n = len > 0.0 ? a[d] / len : 0.0;
+        const float x = V[3 * v + d];
+        V2[3 * v + d] = x;
+        V2[3 * (nV + v) + d] = (float)((double)x - (double)eps * n);
+    }
+}
+
+// F2[f] = F[f];  F2[nF + f] = (F[f][0], F[f][2], F[f][1]) + nV  (out-of-range ids -> 0).
+__global__ __launch_bounds__(kBlock) void k_flip_faces(const int32_t *__restrict__ F, int64_t nF, int64_t nV,
+                                                       int32_t *__restrict__ F2) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nF) return;
+    int32_t id[3];
+    for (int j = 0; j < 3; ++j) {
+        id[j] = F[3 * f + j];
+        if (id[j] < 0 || (int64_t)id[j] >= nV) id[j] = 0;
+    }
+    for (int j = 0; j < 3; ++j) F2[3 * f + j] = id[j];
+    F2[3 * (nF + f) + 0] = id[0] + (int32_t)nV;
+    F2[3 * (nF + f) + 1] = id[2] + (int32_t)nV;
+    F2[3 * (nF + f) + 2] = id[1] + (int32_t)nV;
+}
+
 // ------------------------------------------------------------------ host
 
 namespace {
@@ -224,6 +297,46 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 }  // namespace
 
 size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ) { return plan_backward(nV, nF, nQ).total; }
+
+// The flip reuses the adjoint's layout with no points: the corner sort buffers, vertex
+// bounds, and the face-normal table in place of the per-split partials.
+size_t flip_workspace(int64_t nV, int64_t nF) {
+    const BwdPlan p = plan_backward(nV, nF, 0);
+    return p.total + align_up((size_t)nF * 3 * sizeof(double));
+}
+
+wn_status run_flip(const float *V, int64_t nV, const int32_t *F, int64_t nF, float eps, float *V2, int32_t *F2,
+                   char *ws, size_t ws_bytes, hipStream_t s) {
+    const BwdPlan p = plan_backward(nV, nF, 0);
+    if (ws_bytes < flip_workspace(nV, nF)) return WN_ERR_WORKSPACE;
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+    double *Nf = reinterpret_cast<double *>(ws + p.total);
+    int32_t *keys = reinterpret_cast<int32_t *>(ws + p.off_keys);
+    int32_t *vals = reinterpret_cast<int32_t *>(ws + p.off_vals);
+    int32_t *keys2 = reinterpret_cast<int32_t *>(ws + p.off_keys2);
+    int32_t *vals2 = reinterpret_cast<int32_t *>(ws + p.off_vals2);
+    int32_t *vs = reinterpret_cast<int32_t *>(ws + p.off_vs);
+    int32_t *ve = reinterpret_cast<int32_t *>(ws + p.off_ve);
+    hipError_t e = launch_ws_reset(hdr, s);
+    if (e != hipSuccess) return WN_ERR_HIP;
+    const int64_t nC = 3 * nF;
+    if (nV > 0) {
+        k_fill_i32<<<blocks_for(nV), kBlock, 0, s>>>(vs, nV, 0);
+        k_fill_i32<<<blocks_for(nV), kBlock, 0, s>>>(ve, nV, 0);
+    }
+    if (nF > 0) {
+        k_face_normals<<<blocks_for(nF), kBlock, 0, s>>>(V, nV, F, nF, Nf, hdr);
+        k_corner_keys<<<blocks_for(nC), kBlock, 0, s>>>(F, nC, nV, keys, vals);
+        if ((e = hipGetLastError()) != hipSuccess) return WN_ERR_HIP;
+        size_t tmp = p.sort_tmp;
+        e = rocprim::radix_sort_pairs(ws + p.off_tmp, tmp, keys, keys2, vals, vals2, (size_t)nC, 0u, p.bits, s);
+        if (e != hipSuccess) return WN_ERR_HIP;
+        k_bounds<<<blocks_for(nC), kBlock, 0, s>>>(keys2, nC, vs, ve);
+        k_flip_faces<<<blocks_for(nF), kBlock, 0, s>>>(F, nF, nV, F2);
+    }
+    if (nV > 0) k_flip_vertices<<<blocks_for(nV), kBlock, 0, s>>>(Nf, vals2, vs, ve, V, nV, eps, V2);
+    return hipGetLastError() == hipSuccess ? WN_OK : WN_ERR_HIP;
+}
 
 wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps, int64_t nQ,
                        const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes, hipStream_t s) {

@@ -360,6 +360,11 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
                        int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes,
                        hipStream_t s);
 
+// Flipping duplication (wn_bwd.hip).
+size_t flip_workspace(int64_t nV, int64_t nF);
+wn_status run_flip(const float *V, int64_t nV, const int32_t *F, int64_t nF, float eps, float *V2, int32_t *F2,
+                   char *ws, size_t ws_bytes, hipStream_t s);
+
 // Batched pieces (wn_batched.hip).
 size_t batched_workspace(const wn_mesh_desc *d, int32_t n);
 wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws, size_t ws_bytes,

@@ -30,6 +30,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 POINT_QUANTUM = 2048  # slice sizes are multiples of this many voxels
+SHARE_POLICY = "age"  # "fair": equal shares; "age": shares grow with time since arrival
+AGE_TAU = 0.25        # seconds of waiting that double a request's share under "age"
 
 
 @dataclass
@@ -157,9 +159,15 @@ class Server:
         fwd = [a for a in self.active if not a.launched_all]
         if not fwd:
             return []
-        share = self.quantum / len(fwd)
+        if SHARE_POLICY == "age":
+            now = self.clock() - self.t0
+            w = [1.0 + max(0.0, now - a.req.arrival) / AGE_TAU for a in fwd]
+        else:
+            w = [1.0] * len(fwd)
+        wsum = sum(w)
         slices = []
-        for a in fwd:
+        for a, wi_ in zip(fwd, w):
+            share = self.quantum * wi_ / wsum
             nF = max(1, len(a.req.F))
             pts = max(POINT_QUANTUM, int(share / nF) // POINT_QUANTUM * POINT_QUANTUM)
             pts = min(pts, self._max_slice_points(a.req), a.req.points - a.next_point)

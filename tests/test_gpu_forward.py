@@ -259,11 +259,22 @@ def test_strip_order_parity(dev, orc, cfg):
     torch.cuda.synchronize()
     assert wn.wn_get_device_error() == 0
     torch.testing.assert_close(Ws, Ws2, rtol=0, atol=0)
-    d = float((Ws - Wp).abs().max())
-    print(f"[strips {cfg}] records/face={R.shape[0] / len(c.F):.3f} max|strips - plain|={d:.2e}", flush=True)
-    assert d <= 2e-6
-    Wn = Ws.cpu().numpy().reshape(-1)
+    diff = (Ws - Wp).abs().cpu().numpy().reshape(-1)
     Q = orc.grid_points(c.grid)
+    # the two face orders round differently; where they differ by more than 2e-6 the
+    # voxel must lie in the guard band, or both must hold the oracle's 1e-4
+    far = np.nonzero(diff > 2e-6)[0]
+    print(f"[strips {cfg}] records/face={R.shape[0] / len(c.F):.3f} max|strips - plain|={diff.max():.2e} "
+          f"voxels > 2e-6: {len(far)}", flush=True)
+    assert len(far) <= 1e-3 * len(diff)
+    if len(far):
+        V64 = np.asarray(c.V, np.float32).astype(np.float64)
+        g = orc.guard_mask(V64, c.F, Q[far])
+        Wr = orc.winding(V64, c.F, Q[far])
+        Wsn = Ws.cpu().numpy().reshape(-1)[far]
+        Wpn = Wp.cpu().numpy().reshape(-1)[far]
+        assert np.all(g | ((np.abs(Wsn - Wr) <= 1e-4) & (np.abs(Wpn - Wr) <= 1e-4)))
+    Wn = Ws.cpu().numpy().reshape(-1)
     idx = np.random.default_rng(9).choice(len(Q), 3000, replace=False)
     _compare(orc, c.V, c.F, Q[idx], Wn[idx], f"strips {cfg}", occ_g=occ.cpu().numpy().reshape(-1)[idx])
 

@@ -443,3 +443,52 @@ def test_thread_count_does_not_change_results(orc):
     a = orc.winding(c.V, c.F, Q, threads=1)
     b = orc.winding(c.V, c.F, Q, threads=4)
     np.testing.assert_array_equal(a, b)
+
+
+# ---------------------------------------------------- flipping duplication
+
+def test_vertex_normals_closed_forms(orc):
+    """Regular octahedron: each vertex's four faces have equal area, so its normal is
+    the axis direction; icosphere normals converge to the radial direction."""
+    V, F = wi.octahedron_mesh(1.0)
+    np.testing.assert_allclose(orc.vertex_normals(V, F), V, atol=1e-15)
+    errs = []
+    for s in (2, 3, 4):
+        V, F = wi.icosphere(s)
+        N = orc.vertex_normals(V, F)
+        assert np.abs(np.linalg.norm(N, axis=1) - 1).max() < 1e-14
+        errs.append(np.abs(N - V).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-2
+
+
+def test_flip_duplicate_of_octahedron_is_a_shell(orc):
+    """Algorithm 2 on the closed octahedron: V' = (1 - eps) V exactly, so Sigma^-2 is the
+    octahedron minus a concentric one: W = 1 in the slab between them, 0 inside the
+    inner one and outside (the octahedron is |x|+|y|+|z| <= 1)."""
+    V, F = wi.octahedron_mesh(1.0)
+    eps = 0.1
+    V2, F2 = orc.flip_duplicate(V, F, eps)
+    np.testing.assert_allclose(V2[6:], (1 - eps) * V, atol=1e-15)
+    assert np.array_equal(F2[8:], F[:, [0, 2, 1]] + 6)
+    rng = np.random.default_rng(30)
+    Q = rng.uniform(-1.1, 1.1, size=(2000, 3))
+    l1 = np.abs(Q).sum(1)
+    sure = (np.abs(l1 - 1) > 1e-6) & (np.abs(l1 - (1 - eps)) > 1e-6)
+    expect = ((l1 < 1) & (l1 > 1 - eps)).astype(float)
+    W = orc.winding(V2, F2, Q)
+    np.testing.assert_allclose(W[sure], expect[sure], atol=1e-10)
+
+
+def test_flip_duplicate_closes_an_open_hemisphere(orc):
+    """An open hemisphere shell: alone it gives fractional W; after flipping duplication
+    W is ~1 inside the eps-thin slit under the shell and ~0 away from it (Algorithm 2)."""
+    V, F = wi.uv_ellipsoid(64, 32, semi_axes=(0.4, 0.4, 0.4))
+    cen = V[F].mean(1)
+    F = F[cen[:, 2] > 0]
+    V2, F2 = orc.flip_duplicate(V, F, 0.02)
+    # on the pole axis: inside the slit (radius 0.39), below it (0.3), above (0.45)
+    W = orc.winding(V2, F2, [[0, 0, 0.39], [0, 0, 0.3], [0, 0, 0.45], [0, 0, -0.2]])
+    assert W[0] == pytest.approx(1.0, abs=2e-2)
+    assert abs(W[1]) < 2e-2 and abs(W[2]) < 2e-2 and abs(W[3]) < 2e-2
+    Wopen = orc.winding(V, F, [[0, 0, 0.3]])
+    assert 0.1 < Wopen[0] < 0.9
