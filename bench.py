@@ -239,6 +239,18 @@ def bench_served(n_requests: int, load: float, pairs_per_s: float):
     }
 
 
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain device copy of known size (torch's copy kernel): its FETCH_SIZE and
+    WRITE_SIZE counter readings calibrate the counters' units for the traffic field."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}
+
+
 def cpu_baseline(c, budget_s: float = 15.0):
     """FP64 oracle on a deterministic stride subsample of the workload's voxels."""
     import numpy as np
@@ -283,7 +295,11 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="headline step only")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=48)
+    ap.add_argument("--served-requests", type=int, default=96)
+    ap.add_argument("--rows", default="adjoint,batched,served",
+                    help="comma list of extra rows to measure (adjoint, batched, served)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-load", type=float, default=0.8)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -297,6 +313,7 @@ def main():
         sys.exit(1)
     import paper_2407_11272_amd as wn
     wn.wn_version()
+    calib = copy_calibration() if args.copy_calibration else None
     print(f"# bench: forward, {args.steps} steps after {args.warmup} warm-up", file=sys.stderr, flush=True)
     c, pairs, dev_s, wall_s, fwd_extra = bench_forward(args.steps, args.warmup, not args.no_autotune)
     ms = dev_s / args.steps * 1e3
@@ -341,16 +358,21 @@ def main():
             "launch_ms": launch_s * 1e3,
         },
     }
-    if not args.no_rows:
+    want = set() if args.no_rows else {r.strip() for r in args.rows.split(",") if r.strip()}
+    rows = {}
+    if "adjoint" in want:
         print("# bench: adjoint row", file=sys.stderr, flush=True)
-        rows = {"adjoint": bench_adjoint(max(2, args.steps // 2), 1)}
+        rows["adjoint"] = bench_adjoint(max(2, args.steps // 2), 1)
+    if "batched" in want or "served" in want:
         print("# bench: batched row", file=sys.stderr, flush=True)
         rows["batched"] = bench_batched(3, not args.no_autotune)
-        if args.served_requests > 0:
-            print("# bench: served row", file=sys.stderr, flush=True)
-            rows["served"] = bench_served(args.served_requests, args.served_load,
-                                          rows["batched"]["batched_pairs_per_s"])
+    if "served" in want and args.served_requests > 0:
+        print("# bench: served row", file=sys.stderr, flush=True)
+        rows["served"] = bench_served(args.served_requests, args.served_load, rows["batched"]["batched_pairs_per_s"])
+    if rows:
         out["rows"] = rows
+    if calib:
+        out["copy_calibration"] = calib
     if not args.no_cpu_baseline:
         print("# bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)

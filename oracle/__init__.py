@@ -61,6 +61,14 @@ def _bind(lib):
     lib.wno_grid_points.argtypes = [_dp, _dp, _lp, _dp]
     lib.wno_max_threads.restype = ctypes.c_int
     lib.wno_max_threads.argtypes = []
+    lib.wno_winding_naive.restype = ctypes.c_int
+    lib.wno_winding_naive.argtypes = [_dp, ctypes.c_int64, _lp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp,
+                                      ctypes.c_int]
+    lib.wno_naive_term_grad.restype = None
+    lib.wno_naive_term_grad.argtypes = [_dp, _dp, _dp, _dp, _dp]
+    lib.wno_grad_naive.restype = ctypes.c_int
+    lib.wno_grad_naive.argtypes = [_dp, ctypes.c_int64, _lp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp,
+                                   ctypes.c_int]
     return lib
 
 
@@ -172,6 +180,43 @@ def grad(V, F, Q, dLdW, threads: int = 0):
     D = np.zeros((len(V), 3), dtype=np.float64)
     rc = _load().wno_grad(pv, len(V), pf, len(F), pq, len(Q), pg, T.ctypes.data_as(_dp), D.ctypes.data_as(_dp),
                           int(threads))
+    if rc != 0:
+        raise ValueError("oracle: face index out of range")
+    return T.reshape(-1, 3, 3), D
+
+
+def winding_naive(V, F, Q, threads: int = 0, with_scale: bool = False):
+    """Section 2.1, Eq. 4: one centroid sample per face, 1/(8 pi) sum <N, c - q>/|c - q|^3.
+    With ``with_scale`` also returns 1/(8 pi) sum |term| per point (the rounding scale)."""
+    V, pv = _d(np.asarray(V).reshape(-1, 3))
+    F, pf = _i(np.asarray(F).reshape(-1, 3))
+    Q, pq = _d(np.asarray(Q).reshape(-1, 3))
+    W = np.empty(len(Q))
+    S = np.empty(len(Q))
+    rc = _load().wno_winding_naive(pv, len(V), pf, len(F), pq, len(Q), W.ctypes.data_as(_dp), S.ctypes.data_as(_dp),
+                                   int(threads))
+    if rc != 0:
+        raise ValueError("oracle: face index out of range")
+    return (W, S) if with_scale else W
+
+
+def naive_term_grad(v0, v1, v2, q) -> np.ndarray:
+    out = np.zeros(9, dtype=np.float64)
+    args = [_d(x) for x in (v0, v1, v2, q)]
+    _load().wno_naive_term_grad(*(p for _, p in args), out.ctypes.data_as(_dp))
+    return out.reshape(3, 3)
+
+
+def grad_naive(V, F, Q, dLdW, threads: int = 0):
+    """(dL/dT [nF, 3, 3], dL/dV [nV, 3]) of the Eq. 4 sum for the given dL/dW."""
+    V, pv = _d(np.asarray(V).reshape(-1, 3))
+    F, pf = _i(np.asarray(F).reshape(-1, 3))
+    Q, pq = _d(np.asarray(Q).reshape(-1, 3))
+    g, pg = _d(np.asarray(dLdW).reshape(-1))
+    T = np.zeros((len(F), 9))
+    D = np.zeros((len(V), 3))
+    rc = _load().wno_grad_naive(pv, len(V), pf, len(F), pq, len(Q), pg, T.ctypes.data_as(_dp),
+                                D.ctypes.data_as(_dp), int(threads))
     if rc != 0:
         raise ValueError("oracle: face index out of range")
     return T.reshape(-1, 3, 3), D

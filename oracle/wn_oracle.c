@@ -248,6 +248,117 @@ int wno_grad(const double *V, int64_t nV, const int64_t *F, int64_t nF,
     return 0;
 }
 
+/* --------------------------------------------------- naive integral (Eq. 4) --- */
+
+/*
+ * Section 2.1, Eq. 4: the naive discretisation of the flux integral, one sample per
+ * face at its centroid c_i with the area-weighted normal n_i Delta_i = N_i / 2,
+ * N_i = (v1 - v0) x (v2 - v0):
+ *   W(q) ~= 1/(4 pi) sum_i <n_i, (c_i - q)/|c_i - q|^3> Delta_i
+ *        = 1/(8 pi) sum_i <N_i, c_i - q> / |c_i - q|^3.
+ * A face whose centroid coincides with q contributes 0 (reading: the sample is
+ * undefined there).  `S` (optional) receives 1/(8 pi) sum_i |term_i|, the scale of
+ * the rounding error of any evaluation of this sum.
+ */
+static double naive_term(const double *a, const double *b, const double *c, const double *q)
+{
+    double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double N[3], r[3];
+    cross3(e1, e2, N);
+    for (int d = 0; d < 3; ++d) r[d] = (a[d] + b[d] + c[d]) / 3.0 - q[d];
+    double r2 = dot3(r, r);
+    if (r2 == 0.0) return 0.0;
+    return dot3(N, r) / (r2 * sqrt(r2));
+}
+
+int wno_winding_naive(const double *V, int64_t nV, const int64_t *F, int64_t nF,
+                      const double *Q, int64_t nQ, double *W, double *S, int nthreads)
+{
+    for (int64_t f = 0; f < 3 * nF; ++f)
+        if (F[f] < 0 || F[f] >= nV) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nQ; ++i) {
+        nsum s = {0.0, 0.0}, sa = {0.0, 0.0};
+        for (int64_t f = 0; f < nF; ++f) {
+            double t = naive_term(V + 3 * F[3 * f], V + 3 * F[3 * f + 1], V + 3 * F[3 * f + 2], Q + 3 * i);
+            nsum_add(&s, t);
+            nsum_add(&sa, fabs(t));
+        }
+        W[i] = nsum_get(&s) / (8.0 * M_PI);
+        if (S) S[i] = nsum_get(&sa) / (8.0 * M_PI);
+    }
+    return 0;
+}
+
+/*
+ * Gradient of one naive term g = <N, r> / |r|^3 (r = c - q, c the centroid) with
+ * respect to v_j: dc/dv_j = I/3 and d<a, N>/dv_j = (v_{j+1} - v_{j+2}) x a, so
+ *   dg/dv_j = (N/|r|^3 - 3 <N, r> r/|r|^5) / 3 + (v_{j+1} - v_{j+2}) x r/|r|^3.
+ */
+void wno_naive_term_grad(const double *v0, const double *v1, const double *v2, const double *q, double *out)
+{
+    const double *v[3] = {v0, v1, v2};
+    double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+    double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    double N[3], r[3];
+    cross3(e1, e2, N);
+    for (int d = 0; d < 3; ++d) r[d] = (v0[d] + v1[d] + v2[d]) / 3.0 - q[d];
+    memset(out, 0, 9 * sizeof(double));
+    double r2 = dot3(r, r);
+    if (r2 == 0.0) return;
+    double ir3 = 1.0 / (r2 * sqrt(r2));
+    double nr = dot3(N, r);
+    double a[3];
+    for (int d = 0; d < 3; ++d) a[d] = r[d] * ir3;
+    for (int j = 0; j < 3; ++j) {
+        const double *p = v[(j + 1) % 3], *m = v[(j + 2) % 3];
+        double e[3] = {p[0] - m[0], p[1] - m[1], p[2] - m[2]}, x[3];
+        cross3(e, a, x);
+        for (int d = 0; d < 3; ++d) out[3 * j + d] = (N[d] * ir3 - 3.0 * nr * r[d] * ir3 / r2) / 3.0 + x[d];
+    }
+}
+
+/* Adjoint of wno_winding_naive: dLdT[f][j][c] = sum_i dLdW[i] dW_i/dv_{F[f][j]}[c] and
+ * its per-vertex gather (face order).  Either output may be NULL. */
+int wno_grad_naive(const double *V, int64_t nV, const int64_t *F, int64_t nF,
+                   const double *Q, int64_t nQ, const double *dLdW, double *dLdT, double *dLdV, int nthreads)
+{
+    for (int64_t f = 0; f < 3 * nF; ++f)
+        if (F[f] < 0 || F[f] >= nV) return -1;
+    set_threads(nthreads);
+    double *T = dLdT;
+    double *own = NULL;
+    if (!T) {
+        own = (double *)calloc((size_t)(nF > 0 ? nF : 1) * 9, sizeof(double));
+        if (!own) return -2;
+        T = own;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t f = 0; f < nF; ++f) {
+        nsum s[9];
+        for (int c = 0; c < 9; ++c) s[c].s = s[c].c = 0.0;
+        for (int64_t i = 0; i < nQ; ++i) {
+            double g[9];
+            wno_naive_term_grad(V + 3 * F[3 * f], V + 3 * F[3 * f + 1], V + 3 * F[3 * f + 2], Q + 3 * i, g);
+            for (int c = 0; c < 9; ++c) nsum_add(&s[c], dLdW[i] * g[c]);
+        }
+        for (int c = 0; c < 9; ++c) T[9 * f + c] = nsum_get(&s[c]) / (8.0 * M_PI);
+    }
+    if (dLdV) {
+        nsum *acc = (nsum *)calloc((size_t)(nV > 0 ? nV : 1) * 3, sizeof(nsum));
+        if (!acc) { free(own); return -2; }
+        for (int64_t f = 0; f < nF; ++f)
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 3; ++c) nsum_add(&acc[3 * F[3 * f + j] + c], T[9 * f + 3 * j + c]);
+        for (int64_t x = 0; x < 3 * nV; ++x) dLdV[x] = nsum_get(&acc[x]);
+        free(acc);
+    }
+    free(own);
+    return 0;
+}
+
 /* ------------------------------------------------------- guard-band distances */
 
 /* Distance from p to the segment [a, b] (a vertex when a == b). */

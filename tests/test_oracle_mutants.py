@@ -38,6 +38,14 @@ MUTANTS = [
     ("grad_gather_index", "nsum_add(&acc[3 * F[3 * f + j] + c]", "nsum_add(&acc[3 * F[3 * f] + c]"),
     ("grid_half_offset", "((double)ijk[d] + 0.5)", "((double)ijk[d])"),
     ("dist_plane", "return fabs(t) * sqrt(nn);", "return fabs(t) * nn;"),
+    ("naive_centroid", "r[d] = (a[d] + b[d] + c[d]) / 3.0 - q[d];", "r[d] = (a[d] + b[d] + c[d]) / 2.0 - q[d];"),
+    ("naive_power", "return dot3(N, r) / (r2 * sqrt(r2));", "return dot3(N, r) / r2;"),
+    ("naive_scale", "W[i] = nsum_get(&s) / (8.0 * M_PI);", "W[i] = nsum_get(&s) / (4.0 * M_PI);"),
+    ("naive_grad_third", "* ir3 / r2) / 3.0 + x[d];", "* ir3 / r2) + x[d];"),
+    ("naive_grad_three", "- 3.0 * nr * r[d] * ir3 / r2", "- 2.0 * nr * r[d] * ir3 / r2"),
+    ("naive_grad_cross", "cross3(e, a, x);", "cross3(a, e, x);"),
+    ("naive_grad_scale", "T[9 * f + c] = nsum_get(&s[c]) / (8.0 * M_PI);\n    }\n    if (dLdV) {\n        nsum *acc = (nsum *)calloc((size_t)(nV > 0 ? nV : 1) * 3, sizeof(nsum));\n        if (!acc) { free(own); return -2; }\n        for (int64_t f = 0; f < nF; ++f)\n            for (int j = 0; j < 3; ++j)\n                for (int c = 0; c < 3; ++c) nsum_add(&acc[3 * F[3 * f + j] + c], T[9 * f + 3 * j + c]);\n        for (int64_t x = 0; x < 3 * nV; ++x) dLdV[x] = nsum_get(&acc[x]);\n        free(acc);\n    }\n    free(own);\n    return 0;\n}\n\n/* ----",
+     "T[9 * f + c] = nsum_get(&s[c]) / (4.0 * M_PI);\n    }\n    if (dLdV) {\n        nsum *acc = (nsum *)calloc((size_t)(nV > 0 ? nV : 1) * 3, sizeof(nsum));\n        if (!acc) { free(own); return -2; }\n        for (int64_t f = 0; f < nF; ++f)\n            for (int j = 0; j < 3; ++j)\n                for (int c = 0; c < 3; ++c) nsum_add(&acc[3 * F[3 * f + j] + c], T[9 * f + 3 * j + c]);\n        for (int64_t x = 0; x < 3 * nV; ++x) dLdV[x] = nsum_get(&acc[x]);\n        free(acc);\n    }\n    free(own);\n    return 0;\n}\n\n/* ----"),
 ]
 
 PIN_TESTS = [fn for name, fn in inspect.getmembers(pins, inspect.isfunction)

@@ -492,3 +492,86 @@ def test_flip_duplicate_closes_an_open_hemisphere(orc):
     assert abs(W[1]) < 2e-2 and abs(W[2]) < 2e-2 and abs(W[3]) < 2e-2
     Wopen = orc.winding(V, F, [[0, 0, 0.3]])
     assert 0.1 < Wopen[0] < 0.9
+
+
+# ---------------------------------------------------- naive integral (Eq. 4)
+
+def test_naive_integral_far_field_is_the_solid_angle(orc):
+    """Eq. 4 far from a triangle: the centroid sample of the flux integral is the dipole
+    limit of the solid angle; the relative error falls like (size / distance)^2."""
+    rng = np.random.default_rng(40)
+    for _ in range(10):
+        v = rng.normal(size=(3, 3)) * 0.1
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        errs = []
+        for dist in (2.0, 4.0, 8.0):
+            q = v.mean(0) + dist * d
+            wn_ = orc.winding_naive(v, [[0, 1, 2]], [q])[0]
+            ex = orc.solid_angle(*v, q) / (4 * PI)
+            errs.append(abs(wn_ / ex - 1))
+        assert errs[2] < 1e-3
+        assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+
+
+def test_naive_integral_converges_under_refinement(orc):
+    """Eq. 4 is accurate for well-shaped meshes away from the surface (Section 2.1): on
+    icospheres of increasing subdivision the error against the exact W shrinks about
+    4x per level at interior and exterior points."""
+    Q = np.array([[0, 0, 0], [0.3, 0.2, -0.1], [0.0, 0.55, 0.1], [1.6, 0, 0], [0.7, 0.8, 0.6]])
+    errs = []
+    for s in (2, 3, 4):
+        V, F = wi.icosphere(s)
+        errs.append(np.abs(orc.winding_naive(V, F, Q) - orc.winding(V, F, Q)).max())
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0 and errs[2] < 2e-3
+
+
+def test_naive_integral_orientation_and_scale(orc):
+    """The sum is linear in the normals (reversal negates it) and invariant under a joint
+    scaling of mesh and points; a point at a centroid contributes 0 for that face."""
+    V, F = wi.icosphere(2)
+    rng = np.random.default_rng(41)
+    Q = rng.uniform(-1.2, 1.2, size=(50, 3))
+    W = orc.winding_naive(V, F, Q)
+    np.testing.assert_allclose(orc.winding_naive(V, wi.reverse_faces(F), Q), -W, atol=1e-12)
+    np.testing.assert_allclose(orc.winding_naive(3 * V, F, 3 * Q), W, atol=1e-12)
+    c = V[F[0]].mean(0)
+    single = orc.winding_naive(V, F[:1], [c])
+    assert single[0] == 0.0
+    W, S = orc.winding_naive(V, F, Q, with_scale=True)
+    assert np.all(S >= np.abs(W) - 1e-15)
+
+
+def test_naive_gradient_vs_finite_differences(orc):
+    """Analytic gradient of one Eq. 4 term and of the summed field against FP64 central
+    differences."""
+    rng = np.random.default_rng(42)
+    h = 1e-6
+    for _ in range(30):
+        v = rng.normal(size=(3, 3))
+        q = rng.normal(size=3) * 2
+        G = orc.naive_term_grad(*v, q)
+        fd = np.zeros((3, 3))
+        for j in range(3):
+            for c in range(3):
+                vp, vm = v.copy(), v.copy()
+                vp[j, c] += h
+                vm[j, c] -= h
+                fp = orc.winding_naive(vp, [[0, 1, 2]], [q])[0] * 8 * PI
+                fm = orc.winding_naive(vm, [[0, 1, 2]], [q])[0] * 8 * PI
+                fd[j, c] = (fp - fm) / (2 * h)
+        assert np.abs(G - fd).max() < 1e-6 * max(1.0, np.abs(fd).max())
+    V, F = wi.icosphere(1)
+    Q = rng.uniform(-1.0, 1.0, size=(20, 3))
+    g = rng.normal(size=20)
+    T, D = orc.grad_naive(V, F, Q, g)
+    fdV = np.zeros_like(V)
+    for i in range(len(V)):
+        for c in range(3):
+            Vp, Vm = V.copy(), V.copy()
+            Vp[i, c] += h
+            Vm[i, c] -= h
+            fdV[i, c] = (g @ orc.winding_naive(Vp, F, Q) - g @ orc.winding_naive(Vm, F, Q)) / (2 * h)
+    np.testing.assert_allclose(D, fdV, atol=1e-6 * np.abs(fdV).max())
+    # unlike the exact field, the naive field has non-zero vertex gradients on a closed mesh
+    assert np.abs(D).max() > 1e-3
