@@ -160,6 +160,32 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
                       const float *dLdW, float *dLdV, float *dLdT,
                       void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * The naive discretisation of the flux integral (Section 2.1, Eq. 4): one sample per
+ * face at its centroid c_f with the area-weighted normal N_f / 2,
+ * N_f = (v1 - v0) x (v2 - v0):
+ *     W(q) ~= 1/(8 pi) sum_f <N_f, c_f - q> / |c_f - q|^3,
+ * a face whose centroid coincides with q contributing 0.  It approximates W away from
+ * the surface and, unlike the exact field, has non-vanishing vertex gradients (the
+ * paper uses it for mesh morphing, Section 2.4).  Same arguments, outputs and
+ * workspace (wn_workspace_size(WN_OP_VOXELIZE, ...)) as wn_voxelize.
+ */
+WN_API wn_status wn_voxelize_naive(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                                   const wn_grid *grid, const float *Q, int64_t nQ,
+                                   float *W, int32_t occ_mode, float tau, float k, void *occ,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of wn_voxelize_naive: the same outputs as wn_backward (dLdV overwritten,
+ * optional per-corner dLdT) for the Eq. 4 sum, with
+ *   d term_f / d v_j = (N/|r|^3 - 3 <N, r> r/|r|^5) / 3 + (v_{j+1} - v_{j+2}) x r/|r|^3,
+ * r = c_f - q.  Workspace: wn_workspace_size(WN_OP_BACKWARD, ...).
+ */
+WN_API wn_status wn_backward_naive(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                                   const wn_grid *grid, const float *Q, int64_t nQ,
+                                   const float *dLdW, float *dLdV, float *dLdT,
+                                   void *ws, size_t ws_bytes, void *stream);
+
 /* One mesh of a batched forward launch (host struct; pointers are device memory).
  * The launch evaluates the voxel centres with flat indices
  * [point_begin, point_begin + point_count) of the grid (point_count = 0: to the end of

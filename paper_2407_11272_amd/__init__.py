@@ -15,6 +15,8 @@ from .api import (  # noqa: F401
     as_mesh,
     voxelize,
     wn_backward,
+    wn_backward_naive,
+    wn_voxelize_naive,
     wn_build_strips,
     wn_flip_duplicate,
     wn_voxelize_strips,
@@ -26,4 +28,11 @@ from .api import (  # noqa: F401
     wn_workspace_size,
 )
 from ._lib import WnError  # noqa: F401
-from .autograd import SigmoidOccupancy, WindingNumber, soft_occupancy, winding_number  # noqa: F401
+from .autograd import (  # noqa: F401
+    NaiveWindingNumber,
+    SigmoidOccupancy,
+    WindingNumber,
+    naive_winding_number,
+    soft_occupancy,
+    winding_number,
+)

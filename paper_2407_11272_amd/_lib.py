@@ -39,6 +39,8 @@ EXPORTED = (
     "wn_occupancy",
     "wn_sigmoid_mse",
     "wn_backward",
+    "wn_voxelize_naive",
+    "wn_backward_naive",
     "wn_voxelize_batched",
     "wn_workspace_size_batched",
     "wn_autotune",
@@ -106,6 +108,10 @@ def load():
     lib.wn_sigmoid_mse.argtypes = [vp, vp, i64, f32, f32, vp, vp, vp, sz, vp]
     lib.wn_backward.restype = i32
     lib.wn_backward.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, vp, vp, vp, sz, vp]
+    lib.wn_voxelize_naive.restype = i32
+    lib.wn_voxelize_naive.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i32, f32, f32, vp, vp, sz, vp]
+    lib.wn_backward_naive.restype = i32
+    lib.wn_backward_naive.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, vp, vp, vp, sz, vp]
     lib.wn_voxelize_batched.restype = i32
     lib.wn_voxelize_batched.argtypes = [ctypes.POINTER(WnMeshDesc), i32, i32, vp, sz, vp]
     lib.wn_workspace_size_batched.restype = sz

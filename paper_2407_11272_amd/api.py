@@ -102,7 +102,8 @@ def wn_workspace_size(op: int, nV: int, nF: int, nQ: int) -> int:
 
 
 def wn_voxelize(V, F, grid: Grid | None = None, Q: torch.Tensor | None = None, W: torch.Tensor | None = None,
-                occupancy: str | None = None, tau: float = 0.5, k: float = 50.0, occ: torch.Tensor | None = None):
+                occupancy: str | None = None, tau: float = 0.5, k: float = 50.0, occ: torch.Tensor | None = None,
+                _entry: str = "wn_voxelize"):
     """Winding number at the voxel centres of ``grid`` (or at the rows of ``Q``),
     plus the occupancy map when ``occupancy`` is 'threshold' or 'sigmoid'.
     Returns ``W`` or ``(W, occ)``; outputs may be passed in to avoid allocation."""
@@ -128,9 +129,9 @@ def wn_voxelize(V, F, grid: Grid | None = None, Q: torch.Tensor | None = None, W
         occ = torch.empty(shape, dtype=torch.uint8 if mode == L.WN_OCC_THRESHOLD else torch.float32, device=dev)
     need = wn_workspace_size(L.WN_OP_VOXELIZE, V.shape[0], F.shape[0], P)
     ws, wsb = Workspace.get(need, dev)
-    st = lib.wn_voxelize(_ptr(V), V.shape[0], _ptr(F), F.shape[0], gptr, qptr, nQ, _ptr(W), mode, tau, k,
-                         _ptr(occ if mode != L.WN_OCC_NONE else None), ws, wsb, _stream_handle(dev))
-    L.check("wn_voxelize", st)
+    st = getattr(lib, _entry)(_ptr(V), V.shape[0], _ptr(F), F.shape[0], gptr, qptr, nQ, _ptr(W), mode, tau, k,
+                              _ptr(occ if mode != L.WN_OCC_NONE else None), ws, wsb, _stream_handle(dev))
+    L.check(_entry, st)
     return W if mode == L.WN_OCC_NONE else (W, occ)
 
 
@@ -183,6 +184,16 @@ def wn_voxelize_strips(V, F, strips: torch.Tensor, grid: Grid | None = None, Q: 
     return W if mode == L.WN_OCC_NONE else (W, occ)
 
 
+def wn_voxelize_naive(V, F, grid: Grid | None = None, Q: torch.Tensor | None = None, **kw):
+    """The naive flux sum of Eq. 4 (centroid samples); arguments as :func:`wn_voxelize`."""
+    return wn_voxelize(V, F, grid=grid, Q=Q, _entry="wn_voxelize_naive", **kw)
+
+
+def wn_backward_naive(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None, **kw):
+    """Adjoint of :func:`wn_voxelize_naive`; arguments as :func:`wn_backward`."""
+    return wn_backward(V, F, dLdW, grid=grid, Q=Q, _entry="wn_backward_naive", **kw)
+
+
 def wn_occupancy(W: torch.Tensor, mode: str = "threshold", tau: float = 0.5, k: float = 50.0,
                  occ: torch.Tensor | None = None) -> torch.Tensor:
     m = _OCC_MODES[mode]
@@ -219,7 +230,8 @@ def wn_sigmoid_mse(W: torch.Tensor, target: torch.Tensor, tau: float = 0.5, k: f
 
 
 def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None,
-                want_dLdT: bool = False, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None):
+                want_dLdT: bool = False, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None,
+                _entry: str = "wn_backward"):
     """dL/dV [nV, 3] (and dL/dT [nF, 3, 3] if requested) for the given dL/dW."""
     lib = L.load()
     _check_mesh(V, F)
@@ -241,9 +253,9 @@ def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Ten
         dLdT = torch.empty((F.shape[0], 3, 3), dtype=torch.float32, device=dev)
     need = wn_workspace_size(L.WN_OP_BACKWARD, V.shape[0], F.shape[0], P)
     ws, wsb = Workspace.get(need, dev)
-    st = lib.wn_backward(_ptr(V), V.shape[0], _ptr(F), F.shape[0], gptr, qptr, nQ, _ptr(dLdW), _ptr(dLdV),
-                         _ptr(dLdT if want_dLdT else None), ws, wsb, _stream_handle(dev))
-    L.check("wn_backward", st)
+    st = getattr(lib, _entry)(_ptr(V), V.shape[0], _ptr(F), F.shape[0], gptr, qptr, nQ, _ptr(dLdW), _ptr(dLdV),
+                              _ptr(dLdT if want_dLdT else None), ws, wsb, _stream_handle(dev))
+    L.check(_entry, st)
     return (dLdV, dLdT) if want_dLdT else dLdV
 
 

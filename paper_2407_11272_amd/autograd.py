@@ -27,6 +27,23 @@ class WindingNumber(torch.autograd.Function):
         return dLdV, None, None, None
 
 
+class NaiveWindingNumber(torch.autograd.Function):
+    """The naive flux sum of Eq. 4 (centroid samples), differentiable in V; the surrogate
+    the paper uses for morphing because its vertex gradients do not vanish."""
+
+    @staticmethod
+    def forward(ctx, V, F, grid=None, Q=None):
+        ctx.save_for_backward(V, F, Q)
+        ctx.grid = grid
+        return api.wn_voxelize_naive(V, F, grid=grid, Q=Q)
+
+    @staticmethod
+    def backward(ctx, gW):
+        V, F, Q = ctx.saved_tensors
+        g = gW.contiguous().reshape(-1).to(torch.float32)
+        return api.wn_backward_naive(V, F, g, grid=ctx.grid, Q=Q), None, None, None
+
+
 class SigmoidOccupancy(torch.autograd.Function):
     """occ = sigmoid(k (W - tau)) on the device; backward k occ (1 - occ) g."""
 
@@ -45,6 +62,10 @@ class SigmoidOccupancy(torch.autograd.Function):
 
 def winding_number(V, F, grid=None, Q=None):
     return WindingNumber.apply(V, F, grid, Q)
+
+
+def naive_winding_number(V, F, grid=None, Q=None):
+    return NaiveWindingNumber.apply(V, F, grid, Q)
 
 
 def soft_occupancy(V, F, grid=None, Q=None, tau: float = 0.5, k: float = 50.0):

@@ -181,6 +181,43 @@ wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, 
                         ws_bytes, static_cast<hipStream_t>(stream));
 }
 
+wn_status wn_voxelize_naive(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                            const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
+                            void *ws, size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
+    const int64_t P = query_count(grid, Q, nQ);
+    if (P < 0) return WN_ERR_INVALID_ARG;
+    if (occ_mode != WN_OCC_NONE && occ_mode != WN_OCC_THRESHOLD && occ_mode != WN_OCC_SIGMOID)
+        return WN_ERR_INVALID_ARG;
+    if (P > 0 && W == nullptr) return WN_ERR_INVALID_ARG;
+    if (P > 0 && occ_mode != WN_OCC_NONE && occ == nullptr) return WN_ERR_INVALID_ARG;
+    if (grid)
+        for (int d = 0; d < 3; ++d)
+            if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < naive_fwd_workspace(nF, P)) return WN_ERR_WORKSPACE;
+    if (P == 0) return WN_OK;
+    OccParams op{occ, occ_mode, tau, k};
+    return hip_status(launch_naive_fwd(V, nV, F, nF, make_point_src(grid, Q), P, W, op, static_cast<char *>(ws),
+                                       lookup_config(WN_OP_VOXELIZE, nF, P).ppl, static_cast<hipStream_t>(stream)));
+}
+
+wn_status wn_backward_naive(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                            const float *Q, int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, void *ws,
+                            size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
+    const int64_t P = query_count(grid, Q, nQ);
+    if (P < 0) return WN_ERR_INVALID_ARG;
+    if (nV > 0 && dLdV == nullptr) return WN_ERR_INVALID_ARG;
+    if (P > 0 && nF > 0 && dLdW == nullptr) return WN_ERR_INVALID_ARG;
+    if (grid)
+        for (int d = 0; d < 3; ++d)
+            if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
+    const size_t need = bwd_workspace(nV, nF, P);
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
+    return run_backward(V, nV, F, nF, make_point_src(grid, Q), P, dLdW, dLdV, dLdT, static_cast<char *>(ws),
+                        ws_bytes, static_cast<hipStream_t>(stream), true);
+}
+
 wn_status wn_voxelize_batched(const wn_mesh_desc *desc, int32_t n, int32_t flags, void *ws, size_t ws_bytes,
                               void *stream) {
     if (n < 0 || (n > 0 && desc == nullptr)) return WN_ERR_INVALID_ARG;

@@ -107,16 +107,16 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
     }
 }
 
-// T[f][i] = sum over splits (fixed order) / (2 pi).
+// T[f][i] = sum over splits (fixed order) * scale (1/(2 pi) for the exact field).
 __global__ __launch_bounds__(kBlock) void k_bwd_reduce(const float *__restrict__ partials, int32_t split, int32_t nF,
-                                                       float *__restrict__ T) {
+                                                       float scale, float *__restrict__ T) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)nF * 9) return;
     const int32_t i = (int32_t)(t / nF);
     const int32_t f = (int32_t)(t - (int64_t)i * nF);
     float s = 0.0f, c = 0.0f;
     for (int32_t k = 0; k < split; ++k) neumaier_add(s, c, partials[((int64_t)k * 9 + i) * nF + f]);
-    T[(int64_t)f * 9 + i] = (s + c) * kInv2Pi;
+    T[(int64_t)f * 9 + i] = (s + c) * scale;
 }
 
 // Sort keys: the vertex of each corner (out-of-range ids read as 0, as in packing).
@@ -339,7 +339,8 @@ wn_status run_flip(const float *V, int64_t nV, const int32_t *F, int64_t nF, flo
 }
 
 wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps, int64_t nQ,
-                       const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes, hipStream_t s) {
+                       const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes, hipStream_t s,
+                       bool naive) {
     const BwdPlan p = plan_backward(nV, nF, nQ);
     if (ws_bytes < p.total) return WN_ERR_WORKSPACE;
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
@@ -363,10 +364,16 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
     e = launch_pack(V, nV, F, nF, soup, hdr, s);
     if (e != hipSuccess) return WN_ERR_HIP;
     if (nQ > 0) {
-        k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)p.split), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.chunkP,
-                                                                              dLdW, partials);
-        if ((e = hipGetLastError()) != hipSuccess) return WN_ERR_HIP;
-        k_bwd_reduce<<<blocks_for(9 * nF), kBlock, 0, s>>>(partials, p.split, (int32_t)nF, T);
+        if (naive) {
+            e = launch_naive_bwd(soup, (int32_t)nF, ps, nQ, p.chunkP, p.split, dLdW, partials, s);
+        } else {
+            k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)p.split), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.chunkP,
+                                                                                  dLdW, partials);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return WN_ERR_HIP;
+        k_bwd_reduce<<<blocks_for(9 * nF), kBlock, 0, s>>>(partials, p.split, (int32_t)nF, naive ? kInv8Pi : kInv2Pi,
+                                                            T);
     } else {
         k_fill_i32<<<blocks_for(9 * nF), kBlock, 0, s>>>(reinterpret_cast<int32_t *>(T), 9 * nF, 0);
     }

@@ -115,12 +115,12 @@ __global__ __launch_bounds__(kBlock) void k_wn_fwd(const VRec *__restrict__ recs
 
 // Fixed-order sum of the split partials, scale to W, occupancy.
 __global__ __launch_bounds__(kBlock) void k_wn_reduce(const float *__restrict__ partials, int32_t split,
-                                                      int64_t nQ, float *__restrict__ W, OccParams occ) {
+                                                      int64_t nQ, float scale, float *__restrict__ W, OccParams occ) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nQ) return;
     float s = 0.0f, c = 0.0f;
     for (int32_t k = 0; k < split; ++k) neumaier_add(s, c, partials[(int64_t)k * nQ + idx]);
-    const float w = (s + c) * kInv2Pi;
+    const float w = (s + c) * scale;
     W[idx] = w;
     write_occ(occ, idx, w);
 }
@@ -245,7 +245,14 @@ hipError_t launch_fwd(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t 
         e = launch_fwd_ppl<2>(recs, nR, ps, nQ, split, W, partials, occ, s);
     if (e != hipSuccess || split <= 1) return e;
     const int64_t rblocks = (nQ + kBlock - 1) / kBlock;
-    k_wn_reduce<<<dim3((unsigned)rblocks), kBlock, 0, s>>>(partials, split, nQ, W, occ);
+    k_wn_reduce<<<dim3((unsigned)rblocks), kBlock, 0, s>>>(partials, split, nQ, kInv2Pi, W, occ);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_reduce(const float *partials, int split, int64_t nQ, float scale, float *W,
+                               const OccParams &occ, hipStream_t s) {
+    const int64_t rblocks = (nQ + kBlock - 1) / kBlock;
+    k_wn_reduce<<<dim3((unsigned)rblocks), kBlock, 0, s>>>(partials, split, nQ, scale, W, occ);
     return hipGetLastError();
 }
 

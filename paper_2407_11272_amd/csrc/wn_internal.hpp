@@ -350,15 +350,28 @@ hipError_t launch_pack_records(const float *V, int64_t nV, const int32_t *F, int
 hipError_t launch_fwd(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t nQ, int split,
                       float *W, float *partials, const OccParams &occ, int ppl, hipStream_t s);
 hipError_t launch_occ(const float *W, int64_t n, const OccParams &occ, hipStream_t s);
+// Fixed-order sum of [split][nQ] partials times `scale` into W, plus occupancy.
+hipError_t launch_split_reduce(const float *partials, int split, int64_t nQ, float scale, float *W,
+                               const OccParams &occ, hipStream_t s);
 hipError_t launch_sigmoid_mse(const float *W, const float *target, int64_t n, float tau, float k,
                               float *loss, float *dLdW, float *scratch, hipStream_t s);
 int loss_blocks(int64_t n);
 
-// Backward pieces (wn_bwd.hip).
+// Backward pieces (wn_bwd.hip).  `naive` selects the adjoint of the Eq. 4 sum instead of
+// the exact solid-angle field.
 size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ);
 wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
                        int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes,
-                       hipStream_t s);
+                       hipStream_t s, bool naive = false);
+
+// Naive flux integral of Eq. 4 (wn_naive.hip).
+constexpr float kInv8Pi = 0.0397887357729738340f;
+hipError_t launch_naive_fwd(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
+                            int64_t nQ, float *W, const OccParams &occ, char *ws, int ppl, hipStream_t s);
+size_t naive_fwd_workspace(int64_t nF, int64_t nQ);
+// The adjoint pair kernel of Eq. 4 (defined in wn_naive.hip, launched by run_backward).
+hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int64_t chunkP,
+                            int split, const float *dLdW, float *partials, hipStream_t s);
 
 // Flipping duplication (wn_bwd.hip).
 size_t flip_workspace(int64_t nV, int64_t nF);
