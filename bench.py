@@ -239,6 +239,60 @@ def bench_served(n_requests: int, load: float, pairs_per_s: float):
     }
 
 
+def bench_naive(reps: int):
+    """Eq. 4 naive flux sum: forward on the 19 000-face union at 128^3, adjoint on the
+    5120-face icosphere at 64^3 (both with one centroid sample per face)."""
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    stream = torch.cuda.current_stream()
+    c2 = wi.config2_ellipsoid_union()
+    V, F = wn.as_mesh(torch.as_tensor(c2.V), torch.as_tensor(c2.F))
+    g2 = wn.Grid.of(c2.grid)
+    W = torch.empty(tuple(g2.n), dtype=torch.float32, device="cuda")
+    f_s, _ = time_steps(lambda: wn.wn_voxelize_naive(V, F, grid=g2, W=W), reps, 1, stream)
+    pairs_f = g2.size * len(c2.F)
+    c3 = wi.config3_differentiable()
+    V3, F3 = wn.as_mesh(torch.as_tensor(c3.V), torch.as_tensor(c3.F))
+    g3 = wn.Grid.of(c3.grid)
+    g = torch.randn(g3.size, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    dV = torch.empty_like(V3)
+    b_s, _ = time_steps(lambda: wn.wn_backward_naive(V3, F3, g, grid=g3, dLdV=dV), reps, 1, stream)
+    pairs_b = g3.size * len(c3.F)
+    return {
+        "forward_workload": "ellipsoid-union-19000f-128cube, one centroid sample per face",
+        "forward_ms": f_s / reps * 1e3,
+        "forward_pairs_per_s": pairs_f * reps / f_s,
+        "adjoint_workload": "icosphere-s4-5120f-64cube, random dL/dW",
+        "adjoint_ms": b_s / reps * 1e3,
+        "adjoint_pairs_per_s": pairs_b * reps / b_s,
+    }
+
+
+def bench_flip(reps: int):
+    """Algorithm 2 on the open 4864-face icosphere (5 % of faces removed), then the exact
+    forward of the duplicated 9728-face mesh at 128^3 in strip order."""
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    stream = torch.cuda.current_stream()
+    c = wi.config3_differentiable(res=128, open_variant=True)
+    V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    d_s, _ = time_steps(lambda: wn.wn_flip_duplicate(V, F, 0.01), reps, 1, stream)
+    V2, F2 = wn.wn_flip_duplicate(V, F, 0.01)
+    R = torch.as_tensor(wn.wn_build_strips(F2.cpu().numpy(), V2.shape[0])).cuda()
+    grid = wn.Grid.of(c.grid)
+    W = torch.empty(tuple(grid.n), dtype=torch.float32, device="cuda")
+    v_s, _ = time_steps(lambda: wn.wn_voxelize_strips(V2, F2, R, grid=grid, W=W), reps, 1, stream)
+    pairs = grid.size * F2.shape[0]
+    return {
+        "workload": "open icosphere s4 (4864 faces) -> flipped duplicate (9728 faces), 128^3",
+        "flip_ms": d_s / reps * 1e3,
+        "voxelize_ms": v_s / reps * 1e3,
+        "voxelize_pairs_per_s": pairs * reps / v_s,
+    }
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     """A plain device copy of known size (torch's copy kernel): its FETCH_SIZE and
     WRITE_SIZE counter readings calibrate the counters' units for the traffic field."""
@@ -296,8 +350,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--served-requests", type=int, default=96)
-    ap.add_argument("--rows", default="adjoint,batched,served",
-                    help="comma list of extra rows to measure (adjoint, batched, served)")
+    ap.add_argument("--rows", default="adjoint,batched,served,naive,flip",
+                    help="comma list of extra rows to measure (adjoint, batched, served, naive, flip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-load", type=float, default=0.8)
@@ -369,6 +423,12 @@ def main():
     if "served" in want and args.served_requests > 0:
         print("# bench: served row", file=sys.stderr, flush=True)
         rows["served"] = bench_served(args.served_requests, args.served_load, rows["batched"]["batched_pairs_per_s"])
+    if "naive" in want:
+        print("# bench: naive row", file=sys.stderr, flush=True)
+        rows["naive"] = bench_naive(3)
+    if "flip" in want:
+        print("# bench: flip row", file=sys.stderr, flush=True)
+        rows["flip"] = bench_flip(3)
     if rows:
         out["rows"] = rows
     if calib:
