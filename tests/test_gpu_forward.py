@@ -307,3 +307,29 @@ def test_bad_strip_records_are_reported(dev):
     W = wn.wn_voxelize_strips(Vt, Ft, torch.as_tensor(R).cuda(), grid=c.grid)
     assert wn.wn_get_device_error() == wn._lib.WN_ERR_BAD_INDEX
     assert torch.isfinite(W).all()
+
+
+def test_adversarial_points_on_vertices_and_edges(dev, orc):
+    """Query points exactly at mesh vertices (a face with q at its vertex contributes 0,
+    as in the oracle) and on edges (inside the guard band: any value, but finite), for
+    both record orders; far-from-surface points of the same call keep 1e-4 parity."""
+    import torch
+    import paper_2407_11272_amd as wn
+    rng = np.random.default_rng(77)
+    for seed in range(3):
+        V = np.round(rng.uniform(-0.5, 0.5, (12, 3)) * 64) / 64  # exactly representable
+        F = rng.permutation(12).reshape(4, 3)
+        mids = [(V[a] + V[b]) / 2 for a, b in ((F[0, 0], F[0, 1]), (F[2, 1], F[2, 2]))]
+        far = rng.uniform(-0.5, 0.5, (50, 3)).astype(np.float32).astype(np.float64)
+        Q = np.concatenate([V, np.array(mids), far])
+        Vt, Ft = wn.as_mesh(torch.as_tensor(V), torch.as_tensor(F))
+        Qt = torch.as_tensor(Q, dtype=torch.float32).cuda()
+        R = torch.as_tensor(wn.wn_build_strips(F, len(V))).cuda()
+        for W in (wn.wn_voxelize(Vt, Ft, Q=Qt), wn.wn_voxelize_strips(Vt, Ft, R, Q=Qt)):
+            Wn = W.cpu().numpy()
+            assert np.isfinite(Wn).all()
+            # each vertex belongs to exactly one face of this soup: that face gives 0
+            Wr = orc.winding(V, F, Q)
+            np.testing.assert_allclose(Wn[:12], Wr[:12], atol=1e-4)
+            guard = orc.guard_mask(V, F, far)
+            assert np.abs(Wn[14:] - Wr[14:])[~guard].max() <= 1e-4
