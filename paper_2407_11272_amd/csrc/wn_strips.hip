@@ -15,7 +15,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <unordered_map>
 #include <vector>
 
 #include "wn_internal.hpp"
@@ -29,31 +28,47 @@ constexpr int kMaxStrip = 1024;
 struct Builder {
     const int32_t *F;
     int64_t nF;
-    std::unordered_map<uint64_t, std::vector<int32_t>> edge_faces;
+    std::vector<int32_t> nbr;    // [3 nF]: face across edge (F[f][j], F[f][j+1]), or -1
     std::vector<uint8_t> done;   // face already placed in a strip
     std::vector<int32_t> stamp;  // face used by the current trial (value = trial id)
     int32_t trial = 0;
 
-    static uint64_t key(int32_t u, int32_t v) {
-        const uint32_t a = (uint32_t)(u < v ? u : v), b = (uint32_t)(u < v ? v : u);
-        return ((uint64_t)a << 32) | b;
-    }
-
+    // Edge adjacency from a sorted list of (undirected edge, corner): the faces on an
+    // edge are paired in corner order (a non-manifold edge pairs its first two faces,
+    // then the next two, ...), which keeps the order a pure function of F.
     void build_edges() {
-        edge_faces.reserve((size_t)nF * 2);
+        std::vector<std::pair<uint64_t, int64_t>> e;
+        e.reserve((size_t)nF * 3);
         for (int64_t f = 0; f < nF; ++f)
             for (int j = 0; j < 3; ++j) {
                 const int32_t u = F[3 * f + j], v = F[3 * f + (j + 1) % 3];
-                if (u != v) edge_faces[key(u, v)].push_back((int32_t)f);
+                if (u == v) continue;
+                const uint32_t a = (uint32_t)(u < v ? u : v), b = (uint32_t)(u < v ? v : u);
+                e.emplace_back(((uint64_t)a << 32) | b, 3 * f + j);
             }
+        std::sort(e.begin(), e.end());
+        nbr.assign((size_t)nF * 3, -1);
+        for (size_t i = 0; i + 1 < e.size();) {
+            if (e[i].first == e[i + 1].first) {
+                nbr[(size_t)e[i].second] = (int32_t)(e[i + 1].second / 3);
+                nbr[(size_t)e[i + 1].second] = (int32_t)(e[i].second / 3);
+                i += 2;
+            } else {
+                i += 1;
+            }
+        }
     }
 
-    // Unused face across edge (u, v) other than the ones already taken; -1 if none.
-    int32_t neighbour(int32_t u, int32_t v) const {
-        auto it = edge_faces.find(key(u, v));
-        if (it == edge_faces.end()) return -1;
-        for (int32_t g : it->second)
-            if (!done[(size_t)g] && stamp[(size_t)g] != trial) return g;
+    // Unused face across edge (u, v) of face g; -1 if none.
+    int32_t neighbour(int32_t g, int32_t u, int32_t v) const {
+        for (int j = 0; j < 3; ++j) {
+            const int32_t a = F[3 * (int64_t)g + j], b = F[3 * (int64_t)g + (j + 1) % 3];
+            if ((a == u && b == v) || (a == v && b == u)) {
+                const int32_t h = nbr[3 * (size_t)g + j];
+                if (h >= 0 && !done[(size_t)h] && stamp[(size_t)h] != trial) return h;
+                return -1;
+            }
+        }
         return -1;
     }
 
@@ -73,7 +88,7 @@ struct Builder {
     void extend(std::vector<int32_t> &seq, std::vector<int32_t> &faces) {
         while ((int)faces.size() < kMaxStrip) {
             const int32_t u = seq[seq.size() - 2], v = seq[seq.size() - 1];
-            const int32_t g = neighbour(u, v);
+            const int32_t g = neighbour(faces.back(), u, v);
             if (g < 0) return;
             const int32_t w = third(g, u, v);
             if (w < 0) return;
