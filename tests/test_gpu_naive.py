@@ -1,8 +1,10 @@
 """GPU parity of the naive flux integral (Eq. 4) and its adjoint against the FP64 oracle.
 
 The sum has no bounded condition number near the surface (terms grow like 1/|c - q|^2),
-so the forward tolerance is relative to the sum of absolute terms S(q) that the oracle
-returns: |W_gpu - W_ref| <= 1e-5 S + 2e-6.  Gradients: dL/dT elementwise 1e-3 relative
+so the forward tolerance follows the FP32 error model: arithmetic rounding relative to
+the sum of absolute terms S(q) that the oracle returns, plus the rounding of the inputs
+(voxel centres and centroids, about 6e-8 relative) amplified by 3/|c - q| per term:
+|W_gpu - W_ref| <= 1e-5 S + 5e-7 S2 + 2e-6 with S2 = 1/(8 pi) sum |term| / |c - q|.  Gradients: dL/dT elementwise 1e-3 relative
 where |ref| > 1e-2 |ref|_inf, and dL/dV (not vanishing here) to 1e-3 |ref|_inf.
 """
 import numpy as np
@@ -29,6 +31,21 @@ def _mesh(c):
     return wn.as_mesh(torch.as_tensor(np.asarray(c.V, np.float32)), torch.as_tensor(c.F))
 
 
+def _input_scale(V, F, Q):
+    """S2(q) = 1/(8 pi) sum_f |<N_f, c_f - q>| / |c_f - q|^4 (FP64, numpy)."""
+    V = np.asarray(V, np.float64)
+    a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    N = np.cross(b - a, c - a)
+    cen = (a + b + c) / 3.0
+    out = np.empty(len(Q))
+    for i0 in range(0, len(Q), 256):
+        r = cen[None, :, :] - Q[i0:i0 + 256, None, :]
+        d = np.linalg.norm(r, axis=-1)
+        t = np.abs(np.einsum("qfd,fd->qf", r, N)) / np.maximum(d, 1e-300) ** 4
+        out[i0:i0 + 256] = t.sum(1) / (8 * np.pi)
+    return out
+
+
 @pytest.mark.parametrize("cfg", ["c1", "c3", "c2"])
 def test_naive_forward_matches_oracle(dev, orc, cfg):
     import paper_2407_11272_amd as wn
@@ -37,10 +54,13 @@ def test_naive_forward_matches_oracle(dev, orc, cfg):
     W = wn.wn_voxelize_naive(Vt, Ft, grid=c.grid).cpu().numpy().reshape(-1)
     Q = orc.grid_points(c.grid)
     idx = np.random.default_rng(21).choice(len(Q), 2000, replace=False)
-    Wr, S = orc.winding_naive(np.asarray(c.V, np.float32).astype(np.float64), c.F, Q[idx], with_scale=True)
+    V64 = np.asarray(c.V, np.float32).astype(np.float64)
+    Wr, S = orc.winding_naive(V64, c.F, Q[idx], with_scale=True)
+    S2 = _input_scale(V64, c.F, Q[idx])
     err = np.abs(W[idx] - Wr)
-    print(f"[naive {cfg}] max|dW|={err.max():.2e} max rel to S={np.max(err / (S + 1e-30)):.2e}", flush=True)
-    assert np.all(err <= 1e-5 * S + 2e-6)
+    print(f"[naive {cfg}] max|dW|={err.max():.2e} max err/(1e-5 S + 5e-7 S2 + 2e-6)="
+          f"{np.max(err / (1e-5 * S + 5e-7 * S2 + 2e-6)):.2f}", flush=True)
+    assert np.all(err <= 1e-5 * S + 5e-7 * S2 + 2e-6)
 
 
 def test_naive_split_path(dev, orc):
@@ -51,8 +71,9 @@ def test_naive_split_path(dev, orc):
     Vt, Ft = _mesh(c)
     Q = np.random.default_rng(22).uniform(-0.5, 0.5, (257, 3)).astype(np.float32).astype(np.float64)
     W = wn.wn_voxelize_naive(Vt, Ft, Q=torch.as_tensor(Q, dtype=torch.float32).cuda()).cpu().numpy()
-    Wr, S = orc.winding_naive(np.asarray(c.V, np.float32).astype(np.float64), c.F, Q, with_scale=True)
-    assert np.all(np.abs(W - Wr) <= 1e-5 * S + 2e-6)
+    V64 = np.asarray(c.V, np.float32).astype(np.float64)
+    Wr, S = orc.winding_naive(V64, c.F, Q, with_scale=True)
+    assert np.all(np.abs(W - Wr) <= 1e-5 * S + 5e-7 * _input_scale(V64, c.F, Q) + 2e-6)
 
 
 def test_naive_adjoint_matches_oracle(dev, orc):
