@@ -77,7 +77,7 @@ def time_steps(fn, steps, warmup, stream):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
-def bench_forward(steps, warmup, autotune=True):
+def bench_forward(steps, warmup, autotune=True, compare=True):
     """Headline: the forward step with the mesh's triangle-strip record stream (built on
     the host from F before timing, like the mesh itself); also the same step with the
     default three records per face."""
@@ -105,14 +105,15 @@ def bench_forward(steps, warmup, autotune=True):
         wn.wn_voxelize(V, F, grid=grid, W=W, occupancy="threshold", occ=occ)
 
     dev_s, wall_s = time_steps(step, steps, warmup, stream)
-    plain_s, _ = time_steps(step_plain, max(2, steps // 2), 1, stream)
     pairs = grid.size * len(c.F)
     extra = {
         "strip_records_per_face": len(Rh) / len(c.F),
         "strip_build_ms_host": strip_ms,
-        "three_records_per_face_pairs_per_s": pairs * max(2, steps // 2) / plain_s,
         "autotune": tune["chosen"] if tune else None,
     }
+    if compare:
+        plain_s, _ = time_steps(step_plain, max(2, steps // 2), 1, stream)
+        extra["three_records_per_face_pairs_per_s"] = pairs * max(2, steps // 2) / plain_s
     return c, pairs, dev_s, wall_s, extra
 
 
@@ -294,13 +295,14 @@ def bench_flip(reps: int):
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
-    """A plain device copy of known size (torch's copy kernel): its FETCH_SIZE and
-    WRITE_SIZE counter readings calibrate the counters' units for the traffic field."""
+    """A streaming kernel of known size (torch's elementwise negation: reads nbytes,
+    writes nbytes): its FETCH_SIZE and WRITE_SIZE counter readings calibrate the
+    counters' units for the traffic field."""
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(reps):
-        dst.copy_(src)
+        torch.neg(src, out=dst)
     torch.cuda.synchronize()
     return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}
 
@@ -355,6 +357,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-load", type=float, default=0.8)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the three-records-per-face comparison launches (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -369,7 +373,8 @@ def main():
     wn.wn_version()
     calib = copy_calibration() if args.copy_calibration else None
     print(f"# bench: forward, {args.steps} steps after {args.warmup} warm-up", file=sys.stderr, flush=True)
-    c, pairs, dev_s, wall_s, fwd_extra = bench_forward(args.steps, args.warmup, not args.no_autotune)
+    c, pairs, dev_s, wall_s, fwd_extra = bench_forward(args.steps, args.warmup, not args.no_autotune,
+                                                       not args.no_compare)
     ms = dev_s / args.steps * 1e3
     value = pairs * args.steps / dev_s
     launch_s = dev_s / args.steps

@@ -79,7 +79,7 @@ void save_locked() {
 
 bool valid_ppl(int32_t ppl) { return ppl == 1 || ppl == 2 || ppl == 4; }
 
-TuneConfig default_config(int32_t) { return TuneConfig{2, 0}; }
+TuneConfig default_config(int32_t) { return TuneConfig{1, 0}; }
 
 TuneConfig lookup_config(int32_t op, int64_t a, int64_t b) {
     std::lock_guard<std::mutex> lk(g_mu);
