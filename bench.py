@@ -191,9 +191,11 @@ def bench_batched(reps: int, autotune: bool):
     }
 
 
-def bench_served(n_requests: int, load: float, pairs_per_s: float):
+def bench_served(n_requests: int, load: float, fwd_pairs_per_s: float, adj_pairs_per_s: float):
     """Poisson trace through the continuous-batching server and through the plain FIFO
-    one-mesh-per-launch loop; p50/p99 latency and throughput of both."""
+    one-mesh-per-launch loop; p50/p99 latency and throughput of both.  The arrival rate
+    puts the offered GPU time at ``load`` of the wall clock, with a request's GPU time
+    estimated from the measured batched forward and adjoint pair rates."""
     import numpy as np
     import torch
     import paper_2407_11272_amd as wn
@@ -202,7 +204,10 @@ def bench_served(n_requests: int, load: float, pairs_per_s: float):
                                             run_plain_fifo)
     base = wi.config5_trace(n_requests, 1.0)
     mean_pairs = float(np.mean([r.faces * r.res ** 3 * (2 if r.wants_grad else 1) for r in base]))
-    rate = load * pairs_per_s / mean_pairs
+    mean_gpu_s = float(np.mean([r.faces * r.res ** 3 * (1.0 / fwd_pairs_per_s
+                                                        + (1.0 / adj_pairs_per_s if r.wants_grad else 0.0))
+                                for r in base]))
+    rate = load / mean_gpu_s
     trace = wi.config5_trace(n_requests, rate)
     reqs = []
     for r in trace:
@@ -233,6 +238,7 @@ def bench_served(n_requests: int, load: float, pairs_per_s: float):
         "rate_req_per_s": rate,
         "load": load,
         "mean_pairs_per_request": mean_pairs,
+        "mean_gpu_ms_per_request": mean_gpu_s * 1e3,
         "served": s_stats,
         "plain_fifo": p_stats,
         "p50_speedup": p_stats["p50_ms"] / s_stats["p50_ms"],
@@ -419,7 +425,7 @@ def main():
     }
     want = set() if args.no_rows else {r.strip() for r in args.rows.split(",") if r.strip()}
     rows = {}
-    if "adjoint" in want:
+    if "adjoint" in want or "served" in want:
         print("# bench: adjoint row", file=sys.stderr, flush=True)
         rows["adjoint"] = bench_adjoint(max(2, args.steps // 2), 1)
     if "batched" in want or "served" in want:
@@ -427,7 +433,8 @@ def main():
         rows["batched"] = bench_batched(3, not args.no_autotune)
     if "served" in want and args.served_requests > 0:
         print("# bench: served row", file=sys.stderr, flush=True)
-        rows["served"] = bench_served(args.served_requests, args.served_load, rows["batched"]["batched_pairs_per_s"])
+        rows["served"] = bench_served(args.served_requests, args.served_load, rows["batched"]["batched_pairs_per_s"],
+                                      rows["adjoint"]["adjoint_pairs_per_s"])
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
         rows["naive"] = bench_naive(3)
