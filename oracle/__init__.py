@@ -11,7 +11,9 @@ Paper sections followed (arXiv 2407.11272):
   * Section 2.2, Eq. 7 with the half-angle factor 2, and Eq. 8 (ATAN2 cases);
   * Algorithm 1 (per-face normalise, alpha, beta, ATAN2, accumulate);
   * Section 2.1, Eq. 3: for a closed surface W is the occupancy; the map to a hard
-    or soft occupancy uses a threshold or a sigmoid around 0.5.
+    or soft occupancy uses a threshold or a sigmoid around 0.5;
+  * Section 2.4 (mesh morphing): the voxel loss drives the vertices through Adam
+    (Kingma and Ba, 2015, Algorithm 1), written out in numpy FP64.
 """
 from __future__ import annotations
 
@@ -298,3 +300,39 @@ def sigmoid_mse(W, target, tau: float = 0.5, k: float = 50.0):
     L = float(np.sum((s - t) ** 2) / n)
     dLdW = 2.0 * (s - t) / n * k * s * (1.0 - s)
     return L, dLdW
+
+
+def adam(x, g, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step (Kingma and Ba, 2015, Algorithm 1), FP64: the moment estimates
+    m, v are exponential averages of g and g^2, divided by (1 - beta^t) to remove
+    their bias towards the zero start, and x moves by lr m_hat / (sqrt(v_hat) + eps).
+    Returns the new (x, m, v)."""
+    x, g, m, v = (np.asarray(a, dtype=np.float64) for a in (x, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return x - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def morph(V, F, grid, target, iters: int, integral: str = "naive", tau: float = 0.5, k: float = 50.0,
+          lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, t0: int = 0,
+          m=None, v=None, threads: int = 0):
+    """Mesh morphing by voxel supervision (Section 2.4): repeat {W at the voxel centres
+    (Eq. 4 naive sum, or Eq. 5/7), the soft-occupancy MSE against the target, its
+    gradient with respect to the vertices, one Adam step}.  FP64 throughout.
+    Returns (V, m, v, losses) with losses[i] evaluated before update i."""
+    V = np.array(V, dtype=np.float64)
+    m = np.zeros_like(V) if m is None else np.array(m, dtype=np.float64)
+    v = np.zeros_like(V) if v is None else np.array(v, dtype=np.float64)
+    Q = grid_points(grid)
+    fwd = winding_naive if integral == "naive" else winding
+    bwd = grad_naive if integral == "naive" else grad
+    losses = []
+    for i in range(iters):
+        W = fwd(V, F, Q, threads=threads)
+        L, dLdW = sigmoid_mse(W, target, tau, k)
+        _, dLdV = bwd(V, F, Q, dLdW, threads=threads)
+        V, m, v = adam(V, dLdV, m, v, t0 + 1 + i, lr, beta1, beta2, eps)
+        losses.append(L)
+    return V, m, v, np.array(losses)

@@ -81,3 +81,45 @@ def test_every_mutant_is_caught(tmp_path, orc, name, old, new):
             except Exception:  # an assertion, or a numerical error a pin provokes
                 failed.append(fn.__name__)
     assert failed, f"mutant {name} passed every pin"
+
+
+# Mistakes planted in the numpy parts of the oracle (Adam and the morphing loop): the
+# function's source is edited and re-executed in the oracle module's namespace.
+PY_MUTANTS = [
+    ("adam", "adam_no_bias_correction", "m_hat = m / (1.0 - beta1 ** t)", "m_hat = m"),
+    ("adam", "adam_v_no_bias_correction", "v_hat = v / (1.0 - beta2 ** t)", "v_hat = v"),
+    ("adam", "adam_bias_power", "m_hat = m / (1.0 - beta1 ** t)", "m_hat = m / (1.0 - beta1 ** (t + 1))"),
+    ("adam", "adam_eps_under_root", "np.sqrt(v_hat) + eps", "np.sqrt(v_hat + eps)"),
+    ("adam", "adam_v_linear", "(1.0 - beta2) * g * g", "(1.0 - beta2) * np.abs(g)"),
+    ("adam", "adam_m_weights", "beta1 * m + (1.0 - beta1) * g", "(1.0 - beta1) * m + beta1 * g"),
+    ("adam", "adam_ascent", "return x - lr", "return x + lr"),
+    ("morph", "morph_no_chain_rule", "_, dLdV = bwd(V, F, Q, dLdW, threads=threads)",
+     "_, dLdV = bwd(V, F, Q, np.ones_like(dLdW), threads=threads)"),
+    ("morph", "morph_step_number", "t0 + 1 + i", "t0 + i + 2"),
+    ("morph", "morph_loss_after_update", "        V, m, v = adam(V, dLdV, m, v, t0 + 1 + i, lr, beta1, beta2, eps)\n        losses.append(L)",
+     "        V, m, v = adam(V, dLdV, m, v, t0 + 1 + i, lr, beta1, beta2, eps)\n        losses.append(sigmoid_mse(fwd(V, F, Q, threads=threads), target, tau, k)[0])"),
+]
+
+PY_PIN_TESTS = [fn for fn in PIN_TESTS if "adam" in fn.__name__ or "morph" in fn.__name__]
+
+
+@pytest.mark.parametrize("func,name,old,new", PY_MUTANTS, ids=[m[1] for m in PY_MUTANTS])
+def test_every_python_mutant_is_caught(monkeypatch, orc, func, name, old, new):
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(getattr(oracle, func)))
+    assert src.count(old) >= 1, f"mutant {name}: pattern not found"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new, 1), f"<{name}>", "exec"), ns)
+    monkeypatch.setattr(oracle, func, ns[func])
+    failed = []
+    for fn in PY_PIN_TESTS:
+        params = inspect.signature(fn).parameters
+        try:
+            if "integral" in params:
+                for integral in ("naive", "gwn"):
+                    fn(oracle, integral)
+            else:
+                fn(oracle)
+        except Exception:
+            failed.append(fn.__name__)
+    assert failed, f"mutant {name} passed every pin"

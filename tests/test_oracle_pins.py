@@ -575,3 +575,105 @@ def test_naive_gradient_vs_finite_differences(orc):
     np.testing.assert_allclose(D, fdV, atol=1e-6 * np.abs(fdV).max())
     # unlike the exact field, the naive field has non-zero vertex gradients on a closed mesh
     assert np.abs(D).max() > 1e-3
+
+
+# ------------------------------------------------ morphing loop (Section 2.4)
+
+def test_adam_first_and_constant_gradient_steps(orc):
+    """Adam's bias correction makes the first step, and every step under a constant
+    gradient, exactly lr g / (|g| + eps) (m_hat = g, v_hat = g^2 at every t)."""
+    rng = np.random.default_rng(31)
+    g = rng.normal(size=50) * 10.0 ** rng.uniform(-3, 3, size=50)
+    x = rng.normal(size=50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    lr, eps = 0.01, 1e-8
+    for t in range(1, 8):
+        x2, m, v = orc.adam(x, g, m, v, t, lr, 0.9, 0.999, eps)
+        np.testing.assert_allclose(x - x2, lr * g / (np.abs(g) + eps), rtol=1e-9, atol=1e-15)
+        x = x2
+
+
+def test_adam_alternating_gradient_closed_form(orc):
+    """g = +1 then -1 from a zero state: m_hat_2 = -(1 - b1)/(1 + b1) and v_hat_2 = 1,
+    so the second step moves x by +lr (1 - b1) / ((1 + b1)(1 + eps))."""
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.9), (0.0, 0.99)):
+        x1, m, v = orc.adam([0.0], [1.0], [0.0], [0.0], 1, 0.1, b1, b2, 1e-3)
+        x2, _, _ = orc.adam(x1, [-1.0], m, v, 2, 0.1, b1, b2, 1e-3)
+        assert abs((x2[0] - x1[0]) - 0.1 * (1 - b1) / ((1 + b1) * (1 + 1e-3))) < 1e-12
+
+
+def test_adam_eps_outside_the_root(orc):
+    """eps is added to sqrt(v_hat), not under it: for |g| << eps the step is lr g / eps."""
+    x, _, _ = orc.adam([0.0], [1e-12], [0.0], [0.0], 1, 1.0, 0.9, 0.999, 1e-6)
+    assert abs(-x[0] - 1e-12 / (1e-12 + 1e-6)) < 1e-15
+
+
+def test_adam_minimises_a_quadratic(orc):
+    """On f(x) = sum a_i x_i^2, Adam with a decaying step reaches the minimum."""
+    rng = np.random.default_rng(32)
+    a = 10.0 ** rng.uniform(-2, 2, size=20)
+    x = rng.normal(size=20)
+    m = np.zeros(20)
+    v = np.zeros(20)
+    for t in range(1, 3001):
+        x, m, v = orc.adam(x, 2 * a * x, m, v, t, 0.1 / math.sqrt(t))
+    assert np.abs(x).max() < 1e-2
+
+
+def _recover_gradient(dx, lr, eps):
+    """Invert the first Adam step with beta1 = beta2 = 0 (m_hat = g, v_hat = g^2):
+    dx = -lr g / (|g| + eps)  =>  g = -eps (dx/lr) / (1 - |dx/lr|)."""
+    u = dx / lr
+    return -eps * u / (1.0 - np.abs(u))
+
+
+@pytest.mark.parametrize("integral", ["naive", "gwn"])
+def test_morph_step_follows_the_loss_gradient(orc, integral):
+    """One morphing iteration moves the vertices by Adam's step on dL/dV, where L is the
+    soft-occupancy MSE of the voxelized mesh: the gradient recovered from the step agrees
+    with central differences of L.  The exact (GWN) field needs an open mesh: on a closed
+    mesh its vertex gradient vanishes (the paper's reason to morph with Eq. 4)."""
+    V, F = wi.octahedron_mesh(1.0)
+    V = V + np.random.default_rng(33).normal(scale=0.05, size=V.shape)
+    if integral == "gwn":
+        F = F[1:]
+    grid = wi.Grid.cube(6, -1.6, 1.6)
+    Q = orc.grid_points(grid)
+    target = (np.linalg.norm(Q, axis=1) < 0.8).astype(np.float64)
+    k, lr, eps = 4.0, 1e-3, 1.0
+    fwd = orc.winding_naive if integral == "naive" else orc.winding
+    V1, _, _, losses = orc.morph(V, F, grid, target, 1, integral=integral, k=k, lr=lr, beta1=0.0, beta2=0.0, eps=eps)
+    L0, _ = orc.sigmoid_mse(fwd(V, F, Q), target, 0.5, k)
+    assert abs(losses[0] - L0) < 1e-15
+    g = _recover_gradient(V1 - V, lr, eps)
+    h = 1e-6
+    fd = np.zeros_like(V)
+    for i in range(len(V)):
+        for c in range(3):
+            Vp, Vm = V.copy(), V.copy()
+            Vp[i, c] += h
+            Vm[i, c] -= h
+            fd[i, c] = (orc.sigmoid_mse(fwd(Vp, F, Q), target, 0.5, k)[0]
+                        - orc.sigmoid_mse(fwd(Vm, F, Q), target, 0.5, k)[0]) / (2 * h)
+    assert np.abs(fd).max() > 1e-4
+    np.testing.assert_allclose(g, fd, atol=1e-6 * np.abs(fd).max() + 1e-9)
+
+
+def test_morph_first_step_is_a_sign_step(orc):
+    """From zero moments, the first iteration is Adam step t = 1: with the default betas
+    every coordinate whose gradient exceeds eps moves by lr (m_hat = g, v_hat = g^2)."""
+    V, F = wi.octahedron_mesh(1.0)
+    V = V + np.random.default_rng(34).normal(scale=0.05, size=V.shape)
+    grid = wi.Grid.cube(6, -1.6, 1.6)
+    target = (np.linalg.norm(orc.grid_points(grid), axis=1) < 0.8).astype(np.float64)
+    V1, _, _, _ = orc.morph(V, F, grid, target, 1, integral="naive", k=4.0, lr=1e-3, eps=1e-14)
+    np.testing.assert_allclose(np.abs(V1 - V), 1e-3, rtol=1e-6)
+
+
+def test_morph_lowers_the_loss(orc):
+    """Small steps along the naive-integral gradient lower the voxel loss: a sphere
+    morphing towards an ellipsoid target."""
+    c = wi.config3_differentiable(res=12)
+    _, _, _, losses = orc.morph(c.V, c.F, c.grid, c.target, 6, integral="naive", lr=2e-3)
+    assert np.all(np.diff(losses) < 0)
