@@ -300,6 +300,29 @@ def bench_flip(reps: int):
     }
 
 
+def bench_morph(iters: int):
+    """Mesh morphing (Section 2.4) on the 5120-face icosphere towards the ellipsoid target
+    at 64^3: one wn_morph_step call enqueues ``iters`` iterations (forward, loss, adjoint,
+    Adam), with the naive integral the paper morphs with and with the exact field."""
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    stream = torch.cuda.current_stream()
+    c = wi.config3_differentiable()
+    out = {"workload": f"icosphere-s4-5120f -> ellipsoid target, 64^3, sigmoid(k=50) MSE, Adam lr 2e-3, "
+                       f"{iters} iterations per call"}
+    pairs = c.grid.size * len(c.F) * 2
+    for integral in ("naive", "gwn"):
+        mo = wn.Morpher(c.V, c.F, c.target.reshape(-1), c.grid, integral=integral, tau=c.tau, k=c.k, lr=2e-3)
+        losses = []
+        dt, _ = time_steps(lambda: losses.append(mo.run(iters)), 1, 1, stream)
+        L = losses[-1].cpu().numpy()
+        out[integral] = {"iter_ms": dt / iters * 1e3, "iters_per_s": iters / dt,
+                         "pairs_per_s": pairs * iters / dt,
+                         "loss_first": float(L[0]), "loss_last": float(L[-1])}
+    return out
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     """A streaming kernel of known size (torch's elementwise negation: reads nbytes,
     writes nbytes): its FETCH_SIZE and WRITE_SIZE counter readings calibrate the
@@ -358,8 +381,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--served-requests", type=int, default=96)
-    ap.add_argument("--rows", default="adjoint,batched,served,naive,flip",
-                    help="comma list of extra rows to measure (adjoint, batched, served, naive, flip)")
+    ap.add_argument("--rows", default="adjoint,batched,served,naive,flip,morph",
+                    help="comma list of extra rows to measure (adjoint, batched, served, naive, flip, morph)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-load", type=float, default=0.8)
@@ -438,6 +461,9 @@ def main():
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
         rows["naive"] = bench_naive(3)
+    if "morph" in want:
+        print("# bench: morph row", file=sys.stderr, flush=True)
+        rows["morph"] = bench_morph(20)
     if "flip" in want:
         print("# bench: flip row", file=sys.stderr, flush=True)
         rows["flip"] = bench_flip(3)

@@ -78,6 +78,11 @@ typedef int32_t wn_status;
 #define WN_OP_BATCHED 2
 #define WN_OP_LOSS 3
 #define WN_OP_FLIP 4
+#define WN_OP_MORPH 5
+
+/* Which integral drives a morphing iteration (wn_morph_step). */
+#define WN_INTEGRAL_GWN 0   /* Eq. 5 with Eq. 7 solid angles (wn_voxelize / wn_backward)      */
+#define WN_INTEGRAL_NAIVE 1 /* Eq. 4 centroid samples (wn_voxelize_naive / wn_backward_naive) */
 
 /* Axis-aligned voxel grid: n[d] cells spanning [lo[d], hi[d]]. */
 typedef struct {
@@ -87,8 +92,8 @@ typedef struct {
 } wn_grid;
 
 /* Bytes of device workspace an operation needs (WN_OP_VOXELIZE, WN_OP_BACKWARD,
- * WN_OP_LOSS, WN_OP_FLIP; a batched launch uses wn_workspace_size_batched).  Returns 0 for an
- * unknown op or negative sizes. */
+ * WN_OP_LOSS, WN_OP_FLIP, WN_OP_MORPH; a batched launch uses wn_workspace_size_batched).
+ * Returns 0 for an unknown op or negative sizes. */
 WN_API size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ);
 
 /*
@@ -254,6 +259,38 @@ WN_API wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, vo
  */
 WN_API wn_status wn_flip_duplicate(const float *V, int64_t nV, const int32_t *F, int64_t nF, float eps,
                                    float *V2, int32_t *F2, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adam (Kingma and Ba, 2015, Algorithm 1) on n parameters in place, for step number t >= 1:
+ *   m = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2,
+ *   x -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ * x, m, v (float [n], updated) and g (float [n]) are device arrays; m and v start at 0
+ * for t = 1.  The bias corrections are formed in FP64 on the host.  Needs
+ * 0 <= beta1, beta2 < 1, eps > 0, lr finite; n = 0 is a no-op.  The optimiser of the
+ * mesh-morphing loop (Section 2.4 deforms a mesh by gradients of a voxel loss).
+ */
+WN_API wn_status wn_adam(float *x, const float *g, float *m, float *v, int64_t n, int64_t t, float lr,
+                         float beta1, float beta2, float eps, void *stream);
+
+/*
+ * Mesh morphing by voxel supervision (Section 2.4): `iters` iterations, each
+ *   W = winding numbers of (V, F) at the voxel centres of `grid`
+ *       (integral = WN_INTEGRAL_NAIVE: the Eq. 4 sum the paper uses for morphing, whose
+ *        gradient does not vanish; WN_INTEGRAL_GWN: Eq. 5 and 7),
+ *   L = (1/P) sum_q (sigmoid(k (W_q - tau)) - target_q)^2 and dL/dW (wn_sigmoid_mse),
+ *   dL/dV by the adjoint of the chosen integral,
+ *   Adam (wn_adam) on V in place, step numbers t0 + 1, ..., t0 + iters.
+ * V (float [nV][3]) is updated in place; F (int32 [nF][3]) and target (float [P], P =
+ * grid cells, C order) are read; m and v (float [nV][3]) are the Adam moments, zero
+ * before the first step.  loss_history (optional, device float [iters]) receives L of
+ * each iteration, evaluated before its update.  Everything stays on the device; the call
+ * only enqueues work on `stream`.  Workspace: wn_workspace_size(WN_OP_MORPH, nV, nF, P).
+ * Face indices out of range are replaced and recorded as in wn_voxelize.
+ */
+WN_API wn_status wn_morph_step(float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                               const float *target, int32_t integral, float tau, float k, float lr,
+                               float beta1, float beta2, float eps, int64_t t0, int32_t iters, float *m,
+                               float *v, float *loss_history, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Reads and clears the device-side error record that the most recent call using

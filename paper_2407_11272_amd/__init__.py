@@ -8,6 +8,9 @@ not been built (there is no CPU fallback).
 from .api import (  # noqa: F401
     Grid,
     MeshJob,
+    Morpher,
+    wn_adam,
+    wn_morph_step,
     wn_autotune,
     wn_voxelize_batched,
     wn_workspace_size_batched,

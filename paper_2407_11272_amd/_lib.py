@@ -27,6 +27,10 @@ WN_OP_BACKWARD = 1
 WN_OP_BATCHED = 2
 WN_OP_LOSS = 3
 WN_OP_FLIP = 4
+WN_OP_MORPH = 5
+
+WN_INTEGRAL_GWN = 0
+WN_INTEGRAL_NAIVE = 1
 
 WN_BATCH_NO_GRAPH = 1
 
@@ -45,6 +49,8 @@ EXPORTED = (
     "wn_workspace_size_batched",
     "wn_autotune",
     "wn_flip_duplicate",
+    "wn_adam",
+    "wn_morph_step",
     "wn_get_device_error",
     "wn_status_string",
     "wn_version",
@@ -120,6 +126,11 @@ def load():
     lib.wn_autotune.argtypes = [i32, ctypes.POINTER(WnMeshDesc), i32, vp, sz, vp, ctypes.c_char_p, sz]
     lib.wn_flip_duplicate.restype = i32
     lib.wn_flip_duplicate.argtypes = [vp, i64, vp, i64, f32, vp, vp, vp, sz, vp]
+    lib.wn_adam.restype = i32
+    lib.wn_adam.argtypes = [vp, vp, vp, vp, i64, i64, f32, f32, f32, f32, vp]
+    lib.wn_morph_step.restype = i32
+    lib.wn_morph_step.argtypes = [vp, i64, vp, i64, gp, vp, i32, f32, f32, f32, f32, f32, f32, i64, i32, vp, vp,
+                                  vp, vp, sz, vp]
     lib.wn_get_device_error.restype = i32
     lib.wn_get_device_error.argtypes = [vp, vp]
     lib.wn_status_string.restype = ctypes.c_char_p

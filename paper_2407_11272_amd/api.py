@@ -274,6 +274,76 @@ def wn_flip_duplicate(V, F, eps: float = 0.01):
     return V2, F2
 
 
+def _check_f32(name, t, n=None):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements")
+
+
+def wn_adam(x: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, t: int, lr: float = 1e-3,
+            betas=(0.9, 0.999), eps: float = 1e-8) -> None:
+    """Adam step number ``t`` (>= 1) on x in place, with moments m, v (updated)."""
+    n = x.numel()
+    for name, a in (("x", x), ("g", g), ("m", m), ("v", v)):
+        _check_f32(name, a, n)
+    st = L.load().wn_adam(_ptr(x), _ptr(g), _ptr(m), _ptr(v), n, int(t), lr, betas[0], betas[1], eps,
+                          _stream_handle(x.device))
+    L.check("wn_adam", st)
+
+
+_INTEGRALS = {"naive": L.WN_INTEGRAL_NAIVE, "gwn": L.WN_INTEGRAL_GWN}
+
+
+def wn_morph_step(V: torch.Tensor, F: torch.Tensor, target: torch.Tensor, grid: Grid, m: torch.Tensor,
+                  v: torch.Tensor, t0: int, iters: int = 1, integral: str = "naive", tau: float = 0.5,
+                  k: float = 50.0, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8,
+                  loss_history: torch.Tensor | None = None) -> torch.Tensor:
+    """``iters`` morphing iterations (forward, sigmoid-MSE loss, adjoint, Adam with step
+    numbers t0+1 ...) on V in place; returns the per-iteration losses (device float [iters])."""
+    _check_mesh(V, F)
+    grid = Grid.of(grid)
+    dev = V.device
+    _check_f32("target", target, grid.size)
+    _check_f32("m", m, V.numel())
+    _check_f32("v", v, V.numel())
+    if loss_history is None:
+        loss_history = torch.empty(max(0, int(iters)), dtype=torch.float32, device=dev)
+    else:
+        _check_f32("loss_history", loss_history)
+        if loss_history.numel() < iters:
+            raise ValueError("loss_history holds fewer than iters floats")
+    need = wn_workspace_size(L.WN_OP_MORPH, V.shape[0], F.shape[0], grid.size)
+    ws, wsb = Workspace.get(need, dev)
+    g = grid.to_c()
+    st = L.load().wn_morph_step(_ptr(V), V.shape[0], _ptr(F), F.shape[0], ctypes.byref(g), _ptr(target),
+                                _INTEGRALS[integral], tau, k, lr, betas[0], betas[1], eps, int(t0), int(iters),
+                                _ptr(m), _ptr(v), _ptr(loss_history), ws, wsb, _stream_handle(dev))
+    L.check("wn_morph_step", st)
+    return loss_history
+
+
+class Morpher:
+    """Device-resident morphing state: vertices (updated in place), Adam moments and
+    the step count.  ``run(n)`` enqueues n iterations without synchronising."""
+
+    def __init__(self, V, F, target, grid, integral: str = "naive", tau: float = 0.5, k: float = 50.0,
+                 lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8):
+        self.V, self.F = as_mesh(V, F)
+        self.V = self.V.clone()
+        self.grid = Grid.of(grid)
+        self.target = torch.as_tensor(target).to(self.V.device, torch.float32).reshape(-1).contiguous()
+        self.m = torch.zeros_like(self.V)
+        self.v = torch.zeros_like(self.V)
+        self.t = 0
+        self.opts = dict(integral=integral, tau=tau, k=k, lr=lr, betas=betas, eps=eps)
+
+    def run(self, iters: int) -> torch.Tensor:
+        losses = wn_morph_step(self.V, self.F, self.target, self.grid, self.m, self.v, self.t, iters, **self.opts)
+        self.t += int(iters)
+        return losses
+
+
 def wn_get_device_error(device=None) -> int:
     """Status of the last call on the current stream's workspace (synchronises)."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())

@@ -2,6 +2,8 @@
 // layout and the launch sequence of each call.  No entry point allocates device
 // memory or synchronises (except wn_get_device_error).
 #include <stdio.h>
+#include <cmath>
+#include <algorithm>
 #include <string.h>
 
 #include <string>
@@ -48,6 +50,29 @@ size_t voxelize_ws(int64_t nR, int64_t nQ) {
     return b;
 }
 
+size_t loss_ws(int64_t n) { return kWsHeader + align_up((size_t)loss_blocks(n) * sizeof(float)); }
+
+// Morphing workspace: one region shared in turn by the forward, the loss and the
+// adjoint (they run in order on one stream), then W, dL/dW, dL/dV and a loss slot.
+struct MorphLayout {
+    size_t sub, w, dldw, dldv, loss, total;
+};
+
+MorphLayout morph_layout(int64_t nV, int64_t nF, int64_t P) {
+    MorphLayout l;
+    size_t sub = voxelize_ws(3 * nF, P);
+    sub = std::max(sub, naive_fwd_workspace(nF, P));
+    sub = std::max(sub, bwd_workspace(nV, nF, P));
+    sub = std::max(sub, loss_ws(P));
+    l.sub = 0;
+    l.w = align_up(sub);
+    l.dldw = l.w + align_up((size_t)P * sizeof(float));
+    l.dldv = l.dldw + align_up((size_t)P * sizeof(float));
+    l.loss = l.dldv + align_up((size_t)nV * 3 * sizeof(float));
+    l.total = l.loss + 256;
+    return l;
+}
+
 }  // namespace
 
 extern "C" {
@@ -63,6 +88,9 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
             return kWsHeader + align_up((size_t)loss_blocks(nQ) * sizeof(float));
         case WN_OP_FLIP:
             return flip_workspace(nV, nF);
+        case WN_OP_MORPH:
+            if (nV > kMaxCount || nF > kMaxCount || nQ > kMaxCount) return 0;
+            return morph_layout(nV, nF, nQ).total;
         default:
             return 0;
     }
@@ -311,6 +339,70 @@ wn_status wn_flip_duplicate(const float *V, int64_t nV, const int32_t *F, int64_
     if (!(eps == eps)) return WN_ERR_INVALID_ARG;
     if (ws == nullptr || !aligned256(ws) || ws_bytes < flip_workspace(nV, nF)) return WN_ERR_WORKSPACE;
     return run_flip(V, nV, F, nF, eps, V2, F2, static_cast<char *>(ws), ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+wn_status wn_adam(float *x, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float beta1,
+                  float beta2, float eps, void *stream) {
+    if (n < 0 || t < 1) return WN_ERR_INVALID_ARG;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && std::isfinite(lr)))
+        return WN_ERR_INVALID_ARG;
+    if (n == 0) return WN_OK;
+    if (!x || !g || !m || !v) return WN_ERR_INVALID_ARG;
+    return hip_status(launch_adam(x, g, m, v, n, t, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream)));
+}
+
+wn_status wn_morph_step(float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                        const float *target, int32_t integral, float tau, float k, float lr, float beta1,
+                        float beta2, float eps, int64_t t0, int32_t iters, float *m, float *v, float *loss_history,
+                        void *ws, size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF) || grid == nullptr) return WN_ERR_INVALID_ARG;
+    if (integral != WN_INTEGRAL_GWN && integral != WN_INTEGRAL_NAIVE) return WN_ERR_INVALID_ARG;
+    if (iters < 0 || t0 < 0 || t0 > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && std::isfinite(lr)))
+        return WN_ERR_INVALID_ARG;
+    const int64_t P = query_count(grid, nullptr, 0);
+    if (P < 0) return WN_ERR_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
+    if (P > 0 && target == nullptr) return WN_ERR_INVALID_ARG;
+    if (nV > 0 && (m == nullptr || v == nullptr)) return WN_ERR_INVALID_ARG;
+    const MorphLayout l = morph_layout(nV, nF, P);
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < l.total) return WN_ERR_WORKSPACE;
+    if (iters == 0) return WN_OK;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    char *sub = base + l.sub;
+    const size_t sub_bytes = l.w - l.sub;
+    float *W = reinterpret_cast<float *>(base + l.w);
+    float *dLdW = reinterpret_cast<float *>(base + l.dldw);
+    float *dLdV = reinterpret_cast<float *>(base + l.dldv);
+    float *loss_slot = reinterpret_cast<float *>(base + l.loss);
+    const PointSrc ps = make_point_src(grid, nullptr);
+    const int ppl = lookup_config(WN_OP_VOXELIZE, nF, P).ppl;
+    const bool naive = integral == WN_INTEGRAL_NAIVE;
+    for (int32_t it = 0; it < iters; ++it) {
+        wn_status st = WN_OK;
+        if (P > 0) {
+            if (naive) {
+                OccParams none{nullptr, WN_OCC_NONE, tau, k};
+                st = hip_status(launch_naive_fwd(V, nV, F, nF, ps, P, W, none, sub, ppl, s));
+            } else {
+                st = voxelize_impl(V, nV, F, nF, nullptr, 0, grid, nullptr, 0, W, WN_OCC_NONE, tau, k, nullptr, sub,
+                                   sub_bytes, stream, ppl);
+            }
+            if (st != WN_OK) return st;
+        }
+        float *loss = loss_history ? loss_history + it : loss_slot;
+        float *scratch = reinterpret_cast<float *>(sub + kWsHeader);
+        st = hip_status(launch_sigmoid_mse(W, target, P, tau, k, loss, dLdW, scratch, s));
+        if (st != WN_OK) return st;
+        st = run_backward(V, nV, F, nF, ps, P, dLdW, dLdV, nullptr, sub, sub_bytes, s, naive);
+        if (st != WN_OK) return st;
+        st = hip_status(launch_adam(V, dLdV, m, v, 3 * nV, t0 + 1 + it, lr, beta1, beta2, eps, s));
+        if (st != WN_OK) return st;
+    }
+    return WN_OK;
 }
 
 wn_status wn_get_device_error(void *ws, void *stream) {

@@ -369,6 +369,9 @@ constexpr float kInv8Pi = 0.0397887357729738340f;
 hipError_t launch_naive_fwd(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
                             int64_t nQ, float *W, const OccParams &occ, char *ws, int ppl, hipStream_t s);
 size_t naive_fwd_workspace(int64_t nF, int64_t nQ);
+// Adam over a flat parameter array (wn_morph.hip); t >= 1 is the step number.
+hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float b1,
+                       float b2, float eps, hipStream_t s);
 // The adjoint pair kernel of Eq. 4 (defined in wn_naive.hip, launched by run_backward).
 hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int64_t chunkP,
                             int split, const float *dLdW, float *partials, hipStream_t s);

@@ -1,0 +1,184 @@
+"""GPU parity of the mesh-morphing loop (Section 2.4) and its Adam optimiser against the
+FP64 oracle, through the C ABI (wn_adam, wn_morph_step).
+
+Tolerances, from the FP32 error model:
+  * Adam alone: m and v to 1e-6 of the size of their terms; x to 2e-6 of its step plus
+    one ulp of x (FP32 moments, FP64 bias corrections rounded to FP32, IEEE sqrt/divide).
+  * One morphing iteration from zero moments is Adam step 1, which moves a coordinate by
+    lr g / (|g| + eps).  A gradient error delta changes that by at most
+    lr min(2, 4 delta / (|g| + eps)).  delta = 2e-3 max|g| covers the adjoint's own
+    tolerance (1e-3 of the largest gradient) and the forward's error carried through
+    the loss.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import wn_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_11272_amd as wn
+    wn.wn_version()
+    return torch.device("cuda", 0)
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("n", [0, 1, 257, 1000003])
+@pytest.mark.parametrize("t", [1, 5, 1000])
+def test_adam_matches_oracle(dev, orc, n, t):
+    import paper_2407_11272_amd as wn
+    rng = np.random.default_rng(40 + n + t)
+    x = rng.normal(size=n).astype(np.float32)
+    g = (rng.normal(size=n) * 10.0 ** rng.uniform(-3, 3, size=n)).astype(np.float32)
+    m = (rng.normal(size=n) * 0.1).astype(np.float32) if t > 1 else np.zeros(n, np.float32)
+    v = (np.abs(rng.normal(size=n)) * 0.01).astype(np.float32) if t > 1 else np.zeros(n, np.float32)
+    xd, gd, md, vd = _t(x), _t(g), _t(m), _t(v)
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    wn.wn_adam(xd, gd, md, vd, t, lr, (b1, b2), eps)
+    xr, mr, vr = orc.adam(x, g, m, v, t, float(np.float32(lr)), float(np.float32(b1)), float(np.float32(b2)),
+                          float(np.float32(eps)))
+    xg, mg, vg = xd.cpu().numpy(), md.cpu().numpy(), vd.cpu().numpy()
+    x64, g64 = x.astype(np.float64), g.astype(np.float64)
+    assert np.all(np.abs(mg - mr) <= 1e-6 * (np.abs(b1 * m) + np.abs((1 - b1) * g64)) + 1e-30)
+    assert np.all(np.abs(vg - vr) <= 1e-6 * (np.abs(b2 * v) + np.abs((1 - b2) * g64 * g64)) + 1e-37)
+    assert np.all(np.abs(xg - xr) <= 2e-6 * np.abs(xr - x64) + np.spacing(np.abs(x)))
+
+
+def _morph_case(integral):
+    c = wi.config3_differentiable(res=24, open_variant=(integral == "gwn"))
+    return c
+
+
+@pytest.mark.parametrize("integral", ["naive", "gwn"])
+def test_morph_iteration_matches_oracle(dev, orc, integral):
+    import torch
+    import paper_2407_11272_amd as wn
+    c = _morph_case(integral)
+    V0 = np.asarray(c.V, np.float32)
+    lr, eps = 1e-3, 1e-8
+    Vd, Fd = wn.as_mesh(torch.as_tensor(V0), torch.as_tensor(c.F))
+    Vd = Vd.clone()
+    m, v = torch.zeros_like(Vd), torch.zeros_like(Vd)
+    T = _t(c.target.reshape(-1))
+    losses = wn.wn_morph_step(Vd, Fd, T, c.grid, m, v, 0, 1, integral=integral, tau=c.tau, k=c.k, lr=lr, eps=eps)
+    V1 = Vd.cpu().numpy().astype(np.float64)
+    V064 = V0.astype(np.float64)
+    Vr, _, _, Lr = orc.morph(V064, c.F, c.grid, c.target.reshape(-1), 1, integral=integral, tau=c.tau, k=c.k,
+                             lr=lr, eps=eps)
+    # the oracle's gradient at V0, for the error model
+    Q = orc.grid_points(c.grid)
+    W = (orc.winding_naive if integral == "naive" else orc.winding)(V064, c.F, Q)
+    _, dLdW = orc.sigmoid_mse(W, c.target.reshape(-1), c.tau, c.k)
+    _, g = (orc.grad_naive if integral == "naive" else orc.grad)(V064, c.F, Q, dLdW)
+    delta = 2e-3 * np.abs(g).max()
+    bound = lr * np.minimum(2.0, 4 * delta / (np.abs(g) + eps)) + 1e-5 * lr + np.spacing(np.abs(V0))
+    err = np.abs((V1 - V064) - (Vr - V064))
+    print(f"[morph {integral}] max|dV err|/lr={err.max() / lr:.2e}  coords over 1e-2 lr: {(err > 1e-2 * lr).sum()}"
+          f"  loss {float(losses[0]):.6e} vs {Lr[0]:.6e}", flush=True)
+    assert np.abs(g).max() > 0
+    assert np.all(err <= bound)
+    assert float(losses[0]) == pytest.approx(Lr[0], rel=1e-4)
+
+
+def test_morph_iterations_chain_bit_exactly(dev):
+    """iters = 3 in one call equals three calls of one iteration (t0 = 0, 1, 2)."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable(res=20)
+    V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    T = _t(c.target.reshape(-1))
+    A, B = V.clone(), V.clone()
+    mA, vA, mB, vB = (torch.zeros_like(V) for _ in range(4))
+    LA = wn.wn_morph_step(A, F, T, c.grid, mA, vA, 0, 3, lr=2e-3)
+    LB = torch.cat([wn.wn_morph_step(B, F, T, c.grid, mB, vB, i, 1, lr=2e-3) for i in range(3)])
+    torch.cuda.synchronize()
+    assert torch.equal(A, B) and torch.equal(mA, mB) and torch.equal(vA, vB) and torch.equal(LA, LB)
+    assert not torch.equal(A, V)
+
+
+def test_morph_lowers_the_loss(dev):
+    """Naive-integral morphing of the sphere towards the ellipsoid target at 64^3."""
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable()
+    mo = wn.Morpher(c.V, c.F, c.target.reshape(-1), c.grid, integral="naive", tau=c.tau, k=c.k, lr=2e-3)
+    L = mo.run(20).cpu().numpy()
+    print(f"[morph 64^3] loss {L[0]:.5f} -> {L[-1]:.5f}", flush=True)
+    assert L[-1] < 0.8 * L[0]
+    assert np.sum(np.diff(L) > 0) <= 2
+
+
+def test_morph_empty_and_degenerate(dev):
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable(res=8)
+    V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    T = _t(c.target.reshape(-1))
+    # no faces: W = 0, zero gradient, vertices unchanged
+    A = V.clone()
+    m, v = torch.zeros_like(A), torch.zeros_like(A)
+    L = wn.wn_morph_step(A, F[:0].contiguous(), T, c.grid, m, v, 0, 2)
+    s = 1.0 / (1.0 + np.exp(-c.k * (0.0 - c.tau)))
+    assert torch.equal(A, V)
+    np.testing.assert_allclose(L.cpu().numpy(), np.mean((s - c.target.reshape(-1)) ** 2), rtol=1e-5)
+    # empty grid: zero loss, zero gradient
+    g0 = wn.Grid((-0.5,) * 3, (0.5,) * 3, (0, 4, 4))
+    A = V.clone()
+    L = wn.wn_morph_step(A, F, _t(np.zeros(0)), g0, m.zero_(), v.zero_(), 0, 1)
+    assert torch.equal(A, V) and float(L[0]) == 0.0
+    # zero iterations: nothing happens
+    assert wn.wn_morph_step(A, F, T, c.grid, m, v, 0, 0).numel() == 0
+
+
+def test_morph_argument_errors(dev):
+    import torch
+    import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd import _lib as L
+    lib = L.load()
+    V = torch.zeros((3, 3), device="cuda")
+    F = torch.tensor([[0, 1, 2]], dtype=torch.int32, device="cuda")
+    g = wn.Grid.cube(2).to_c()
+    T = torch.zeros(8, device="cuda")
+    m, v = torch.zeros_like(V), torch.zeros_like(V)
+    need = wn.wn_workspace_size(L.WN_OP_MORPH, 3, 1, 8)
+    ws = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = ctypes.c_void_p
+
+    def call(integral=1, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, t0=0, iters=1, mm=m, wsb=need, target=T, grid=g):
+        return lib.wn_morph_step(p(V.data_ptr()), 3, p(F.data_ptr()), 1,
+                                 ctypes.byref(grid) if grid is not None else None,
+                                 p(target.data_ptr()) if target is not None else None, integral, 0.5, 50.0, lr, b1,
+                                 b2, eps, t0, iters, p(mm.data_ptr()) if mm is not None else None, p(v.data_ptr()),
+                                 None, p(base), wsb, s)
+
+    assert call() == L.WN_OK
+    assert call(integral=0) == L.WN_OK
+    assert call(integral=2) == L.WN_ERR_INVALID_ARG
+    assert call(t0=-1) == L.WN_ERR_INVALID_ARG
+    assert call(iters=-1) == L.WN_ERR_INVALID_ARG
+    assert call(b1=1.0) == L.WN_ERR_INVALID_ARG
+    assert call(b2=-0.1) == L.WN_ERR_INVALID_ARG
+    assert call(eps=0.0) == L.WN_ERR_INVALID_ARG
+    assert call(lr=float("nan")) == L.WN_ERR_INVALID_ARG
+    assert call(mm=None) == L.WN_ERR_INVALID_ARG
+    assert call(target=None) == L.WN_ERR_INVALID_ARG
+    assert call(grid=None) == L.WN_ERR_INVALID_ARG
+    assert call(wsb=need - 1) == L.WN_ERR_WORKSPACE
+    x = torch.zeros(4, device="cuda")
+    assert lib.wn_adam(p(x.data_ptr()), p(x.data_ptr()), p(x.data_ptr()), p(x.data_ptr()), 4, 0, 1e-3, 0.9, 0.999,
+                       1e-8, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_adam(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, s) == L.WN_OK
+    torch.cuda.synchronize()
