@@ -13,7 +13,10 @@ Paper sections followed (arXiv 2407.11272):
   * Section 2.1, Eq. 3: for a closed surface W is the occupancy; the map to a hard
     or soft occupancy uses a threshold or a sigmoid around 0.5;
   * Section 2.4 (mesh morphing): the voxel loss drives the vertices through Adam
-    (Kingma and Ba, 2015, Algorithm 1), written out in numpy FP64.
+    (Kingma and Ba, 2015, Algorithm 1), written out in numpy FP64;
+  * Section 3 (evaluation): occupancy -> cube surface ("cubified") -> Laplacian
+    smoothing (10 iterations, lambda = 0.15) -> 20 000 surface samples -> Chamfer and
+    Hausdorff distances to the original mesh.
 """
 from __future__ import annotations
 
@@ -71,6 +74,8 @@ def _bind(lib):
     lib.wno_grad_naive.restype = ctypes.c_int
     lib.wno_grad_naive.argtypes = [_dp, ctypes.c_int64, _lp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp,
                                    ctypes.c_int]
+    lib.wno_nn_dist.restype = ctypes.c_int
+    lib.wno_nn_dist.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, ctypes.c_int]
     return lib
 
 
@@ -336,3 +341,144 @@ def morph(V, F, grid, target, iters: int, integral: str = "naive", tau: float = 
         V, m, v = adam(V, dLdV, m, v, t0 + 1 + i, lr, beta1, beta2, eps)
         losses.append(L)
     return V, m, v, np.array(losses)
+
+
+# ------------------------------------------------------------ evaluation chain (Section 3)
+
+# Faces of the unit cube [0,1]^3 around a voxel, in the order -x, +x, -y, +y, -z, +z.
+# Each entry: (axis, side, the two in-plane axes (u, w) with u x w = +axis).  A face's
+# corners p0..p3 walk (0,0), (1,0), (1,1), (0,1) in (u, w); triangles (p0,p1,p2),
+# (p0,p2,p3) face +axis, and their reversal faces -axis.
+_CUBE_DIRS = [(0, 0, 1, 2), (0, 1, 1, 2), (1, 0, 2, 0), (1, 1, 2, 0), (2, 0, 0, 1), (2, 1, 0, 1)]
+
+
+def _quad_corners(ijk, d):
+    axis, side, u, w = _CUBE_DIRS[d]
+    base = list(ijk)
+    base[axis] += side
+    out = []
+    for du, dw in ((0, 0), (1, 0), (1, 1), (0, 1)):
+        c = list(base)
+        c[u] += du
+        c[w] += dw
+        out.append(tuple(c))
+    if side == 0:
+        tris = [(out[0], out[2], out[1]), (out[0], out[3], out[2])]
+    else:
+        tris = [(out[0], out[1], out[2]), (out[0], out[2], out[3])]
+    return tris
+
+
+def cubify(occ, grid):
+    """Cube surface of an occupancy grid (the 'cubified' occupancy of Section 3): every
+    face of an occupied voxel whose neighbour is empty or outside the grid becomes two
+    outward triangles.  Faces in voxel C order, then -x, +x, -y, +y, -z, +z; vertices
+    are the lattice corners used, numbered in lattice C order, at lo + corner * h (FP64).
+    Returns (V [nV, 3] float64, F [nF, 3] int64)."""
+    occ = np.asarray(occ).reshape(tuple(int(x) for x in grid.n)).astype(bool)
+    n = occ.shape
+    pad = np.pad(occ, 1)
+    keys, tris = [], []
+    idx = np.argwhere(occ)  # C order
+    lin = (idx[:, 0] * n[1] + idx[:, 1]) * n[2] + idx[:, 2]
+    for d in range(6):
+        axis, side = _CUBE_DIRS[d][0], _CUBE_DIRS[d][1]
+        nb = idx + 1
+        nb[:, axis] += 1 if side else -1
+        bnd = ~pad[nb[:, 0], nb[:, 1], nb[:, 2]]
+        for t in range(2):
+            corners = np.stack([np.array(_quad_corners((0, 0, 0), d)[t][j]) for j in range(3)])  # [3, 3]
+            tris.append(idx[bnd][:, None, :] + corners[None])
+            keys.append(lin[bnd] * 12 + 2 * d + t)
+    if not idx.size or not np.concatenate(keys).size:
+        return np.zeros((0, 3)), np.zeros((0, 3), np.int64)
+    order = np.argsort(np.concatenate(keys), kind="stable")
+    T = np.concatenate(tris)[order]  # [nF, 3 corners, 3 coords]
+    clin = (T[..., 0] * (n[1] + 1) + T[..., 1]) * (n[2] + 1) + T[..., 2]
+    used, F = np.unique(clin.reshape(-1), return_inverse=True)
+    F = F.reshape(-1, 3)
+    ci = np.stack([used // ((n[1] + 1) * (n[2] + 1)), (used // (n[2] + 1)) % (n[1] + 1), used % (n[2] + 1)], 1)
+    lo = np.asarray(grid.lo, np.float64)
+    h = (np.asarray(grid.hi, np.float64) - lo) / np.asarray(grid.n, np.float64)
+    return lo + ci * h, F
+
+
+def vertex_neighbours(nV, F):
+    """Sorted unique neighbour lists (vertices joined by a face edge), as CSR arrays."""
+    F = np.asarray(F, np.int64)
+    e = np.concatenate([F[:, [0, 1]], F[:, [1, 0]], F[:, [1, 2]], F[:, [2, 1]], F[:, [2, 0]], F[:, [0, 2]]])
+    e = np.unique(e, axis=0)
+    e = e[e[:, 0] != e[:, 1]]
+    off = np.zeros(nV + 1, np.int64)
+    np.add.at(off, e[:, 0] + 1, 1)
+    return np.cumsum(off), e[:, 1]
+
+
+def laplacian_smooth(V, F, lam: float = 0.15, iters: int = 10):
+    """Umbrella-operator Laplacian smoothing, Jacobi form: every iteration moves each
+    vertex by lam times (mean of its edge neighbours - itself); isolated vertices stay."""
+    V = np.array(V, dtype=np.float64)
+    off, nbr = vertex_neighbours(len(V), F)
+    deg = np.diff(off)
+    for _ in range(iters):
+        S = np.zeros_like(V)
+        for c in range(3):
+            S[:, c] = np.add.reduceat(np.concatenate([V[nbr, c], [0.0]]), off[:-1]) if len(nbr) else 0.0
+        has = deg > 0
+        mean = np.zeros_like(V)
+        mean[has] = S[has] / deg[has, None]
+        V = np.where(has[:, None], V + lam * (mean - V), V)
+    return V
+
+
+def face_area_weights(V, F):
+    """Integer sampling weights w_f = floor(area_f * 2^32 / max area) (uint64): areas in
+    FP64 from the given coordinates, so that face choice is exact integer arithmetic."""
+    V = np.asarray(V, np.float64)
+    F = np.asarray(F, np.int64)
+    a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    e1, e2 = b - a, c - a
+    cx = e1[:, 1] * e2[:, 2] - e1[:, 2] * e2[:, 1]
+    cy = e1[:, 2] * e2[:, 0] - e1[:, 0] * e2[:, 2]
+    cz = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    area = 0.5 * np.sqrt((cx * cx + cy * cy) + cz * cz)
+    amax = area.max() if len(area) else 0.0
+    if amax <= 0:
+        return np.zeros(len(F), np.uint64)
+    return np.floor(area * (4294967296.0 / amax)).astype(np.uint64)
+
+
+def sample_surface(V, F, u):
+    """Area-uniform surface samples from uniform numbers u [n, 3] in [0, 1): u0 picks the
+    face by inverse CDF of the integer area weights, (u1, u2) the barycentric point
+    (reflected into the triangle when u1 + u2 > 1).  Returns (points [n, 3], face ids)."""
+    V = np.asarray(V, np.float64)
+    F = np.asarray(F, np.int64)
+    u = np.asarray(u, np.float64)
+    w = face_area_weights(V, F)
+    cdf = np.cumsum(w, dtype=np.uint64)
+    total = int(cdf[-1])
+    t = np.minimum(np.floor(u[:, 0] * float(total)), float(total - 1)).astype(np.uint64)
+    f = np.searchsorted(cdf, t, side="right")
+    r1, r2 = u[:, 1].copy(), u[:, 2].copy()
+    flip = r1 + r2 > 1.0
+    r1[flip], r2[flip] = 1.0 - r1[flip], 1.0 - r2[flip]
+    a, b, c = V[F[f, 0]], V[F[f, 1]], V[F[f, 2]]
+    return a + r1[:, None] * (b - a) + r2[:, None] * (c - a), f
+
+
+def nn_distances(A, B, threads: int = 0):
+    """d[i] = min_j |A_i - B_j| (FP64 brute force)."""
+    A, pa = _d(np.asarray(A, np.float64).reshape(-1, 3))
+    B, pb = _d(np.asarray(B, np.float64).reshape(-1, 3))
+    d = np.empty(len(A))
+    if _load().wno_nn_dist(pa, len(A), pb, len(B), d.ctypes.data_as(_dp), threads) != 0:
+        raise ValueError("empty point set")
+    return d
+
+
+def chamfer_hausdorff(A, B, threads: int = 0):
+    """Chamfer distance mean_a min_b |a-b| + mean_b min_a |a-b| and Hausdorff distance
+    max(max_a min_b, max_b min_a) between two point sets."""
+    dab, dba = nn_distances(A, B, threads), nn_distances(B, A, threads)
+    return float(dab.mean() + dba.mean()), float(max(dab.max(), dba.max()))

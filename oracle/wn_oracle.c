@@ -429,3 +429,22 @@ int wno_min_dist(const double *V, int64_t nV, const int64_t *F, int64_t nF,
     }
     return 0;
 }
+
+/* Evaluation chain (Section 3): nearest-neighbour distance from every point of A to
+ * the point set B, d[i] = min_j |A_i - B_j|, by brute force in FP64. */
+int wno_nn_dist(const double *A, int64_t nA, const double *B, int64_t nB, double *d, int nthreads)
+{
+    if (nB <= 0 && nA > 0) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nA; ++i) {
+        double best = INFINITY;
+        for (int64_t j = 0; j < nB; ++j) {
+            const double dx = A[3 * i] - B[3 * j], dy = A[3 * i + 1] - B[3 * j + 1], dz = A[3 * i + 2] - B[3 * j + 2];
+            const double s = dx * dx + dy * dy + dz * dz;
+            if (s < best) best = s;
+        }
+        d[i] = sqrt(best);
+    }
+    return 0;
+}

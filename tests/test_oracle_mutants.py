@@ -107,9 +107,24 @@ PY_MUTANTS = [
     ("morph", "morph_step_number", "t0 + 1 + i", "t0 + i + 2"),
     ("morph", "morph_loss_after_update", "        V, m, v = adam(V, dLdV, m, v, t0 + 1 + i, lr, beta1, beta2, eps)\n        losses.append(L)",
      "        V, m, v = adam(V, dLdV, m, v, t0 + 1 + i, lr, beta1, beta2, eps)\n        losses.append(sigmoid_mse(fwd(V, F, Q, threads=threads), target, tau, k)[0])"),
+    ("_quad_corners", "cubify_inward_faces", "tris = [(out[0], out[2], out[1]), (out[0], out[3], out[2])]",
+     "tris = [(out[0], out[1], out[2]), (out[0], out[2], out[3])]"),
+    ("_quad_corners", "cubify_wrong_side", "base[axis] += side", "base[axis] += 1 - side"),
+    ("cubify", "cubify_interior_faces", "bnd = ~pad[", "bnd = pad["),
+    ("laplacian_smooth", "smooth_full_step", "V + lam * (mean - V)", "V + lam * mean"),
+    ("laplacian_smooth", "smooth_unnormalised", "S[has] / deg[has, None]", "S[has] / 6.0"),
+    ("vertex_neighbours", "smooth_duplicate_edges", "e = np.unique(e, axis=0)", "e = e[np.argsort(e[:, 0], kind='stable')]"),
+    ("sample_surface", "sample_cdf_side", 'side="right"', 'side="left"'),
+    ("sample_surface", "sample_no_reflection", "r1[flip], r2[flip] = 1.0 - r1[flip], 1.0 - r2[flip]",
+     "r1[flip], r2[flip] = r2[flip], r1[flip]"),
+    ("face_area_weights", "sample_area_squared", "0.5 * np.sqrt((cx * cx + cy * cy) + cz * cz)",
+     "0.25 * ((cx * cx + cy * cy) + cz * cz)"),
+    ("chamfer_hausdorff", "chamfer_one_way", "dab.mean() + dba.mean()", "dab.mean()"),
+    ("chamfer_hausdorff", "hausdorff_one_way", "max(dab.max(), dba.max())", "dab.max()"),
 ]
 
-PY_PIN_TESTS = [fn for fn in PIN_TESTS if "adam" in fn.__name__ or "morph" in fn.__name__]
+PY_PIN_TESTS = [fn for fn in PIN_TESTS
+                if any(k in fn.__name__ for k in ("adam", "morph", "cubify", "laplacian", "sampling", "nn_dist"))]
 
 
 @pytest.mark.parametrize("func,name,old,new", PY_MUTANTS, ids=[m[1] for m in PY_MUTANTS])

@@ -677,3 +677,128 @@ def test_morph_lowers_the_loss(orc):
     c = wi.config3_differentiable(res=12)
     _, _, _, losses = orc.morph(c.V, c.F, c.grid, c.target, 6, integral="naive", lr=2e-3)
     assert np.all(np.diff(losses) < 0)
+
+
+# ------------------------------------------------ evaluation chain (Section 3)
+
+def _edge_use_counts(F):
+    e = np.sort(np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]]), axis=1)
+    _, cnt = np.unique(e, axis=0, return_counts=True)
+    return cnt
+
+
+def test_cubify_single_voxel_and_block(orc):
+    """One voxel gives the 8-corner, 12-triangle cube; an a x b x c block gives a closed
+    box of area 2(ab + bc + ca) h^2 and volume abc h^3."""
+    g = wi.Grid((0.0, 0.0, 0.0), (2.0, 3.0, 4.0), (4, 6, 8))  # h = 0.5 on every axis
+    occ = np.zeros((4, 6, 8), np.uint8)
+    occ[0, 0, 0] = 1
+    V, F = orc.cubify(occ, g)
+    assert V.shape == (8, 3) and F.shape == (12, 3)
+    assert abs(signed_volume(V, F) - 0.125) < 1e-15
+    assert np.all(_edge_use_counts(F) == 2)
+    occ[:] = 0
+    occ[1:3, 2:5, 3:7] = 1  # 2 x 3 x 4 voxels
+    V, F = orc.cubify(occ, g)
+    a, b, c = 2, 3, 4
+    area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
+    assert abs(area - 2 * (a * b + b * c + c * a) * 0.25) < 1e-12
+    assert abs(signed_volume(V, F) - a * b * c * 0.125) < 1e-12
+    assert np.all(_edge_use_counts(F) == 2)
+    assert len(F) == 2 * 2 * (a * b + b * c + c * a)
+
+
+def test_cubify_winding_number_is_the_occupancy(orc):
+    """Eq. 3 applied to the cube surface: its winding number at every voxel centre is
+    exactly that voxel's occupancy, for random occupancy (non-manifold contacts and
+    grid-boundary voxels included).  Fixes orientation, completeness and placement."""
+    rng = np.random.default_rng(51)
+    for shape, p in (((6, 5, 4), 0.5), ((7, 3, 9), 0.3), ((5, 5, 5), 0.9)):
+        g = wi.Grid((-1.0, -0.5, 0.0), (1.0, 0.5, 2.0), shape)
+        occ = (rng.random(shape) < p).astype(np.uint8)
+        V, F = orc.cubify(occ, g)
+        W = orc.winding(V, F, orc.grid_points(g))
+        assert np.abs(W - occ.reshape(-1)).max() < 1e-12
+        # one quad (two triangles) per occupied voxel face next to empty or outside
+        pad = np.pad(occ.astype(bool), 1)
+        inner = pad[1:-1, 1:-1, 1:-1]
+        n_quads = sum(int(np.sum(inner & ~np.roll(pad, s, ax)[1:-1, 1:-1, 1:-1]))
+                      for ax in range(3) for s in (1, -1))
+        assert len(F) == 2 * n_quads
+    V, F = orc.cubify(np.zeros((3, 3, 3), np.uint8), wi.Grid.cube(3))
+    assert V.shape == (0, 3) and F.shape == (0, 3)
+
+
+def test_laplacian_smoothing_closed_forms(orc):
+    """Umbrella smoothing of regular solids shrinks them radially by a known factor per
+    iteration: octahedron 1 - lam (neighbour mean is the centre), icosahedron
+    1 - lam + lam / sqrt(5) (neighbours at cos = 1/sqrt 5).  lam = 0 is the identity."""
+    V, F = wi.octahedron_mesh(1.0)
+    S = orc.laplacian_smooth(V, F, 0.15, 10)
+    np.testing.assert_allclose(S, V * (1 - 0.15) ** 10, atol=1e-15)
+    V, F = wi.icosphere(0)
+    S = orc.laplacian_smooth(V, F, 0.15, 10)
+    np.testing.assert_allclose(S, V * (1 - 0.15 + 0.15 / math.sqrt(5)) ** 10, atol=1e-14)
+    np.testing.assert_array_equal(orc.laplacian_smooth(V, F, 0.0, 10), V)
+
+
+def test_laplacian_smoothing_keeps_planar_grid_interior(orc):
+    """On a flat triangulated grid (diagonals all one way) interior vertices are the mean
+    of their six neighbours, so they do not move; boundary vertices do."""
+    n = 6
+    x, y = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="ij")
+    V = np.stack([x.ravel(), y.ravel(), np.zeros(n * n)], 1)
+    F = []
+    for i in range(n - 1):
+        for j in range(n - 1):
+            a, b, c, d = i * n + j, (i + 1) * n + j, (i + 1) * n + j + 1, i * n + j + 1
+            F += [[a, b, c], [a, c, d]]
+    S = orc.laplacian_smooth(V, np.array(F), 0.3, 1)
+    inner = (x.ravel() > 0) & (x.ravel() < n - 1) & (y.ravel() > 0) & (y.ravel() < n - 1)
+    np.testing.assert_allclose(S[inner], V[inner], atol=1e-15)
+    assert np.abs(S[~inner] - V[~inner]).max() > 0.05
+    # two triangles sharing edge (1, 2): each neighbour counts once however many faces share it
+    K = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [2, 2, 1]], float)
+    S = orc.laplacian_smooth(K, np.array([[0, 1, 2], [1, 3, 2]]), 0.3, 1)
+    np.testing.assert_allclose(S[1], K[1] + 0.3 * ((K[0] + K[2] + K[3]) / 3 - K[1]), atol=1e-15)
+    np.testing.assert_allclose(S[0], K[0] + 0.3 * ((K[1] + K[2]) / 2 - K[0]), atol=1e-15)
+
+
+def test_surface_sampling_exact_face_choice_and_placement(orc):
+    """Face choice is integer inverse-CDF sampling of w_f = floor(area_f 2^32 / max):
+    two triangles of areas 1 and 3 split u0 at w_0 / (w_0 + w_1) = floor(2^32/3) /
+    (floor(2^32/3) + 2^32).  Points lie in their face, and their mean over one triangle
+    approaches its centroid."""
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 0], [0, 0, 1], [3, 0, 1], [0, 2, 1]], float)
+    F = np.array([[0, 1, 2], [3, 4, 5]])
+    w0, w1 = math.floor(2 ** 32 / 3), 2 ** 32
+    np.testing.assert_array_equal(orc.face_area_weights(V, F), [w0, w1])
+    split = w0 / (w0 + w1)
+    u = np.array([[np.nextafter(split, 0), 0.2, 0.3], [split + 1e-12, 0.2, 0.3], [0.0, 0.9, 0.8],
+                  [np.nextafter(1.0, 0), 0.5, 0.5]])
+    P, f = orc.sample_surface(V, F, u)
+    np.testing.assert_array_equal(f, [0, 1, 0, 1])
+    np.testing.assert_allclose(P[2], V[0] + 0.1 * (V[1] - V[0]) + 0.2 * (V[2] - V[0]), atol=1e-15)
+    u = np.random.default_rng(52).random((200000, 3))
+    P, f = orc.sample_surface(V[:3], F[:1], u)
+    bary = np.linalg.lstsq(np.stack([V[1] - V[0], V[2] - V[0]], 1)[:2], (P - V[0])[:, :2].T, rcond=None)[0]
+    assert np.all(bary >= -1e-12) and np.all(bary.sum(0) <= 1 + 1e-12) and np.all(P[:, 2] == 0)
+    assert np.abs(P.mean(0) - V[:3].mean(0)).max() < 5e-3
+
+
+def test_nn_distances_and_chamfer_hausdorff(orc):
+    """Brute-force nearest neighbours against a k-d tree (scipy), and the metrics on
+    point sets with known answers."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(53)
+    A, B = rng.normal(size=(3000, 3)), rng.normal(size=(2000, 3)) * 1.5
+    np.testing.assert_allclose(orc.nn_distances(A, B), cKDTree(B).query(A)[0], rtol=1e-12)
+    cd, hd = orc.chamfer_hausdorff(A, A)
+    assert cd == 0.0 and hd == 0.0
+    cd, hd = orc.chamfer_hausdorff([[0, 0, 0]], [[3, 4, 0]])
+    assert cd == 10.0 and hd == 5.0
+    # a set against itself plus one outlier at distance 2 from its nearest point
+    B = np.concatenate([A, [[100.0, 0, 0]]])
+    dmin = np.min(np.linalg.norm(A - [100.0, 0, 0], axis=1))
+    cd, hd = orc.chamfer_hausdorff(A, B)
+    assert abs(hd - dmin) < 1e-12 and abs(cd - dmin / len(B)) < 1e-12
