@@ -323,6 +323,44 @@ def bench_morph(iters: int):
     return out
 
 
+def bench_eval(reps: int):
+    """The evaluation chain of Section 3 on the 19 000-face union at 128^3: strip-order
+    forward with threshold occupancy, cube surface, 10 smoothing steps (lambda 0.15),
+    20 000 samples of the result and of the mesh, Chamfer and Hausdorff."""
+    import torch
+    import paper_2407_11272_amd as wn
+    import wn_inputs as wi
+    c = wi.config2_ellipsoid_union()
+    V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    R = torch.as_tensor(wn.wn_build_strips(c.F, len(c.V))).cuda()
+    grid = wn.Grid.of(c.grid)
+    ua, ub = (torch.as_tensor(u).cuda() for u in wi.evaluation_samples())
+    stages = {}
+
+    def timed(name, fn):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        out = fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        stages.setdefault(name, []).append(ev0.elapsed_time(ev1))
+        return out
+
+    for _ in range(reps + 1):
+        W, occ = timed("voxelize", lambda: wn.wn_voxelize_strips(V, F, R, grid=grid, occupancy="threshold"))
+        Vc, Fc = timed("cubify", lambda: wn.wn_cubify(occ, grid))
+        Vs = timed("smooth", lambda: wn.wn_laplacian_smooth(Vc, Fc, 0.15, 10))
+        Pa, _ = timed("sample", lambda: wn.wn_sample_surface(Vs, Fc, ua))
+        Pb, _ = timed("sample_ref", lambda: wn.wn_sample_surface(V, F, ub))
+        m = timed("metrics", lambda: wn.wn_chamfer_hausdorff(Pa, Pb))
+    ms = {k: sum(v[1:]) / reps for k, v in stages.items()}  # first pass is a warm-up
+    m = m.cpu().numpy()
+    return {"workload": "ellipsoid-union-19000f-128cube: occupancy -> cube surface -> 10 x Laplacian(0.15) "
+                        "-> 2 x 20000 samples -> Chamfer/Hausdorff",
+            "stage_ms": ms, "total_ms": sum(ms.values()), "cube_faces": int(Fc.shape[0]),
+            "chamfer": float(m[0]), "hausdorff": float(m[1])}
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     """A streaming kernel of known size (torch's elementwise negation: reads nbytes,
     writes nbytes): its FETCH_SIZE and WRITE_SIZE counter readings calibrate the
@@ -381,8 +419,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--served-requests", type=int, default=96)
-    ap.add_argument("--rows", default="adjoint,batched,served,naive,flip,morph",
-                    help="comma list of extra rows to measure (adjoint, batched, served, naive, flip, morph)")
+    ap.add_argument("--rows", default="adjoint,batched,served,naive,flip,morph,eval",
+                    help="comma list of extra rows to measure (adjoint, batched, served, naive, flip, morph, eval)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-load", type=float, default=0.8)
@@ -461,6 +499,9 @@ def main():
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
         rows["naive"] = bench_naive(3)
+    if "eval" in want:
+        print("# bench: evaluation-chain row", file=sys.stderr, flush=True)
+        rows["eval"] = bench_eval(3)
     if "morph" in want:
         print("# bench: morph row", file=sys.stderr, flush=True)
         rows["morph"] = bench_morph(20)

@@ -79,6 +79,10 @@ typedef int32_t wn_status;
 #define WN_OP_LOSS 3
 #define WN_OP_FLIP 4
 #define WN_OP_MORPH 5
+#define WN_OP_CUBIFY 6 /* wn_workspace_size(WN_OP_CUBIFY, 0, 0, voxels) for a grid; see wn_cubify  */
+#define WN_OP_SMOOTH 7 /* wn_workspace_size(WN_OP_SMOOTH, nV, nF, 0)                              */
+#define WN_OP_SAMPLE 8 /* wn_workspace_size(WN_OP_SAMPLE, 0, nF, n samples)                       */
+#define WN_OP_NN 9     /* wn_workspace_size(WN_OP_NN, |A|, |B|, 0)                                 */
 
 /* Which integral drives a morphing iteration (wn_morph_step). */
 #define WN_INTEGRAL_GWN 0   /* Eq. 5 with Eq. 7 solid angles (wn_voxelize / wn_backward)      */
@@ -92,7 +96,9 @@ typedef struct {
 } wn_grid;
 
 /* Bytes of device workspace an operation needs (WN_OP_VOXELIZE, WN_OP_BACKWARD,
- * WN_OP_LOSS, WN_OP_FLIP, WN_OP_MORPH; a batched launch uses wn_workspace_size_batched).
+ * WN_OP_LOSS, WN_OP_FLIP, WN_OP_MORPH, WN_OP_SMOOTH, WN_OP_SAMPLE, WN_OP_NN, and
+ * WN_OP_CUBIFY for a cube grid of nQ voxels; a batched launch uses
+ * wn_workspace_size_batched, a cube surface of any grid wn_workspace_size_cubify).
  * Returns 0 for an unknown op or negative sizes. */
 WN_API size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ);
 
@@ -291,6 +297,65 @@ WN_API wn_status wn_morph_step(float *V, int64_t nV, const int32_t *F, int64_t n
                                const float *target, int32_t integral, float tau, float k, float lr,
                                float beta1, float beta2, float eps, int64_t t0, int32_t iters, float *m,
                                float *v, float *loss_history, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Evaluation chain of the paper's experiments (Section 3): each method's occupancy is
+ * "cubified", smoothed with a Laplacian filter (10 iterations, lambda = 0.15), and
+ * compared with the original mesh by Chamfer and Hausdorff distances over 20 000
+ * surface samples.  The four calls below are those steps.
+ */
+
+/*
+ * Cube surface of an occupancy grid: every face of an occupied voxel (occ[i] != 0,
+ * uint8 [P], C order like the grid points) whose neighbour is empty or outside the grid
+ * becomes two triangles facing outward.  Faces are ordered by voxel, then -x, +x, -y,
+ * +y, -z, +z; vertices are the lattice corners used, numbered in lattice C order, at
+ * lo + c (hi - lo) / n.  Writes counts[0] = nV, counts[1] = nF (device int64 [2]) and
+ * the first capV vertices (float [capV][3]) and capF faces (int32 [capF][3]); nothing
+ * beyond the capacities.  Bounds: nV <= (nx+1)(ny+1)(nz+1), nF <= 12 P.  The lattice must
+ * have fewer than 2^31 corners.  Workspace: wn_workspace_size(WN_OP_CUBIFY, 0, 0, P) for
+ * a cube grid; in general wn_workspace_size_cubify(grid).
+ */
+WN_API size_t wn_workspace_size_cubify(const wn_grid *grid);
+WN_API wn_status wn_cubify(const uint8_t *occ, const wn_grid *grid, float *V, int64_t capV, int32_t *F,
+                           int64_t capF, int64_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Laplacian smoothing with the umbrella operator, `iters` Jacobi steps
+ *   v <- v + lam (mean of the vertices joined to v by a face edge - v);
+ * vertices without neighbours stay.  Each vertex adds its neighbours in increasing id
+ * order, so the result is deterministic.  V (float [nV][3]) is read, Vout (float
+ * [nV][3], not aliasing V) written.  Out-of-range face indices are replaced by 0 and
+ * recorded.  Workspace: wn_workspace_size(WN_OP_SMOOTH, nV, nF, 0).
+ */
+WN_API wn_status wn_laplacian_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam,
+                                     int32_t iters, float *Vout, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Area-uniform surface samples from caller-supplied uniform numbers u (device double
+ * [n][3] in [0, 1)).  Face weights are w_f = floor(area_f 2^32 / max area) with areas in
+ * FP64 from the FP32 coordinates (products rounded separately); sample s takes the
+ * first face whose inclusive prefix of w exceeds min(floor(u0 W), W - 1), W = sum w, and
+ * the point a + r1 (b - a) + r2 (c - a) with (r1, r2) = (u1, u2), reflected to
+ * (1 - u1, 1 - u2) when u1 + u2 > 1.  Writes P (float [n][3]) and face (int32 [n]);
+ * if every face has zero area, face = -1 and P = 0.  Needs nF > 0 when n > 0.
+ * Workspace: wn_workspace_size(WN_OP_SAMPLE, 0, nF, n).
+ */
+WN_API wn_status wn_sample_surface(const float *V, int64_t nV, const int32_t *F, int64_t nF, const double *u,
+                                   int64_t n, float *P, int32_t *face, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Nearest-neighbour distances d[i] = min_j |A_i - B_j| (float [nA]; A float [nA][3],
+ * B float [nB][3], nB > 0 when nA > 0), and the two metrics of the evaluation:
+ * out[0] = Chamfer distance mean_a d(a, B) + mean_b d(b, A), out[1] = Hausdorff distance
+ * max(max_a d(a, B), max_b d(b, A)) (device double [2]; nA, nB > 0).  Squared distances
+ * are FP32; the minimum is exact for them; the means are FP64 sums in a fixed order.
+ * Workspace: wn_workspace_size(WN_OP_NN, nA, nB, 0).
+ */
+WN_API wn_status wn_nn_distance(const float *A, int64_t nA, const float *B, int64_t nB, float *d, void *ws,
+                                size_t ws_bytes, void *stream);
+WN_API wn_status wn_chamfer_hausdorff(const float *A, int64_t nA, const float *B, int64_t nB, double *out,
+                                      void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Reads and clears the device-side error record that the most recent call using

@@ -459,7 +459,7 @@ def sample_surface(V, F, u):
     cdf = np.cumsum(w, dtype=np.uint64)
     total = int(cdf[-1])
     t = np.minimum(np.floor(u[:, 0] * float(total)), float(total - 1)).astype(np.uint64)
-    f = np.searchsorted(cdf, t, side="right")
+    f = np.minimum(np.searchsorted(cdf, t, side="right"), len(F) - 1)
     r1, r2 = u[:, 1].copy(), u[:, 2].copy()
     flip = r1 + r2 > 1.0
     r1[flip], r2[flip] = 1.0 - r1[flip], 1.0 - r2[flip]

@@ -11,6 +11,12 @@ from .api import (  # noqa: F401
     Morpher,
     wn_adam,
     wn_morph_step,
+    wn_cubify,
+    wn_laplacian_smooth,
+    wn_sample_surface,
+    wn_nn_distance,
+    wn_chamfer_hausdorff,
+    evaluate_occupancy,
     wn_autotune,
     wn_voxelize_batched,
     wn_workspace_size_batched,

@@ -28,6 +28,10 @@ WN_OP_BATCHED = 2
 WN_OP_LOSS = 3
 WN_OP_FLIP = 4
 WN_OP_MORPH = 5
+WN_OP_CUBIFY = 6
+WN_OP_SMOOTH = 7
+WN_OP_SAMPLE = 8
+WN_OP_NN = 9
 
 WN_INTEGRAL_GWN = 0
 WN_INTEGRAL_NAIVE = 1
@@ -51,6 +55,12 @@ EXPORTED = (
     "wn_flip_duplicate",
     "wn_adam",
     "wn_morph_step",
+    "wn_workspace_size_cubify",
+    "wn_cubify",
+    "wn_laplacian_smooth",
+    "wn_sample_surface",
+    "wn_nn_distance",
+    "wn_chamfer_hausdorff",
     "wn_get_device_error",
     "wn_status_string",
     "wn_version",
@@ -131,6 +141,18 @@ def load():
     lib.wn_morph_step.restype = i32
     lib.wn_morph_step.argtypes = [vp, i64, vp, i64, gp, vp, i32, f32, f32, f32, f32, f32, f32, i64, i32, vp, vp,
                                   vp, vp, sz, vp]
+    lib.wn_workspace_size_cubify.restype = sz
+    lib.wn_workspace_size_cubify.argtypes = [gp]
+    lib.wn_cubify.restype = i32
+    lib.wn_cubify.argtypes = [vp, gp, vp, i64, vp, i64, vp, vp, sz, vp]
+    lib.wn_laplacian_smooth.restype = i32
+    lib.wn_laplacian_smooth.argtypes = [vp, i64, vp, i64, f32, i32, vp, vp, sz, vp]
+    lib.wn_sample_surface.restype = i32
+    lib.wn_sample_surface.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, vp, sz, vp]
+    lib.wn_nn_distance.restype = i32
+    lib.wn_nn_distance.argtypes = [vp, i64, vp, i64, vp, vp, sz, vp]
+    lib.wn_chamfer_hausdorff.restype = i32
+    lib.wn_chamfer_hausdorff.argtypes = [vp, i64, vp, i64, vp, vp, sz, vp]
     lib.wn_get_device_error.restype = i32
     lib.wn_get_device_error.argtypes = [vp, vp]
     lib.wn_status_string.restype = ctypes.c_char_p

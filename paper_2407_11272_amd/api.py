@@ -344,6 +344,100 @@ class Morpher:
         return losses
 
 
+# ------------------------------------------------------- evaluation chain (Section 3)
+
+def _check_points(name, t):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 2 and t.shape[1] == 3):
+        raise ValueError(f"{name} must be a contiguous float32 [n, 3] device tensor")
+
+
+def wn_cubify(occ: torch.Tensor, grid: Grid):
+    """Cube surface of an occupancy grid (uint8/bool, grid.size voxels): (V [nV, 3], F [nF, 3]).
+    Reads the two counts back (one synchronisation)."""
+    grid = Grid.of(grid)
+    occ = occ.reshape(-1)
+    if occ.dtype == torch.bool:
+        occ = occ.view(torch.uint8)
+    if not (occ.is_cuda and occ.dtype == torch.uint8 and occ.is_contiguous() and occ.numel() == grid.size):
+        raise ValueError("occ must be a contiguous uint8 device tensor with one entry per voxel")
+    dev = occ.device
+    n = [int(x) for x in grid.n]
+    capV = (n[0] + 1) * (n[1] + 1) * (n[2] + 1)
+    capF = 12 * grid.size
+    V = torch.empty((capV, 3), dtype=torch.float32, device=dev)
+    F = torch.empty((capF, 3), dtype=torch.int32, device=dev)
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    g = grid.to_c()
+    lib = L.load()
+    ws, wsb = Workspace.get(lib.wn_workspace_size_cubify(ctypes.byref(g)), dev)
+    st = lib.wn_cubify(_ptr(occ), ctypes.byref(g), _ptr(V), capV, _ptr(F), capF, _ptr(counts), ws, wsb,
+                       _stream_handle(dev))
+    L.check("wn_cubify", st)
+    nV, nF = (int(x) for x in counts.cpu())
+    return V[:nV], F[:nF]
+
+
+def wn_laplacian_smooth(V: torch.Tensor, F: torch.Tensor, lam: float = 0.15, iters: int = 10) -> torch.Tensor:
+    """Umbrella-operator Laplacian smoothing (Jacobi steps); returns new vertices."""
+    _check_mesh(V, F)
+    out = torch.empty_like(V)
+    ws, wsb = Workspace.get(wn_workspace_size(L.WN_OP_SMOOTH, V.shape[0], F.shape[0], 0), V.device)
+    st = L.load().wn_laplacian_smooth(_ptr(V), V.shape[0], _ptr(F), F.shape[0], lam, int(iters), _ptr(out), ws, wsb,
+                                      _stream_handle(V.device))
+    L.check("wn_laplacian_smooth", st)
+    return out
+
+
+def wn_sample_surface(V: torch.Tensor, F: torch.Tensor, u: torch.Tensor):
+    """Area-uniform surface samples from uniform numbers u (float64 [n, 3]): (P [n, 3], face [n])."""
+    _check_mesh(V, F)
+    if not (u.is_cuda and u.dtype == torch.float64 and u.is_contiguous() and u.dim() == 2 and u.shape[1] == 3):
+        raise ValueError("u must be a contiguous float64 [n, 3] device tensor")
+    n = u.shape[0]
+    P = torch.empty((n, 3), dtype=torch.float32, device=V.device)
+    face = torch.empty(n, dtype=torch.int32, device=V.device)
+    ws, wsb = Workspace.get(wn_workspace_size(L.WN_OP_SAMPLE, 0, F.shape[0], n), V.device)
+    st = L.load().wn_sample_surface(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(u), n, _ptr(P), _ptr(face), ws,
+                                    wsb, _stream_handle(V.device))
+    L.check("wn_sample_surface", st)
+    return P, face
+
+
+def wn_nn_distance(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+    """d[i] = min_j |A_i - B_j|."""
+    _check_points("A", A)
+    _check_points("B", B)
+    d = torch.empty(A.shape[0], dtype=torch.float32, device=A.device)
+    ws, wsb = Workspace.get(wn_workspace_size(L.WN_OP_NN, A.shape[0], B.shape[0], 0), A.device)
+    st = L.load().wn_nn_distance(_ptr(A), A.shape[0], _ptr(B), B.shape[0], _ptr(d), ws, wsb, _stream_handle(A.device))
+    L.check("wn_nn_distance", st)
+    return d
+
+
+def wn_chamfer_hausdorff(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+    """Device float64 [2]: (Chamfer distance, Hausdorff distance) between point sets."""
+    _check_points("A", A)
+    _check_points("B", B)
+    out = torch.empty(2, dtype=torch.float64, device=A.device)
+    ws, wsb = Workspace.get(wn_workspace_size(L.WN_OP_NN, A.shape[0], B.shape[0], 0), A.device)
+    st = L.load().wn_chamfer_hausdorff(_ptr(A), A.shape[0], _ptr(B), B.shape[0], _ptr(out), ws, wsb,
+                                       _stream_handle(A.device))
+    L.check("wn_chamfer_hausdorff", st)
+    return out
+
+
+def evaluate_occupancy(occ: torch.Tensor, grid: Grid, V_ref: torch.Tensor, F_ref: torch.Tensor,
+                       u_rec: torch.Tensor, u_ref: torch.Tensor, lam: float = 0.15, iters: int = 10):
+    """The paper's accuracy measure of an occupancy grid: cube surface, Laplacian
+    smoothing, surface samples of the result and of the reference mesh (uniform numbers
+    u_rec, u_ref), then (Chamfer, Hausdorff) as a device float64 [2]."""
+    Vc, Fc = wn_cubify(occ, grid)
+    Vs = wn_laplacian_smooth(Vc, Fc, lam, iters)
+    Pa, _ = wn_sample_surface(Vs, Fc, u_rec)
+    Pb, _ = wn_sample_surface(V_ref, F_ref, u_ref)
+    return wn_chamfer_hausdorff(Pa, Pb)
+
+
 def wn_get_device_error(device=None) -> int:
     """Status of the last call on the current stream's workspace (synchronises)."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())

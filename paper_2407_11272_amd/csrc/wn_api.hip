@@ -91,6 +91,21 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
         case WN_OP_MORPH:
             if (nV > kMaxCount || nF > kMaxCount || nQ > kMaxCount) return 0;
             return morph_layout(nV, nF, nQ).total;
+        case WN_OP_CUBIFY: {
+            int64_t r = 0;
+            while ((r + 1) * (r + 1) * (r + 1) <= nQ) ++r;
+            if (r * r * r != nQ || nQ > kMaxCount) return 0;
+            return cubify_workspace(nQ, (r + 1) * (r + 1) * (r + 1));
+        }
+        case WN_OP_SMOOTH:
+            if (nV > kMaxCount || nF > kMaxCount / 6) return 0;
+            return smooth_workspace(nV, nF);
+        case WN_OP_SAMPLE:
+            if (nF > kMaxCount || nQ > kMaxCount) return 0;
+            return sample_workspace(nF);
+        case WN_OP_NN:
+            if (nV > kMaxCount || nF > kMaxCount) return 0;
+            return nn_workspace(nV, nF);
         default:
             return 0;
     }
@@ -403,6 +418,65 @@ wn_status wn_morph_step(float *V, int64_t nV, const int32_t *F, int64_t nF, cons
         if (st != WN_OK) return st;
     }
     return WN_OK;
+}
+
+size_t wn_workspace_size_cubify(const wn_grid *grid) {
+    if (!grid) return 0;
+    int64_t P = 1, C = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (grid->n[d] < 0) return 0;
+        P *= grid->n[d];
+        C *= (int64_t)grid->n[d] + 1;
+    }
+    if (P > kMaxCount || C > kMaxCount) return 0;
+    return cubify_workspace(P, C);
+}
+
+wn_status wn_cubify(const uint8_t *occ, const wn_grid *grid, float *V, int64_t capV, int32_t *F, int64_t capF,
+                    int64_t *counts, void *ws, size_t ws_bytes, void *stream) {
+    if (grid == nullptr || counts == nullptr || capV < 0 || capF < 0) return WN_ERR_INVALID_ARG;
+    const size_t need = wn_workspace_size_cubify(grid);
+    if (need == 0) return WN_ERR_INVALID_ARG;
+    const int64_t P = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+    if (P > 0 && occ == nullptr) return WN_ERR_INVALID_ARG;
+    if ((capV > 0 && V == nullptr) || (capF > 0 && F == nullptr)) return WN_ERR_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
+    return run_cubify(occ, grid->n, grid->lo, grid->hi, V, capV, F, capF, counts, static_cast<char *>(ws),
+                      static_cast<hipStream_t>(stream));
+}
+
+wn_status wn_laplacian_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam, int32_t iters,
+                              float *Vout, void *ws, size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF) || nF > kMaxCount / 6 || iters < 0 || !std::isfinite(lam)) return WN_ERR_INVALID_ARG;
+    if (nV > 0 && (Vout == nullptr || Vout == V)) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < smooth_workspace(nV, nF)) return WN_ERR_WORKSPACE;
+    return run_smooth(V, nV, F, nF, lam, iters, Vout, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
+}
+
+wn_status wn_sample_surface(const float *V, int64_t nV, const int32_t *F, int64_t nF, const double *u, int64_t n,
+                            float *P, int32_t *face, void *ws, size_t ws_bytes, void *stream) {
+    if (!mesh_ok(V, nV, F, nF) || n < 0 || n > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (n > 0 && (nF == 0 || u == nullptr || P == nullptr || face == nullptr)) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < sample_workspace(nF)) return WN_ERR_WORKSPACE;
+    return run_sample(V, nV, F, nF, u, n, P, face, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
+}
+
+wn_status wn_nn_distance(const float *A, int64_t nA, const float *B, int64_t nB, float *d, void *ws,
+                         size_t ws_bytes, void *stream) {
+    if (nA < 0 || nB < 0 || nA > kMaxCount || nB > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (nA > 0 && (A == nullptr || d == nullptr || nB == 0 || B == nullptr)) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < nn_workspace(nA, nB)) return WN_ERR_WORKSPACE;
+    return run_nn(A, nA, B, nB, d, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
+}
+
+wn_status wn_chamfer_hausdorff(const float *A, int64_t nA, const float *B, int64_t nB, double *out, void *ws,
+                               size_t ws_bytes, void *stream) {
+    if (nA <= 0 || nB <= 0 || nA > kMaxCount || nB > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (A == nullptr || B == nullptr || out == nullptr) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr || !aligned256(ws) || ws_bytes < nn_workspace(nA, nB)) return WN_ERR_WORKSPACE;
+    return run_chamfer(A, nA, B, nB, out, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
 }
 
 wn_status wn_get_device_error(void *ws, void *stream) {

@@ -211,8 +211,12 @@ __device__ __forceinline__ void push_record(const float4 v, const bool face, con
     }
 }
 
-__device__ __forceinline__ bool record_face(const float4 v) {
-    return __builtin_amdgcn_readfirstlane(__float_as_int(v.w)) != 0;
+// Face flags of a staged tile (record i's flag is bit i) as a wave-uniform mask, so the
+// per-record branch costs no vector instruction.  Needs nt <= 64.
+__device__ __forceinline__ unsigned long long tile_face_mask(const float4 *tile, int nt) {
+    const int lane = threadIdx.x & 63;
+    const float flag = lane < nt ? tile[2 * lane].w : 0.0f;
+    return __builtin_amdgcn_ballot_w64(flag != 0.0f);
 }
 
 // Sum of the half solid angles of the faces completed by records [r0, r1), at PPL
@@ -247,24 +251,25 @@ __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int6
         __syncthreads();
         if (tid < 2 * nt) tile[tid] = src[2 * t0 + tid];
         __syncthreads();
+        const unsigned long long fmask = tile_face_mask(tile, nt);
         float ts[PPL];
 #pragma unroll
         for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
         int i = 0;
         for (; i + 3 <= nt; i += 3) {
-            const float4 v0 = tile[2 * i], v1 = tile[2 * i + 2], v2 = tile[2 * i + 4];
-            push_record<PPL>(v0, record_face(v0), tile[2 * i + 1], S1, S2, S0, qx, qy, qz, ts);
-            push_record<PPL>(v1, record_face(v1), tile[2 * i + 3], S2, S0, S1, qx, qy, qz, ts);
-            push_record<PPL>(v2, record_face(v2), tile[2 * i + 5], S0, S1, S2, qx, qy, qz, ts);
+            const float4 *g = tile + 2 * i;
+            const float4 v0 = g[0], n0 = g[1], v1 = g[2], n1 = g[3], v2 = g[4], n2 = g[5];
+            const unsigned bits = (unsigned)(fmask >> i);
+            push_record<PPL>(v0, bits & 1u, n0, S1, S2, S0, qx, qy, qz, ts);
+            push_record<PPL>(v1, bits & 2u, n1, S2, S0, S1, qx, qy, qz, ts);
+            push_record<PPL>(v2, bits & 4u, n2, S0, S1, S2, qx, qy, qz, ts);
         }
         // a partial group only occurs in the last tile of the range
         if (i < nt) {
-            const float4 v0 = tile[2 * i];
-            push_record<PPL>(v0, record_face(v0), tile[2 * i + 1], S1, S2, S0, qx, qy, qz, ts);
-            if (i + 1 < nt) {
-                const float4 v1 = tile[2 * i + 2];
-                push_record<PPL>(v1, record_face(v1), tile[2 * i + 3], S2, S0, S1, qx, qy, qz, ts);
-            }
+            const unsigned bits = (unsigned)(fmask >> i);
+            push_record<PPL>(tile[2 * i], bits & 1u, tile[2 * i + 1], S1, S2, S0, qx, qy, qz, ts);
+            if (i + 1 < nt)
+                push_record<PPL>(tile[2 * i + 2], bits & 2u, tile[2 * i + 3], S2, S0, S1, qx, qy, qz, ts);
         }
 #pragma unroll
         for (int p = 0; p < PPL; ++p) neumaier_add(s[p], c[p], ts[p]);
@@ -369,6 +374,21 @@ constexpr float kInv8Pi = 0.0397887357729738340f;
 hipError_t launch_naive_fwd(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
                             int64_t nQ, float *W, const OccParams &occ, char *ws, int ppl, hipStream_t s);
 size_t naive_fwd_workspace(int64_t nF, int64_t nQ);
+// Evaluation chain (wn_eval.hip): cube surface of an occupancy grid, Laplacian
+// smoothing, area-uniform surface samples, nearest-neighbour distances and metrics.
+size_t cubify_workspace(int64_t P, int64_t C);
+size_t smooth_workspace(int64_t nV, int64_t nF);
+size_t sample_workspace(int64_t nF);
+size_t nn_workspace(int64_t nA, int64_t nB);
+wn_status run_cubify(const uint8_t *occ, const int32_t n[3], const float lo[3], const float hi[3], float *V,
+                     int64_t capV, int32_t *F, int64_t capF, int64_t *counts, char *ws, hipStream_t s);
+wn_status run_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam, int32_t iters, float *Vout,
+                     char *ws, hipStream_t s);
+wn_status run_sample(const float *V, int64_t nV, const int32_t *F, int64_t nF, const double *u, int64_t n, float *P,
+                     int32_t *face, char *ws, hipStream_t s);
+wn_status run_nn(const float *A, int64_t nA, const float *B, int64_t nB, float *d, char *ws, hipStream_t s);
+wn_status run_chamfer(const float *A, int64_t nA, const float *B, int64_t nB, double *out, char *ws, hipStream_t s);
+
 // Adam over a flat parameter array (wn_morph.hip); t >= 1 is the step number.
 hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float b1,
                        float b2, float eps, hipStream_t s);

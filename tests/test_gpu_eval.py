@@ -1,0 +1,190 @@
+"""GPU parity of the evaluation chain (Section 3) against the FP64 oracle, through the C
+ABI: cube surface, Laplacian smoothing, surface sampling, nearest neighbours and the
+Chamfer/Hausdorff metrics.
+
+Bars: the cube surface's faces (integer work) bit-exact and its vertices within 2 ulp
+of the coordinate range; the sampled face ids bit-exact (integer area weights, FP64
+areas on both sides); FP32 coordinates within a few ulp of the largest coordinate
+times the number of FP32 steps (10 smoothing iterations, one barycentric combination);
+distances within 1e-6 of the point-set scale.
+"""
+import numpy as np
+import pytest
+
+import wn_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_11272_amd as wn
+    wn.wn_version()
+    return torch.device("cuda", 0)
+
+
+def _cuda(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _union_occupancy(res):
+    c = wi.config2_ellipsoid_union(res)
+    occ = np.zeros(c.grid.size, bool)
+    for e in c.extra["ellipsoids"]:
+        occ |= wi.ellipsoid_target_on_grid(c.grid, e) > 0
+    return c, occ.astype(np.uint8)
+
+
+def _occupancies():
+    rng = np.random.default_rng(61)
+    out = []
+    for n, p in (((13, 7, 5), 0.5), ((1, 1, 1), 1.0), ((4, 4, 4), 1.0), ((6, 3, 8), 0.0), ((9, 9, 9), 0.2)):
+        g = wi.Grid((-1.0, -0.25, 0.5), (1.0, 0.5, 2.5), n)
+        out.append((f"random{n}", g, (rng.random(n) < p).astype(np.uint8).reshape(-1)))
+    c, occ = _union_occupancy(128)
+    out.append(("union128", c.grid, occ))
+    return out
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_cubify_matches_oracle(dev, orc, case):
+    import paper_2407_11272_amd as wn
+    name, g, occ = _occupancies()[case]
+    V, F = wn.wn_cubify(_cuda(occ), g)
+    Vr, Fr = orc.cubify(occ, g)
+    print(f"[cubify {name}] nV={len(Vr)} nF={len(Fr)}", flush=True)
+    assert F.shape == Fr.shape and V.shape == Vr.shape
+    np.testing.assert_array_equal(F.cpu().numpy(), Fr)
+    scale = max(np.abs(np.asarray(g.lo)).max(), np.abs(np.asarray(g.hi)).max())
+    assert np.abs(V.cpu().numpy() - Vr).max() <= 2 * np.spacing(np.float32(scale))
+
+
+def test_smoothing_matches_oracle(dev, orc):
+    import paper_2407_11272_amd as wn
+    rng = np.random.default_rng(62)
+    g = wi.Grid((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0), (11, 9, 10))
+    Vc, Fc = orc.cubify((rng.random(g.size) < 0.4).astype(np.uint8), g)
+    c1 = wi.config1_icosphere()
+    for name, V, F, iters in (("cubified", Vc, Fc, 10), ("icosphere", c1.V, c1.F, 10), ("one step", Vc, Fc, 1),
+                              ("no steps", Vc, Fc, 0)):
+        V32 = np.asarray(V, np.float32)
+        S = wn.wn_laplacian_smooth(_cuda(V32), _cuda(np.asarray(F, np.int32)), 0.15, iters).cpu().numpy()
+        Sr = orc.laplacian_smooth(V32.astype(np.float64), F, 0.15, iters)
+        err = np.abs(S - Sr).max() / np.abs(Sr).max()
+        print(f"[smooth {name}] max err / max |v| = {err:.2e}", flush=True)
+        assert err <= 4e-7 * max(iters, 1)
+    # no faces: vertices unchanged; isolated vertex among faces stays
+    S = wn.wn_laplacian_smooth(_cuda(V32), _cuda(np.zeros((0, 3), np.int32)), 0.15, 10)
+    np.testing.assert_array_equal(S.cpu().numpy(), V32)
+
+
+@pytest.mark.parametrize("n", [1, 257, 20000])
+def test_sampling_matches_oracle(dev, orc, n):
+    import paper_2407_11272_amd as wn
+    for c in (wi.config1_icosphere(), wi.config2_ellipsoid_union()):
+        V32 = np.asarray(c.V, np.float32)
+        u = wi.uniform_samples(n, 63 + n)
+        P, f = wn.wn_sample_surface(_cuda(V32), _cuda(np.asarray(c.F, np.int32)), _cuda(u))
+        Pr, fr = orc.sample_surface(V32.astype(np.float64), c.F, u)
+        np.testing.assert_array_equal(f.cpu().numpy(), fr)
+        assert np.abs(P.cpu().numpy() - Pr).max() <= 8 * np.spacing(np.float32(np.abs(V32).max()))
+
+
+def test_sampling_degenerate_mesh(dev):
+    import paper_2407_11272_amd as wn
+    V = np.array([[0, 0, 0], [1, 1, 1], [2, 2, 2]], np.float32)  # collinear: zero area
+    P, f = wn.wn_sample_surface(_cuda(V), _cuda(np.array([[0, 1, 2]], np.int32)), _cuda(wi.uniform_samples(5, 1)))
+    assert np.all(f.cpu().numpy() == -1) and np.all(P.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("nA,nB", [(1, 1), (3, 1000), (20000, 20000), (1000, 3)])
+def test_nn_and_metrics_match_oracle(dev, orc, nA, nB):
+    import paper_2407_11272_amd as wn
+    rng = np.random.default_rng(64 + nA)
+    A = rng.normal(size=(nA, 3)).astype(np.float32)
+    B = (rng.normal(size=(nB, 3)) * 1.3).astype(np.float32)
+    if nA > 2 and nB > 2:
+        A[1] = B[2]  # an exact duplicate: distance 0
+    d = wn.wn_nn_distance(_cuda(A), _cuda(B)).cpu().numpy()
+    dr = orc.nn_distances(A.astype(np.float64), B.astype(np.float64))
+    tol = 1e-6 * max(np.abs(A).max(), np.abs(B).max())
+    assert np.abs(d - dr).max() <= tol
+    m = wn.wn_chamfer_hausdorff(_cuda(A), _cuda(B)).cpu().numpy()
+    cd, hd = orc.chamfer_hausdorff(A.astype(np.float64), B.astype(np.float64))
+    assert abs(m[0] - cd) <= 2 * tol and abs(m[1] - hd) <= tol
+
+
+def test_evaluation_chain_matches_oracle(dev, orc):
+    """Occupancy (the oracle's W of the 1280-face icosphere at 64^3, threshold 0.5) ->
+    cube surface -> 10 smoothing steps (lambda 0.15) -> 20 000 samples of it and of the
+    mesh -> Chamfer and Hausdorff."""
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere(64)
+    V32 = np.asarray(c.V, np.float32)
+    W = orc.winding_grid(V32.astype(np.float64), c.F, c.grid)
+    occ = orc.occupancy_threshold(W)
+    ua, ub = wi.evaluation_samples()
+    m = wn.evaluate_occupancy(_cuda(occ), c.grid, _cuda(V32), _cuda(np.asarray(c.F, np.int32)), _cuda(ua),
+                              _cuda(ub)).cpu().numpy()
+    Vc, Fc = orc.cubify(occ, c.grid)
+    Vs = orc.laplacian_smooth(Vc.astype(np.float32).astype(np.float64), Fc)
+    Pa, _ = orc.sample_surface(Vs, Fc, ua)
+    Pb, _ = orc.sample_surface(V32.astype(np.float64), c.F, ub)
+    cd, hd = orc.chamfer_hausdorff(Pa, Pb)
+    print(f"[eval chain icosphere 64^3] Chamfer {m[0]:.6f} vs {cd:.6f}, Hausdorff {m[1]:.6f} vs {hd:.6f}", flush=True)
+    # The smoothed vertices differ by FP32 rounding (about 1e-7 relative), which moves the
+    # integer area weights by ~1e-7 of their size; of 20 000 samples, those whose u0 lies
+    # within that of a face boundary (~nF * 1e-7 of them, under 1 %) land on a neighbouring
+    # face, at most a voxel away.  Hence a relative bound on the mean and a voxel on the max.
+    h = 1.0 / 64
+    assert abs(m[0] - cd) <= 0.02 * cd and abs(m[1] - hd) <= h
+    assert cd < h and hd < 2 * h  # the smoothed cube surface stays within a voxel or two
+
+
+def test_eval_argument_errors(dev):
+    import ctypes
+    import torch
+    import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd import _lib as L
+    lib = L.load()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ws = torch.zeros(1 << 22, dtype=torch.uint8, device="cuda")
+    base = ctypes.c_void_p(ws.data_ptr() + ((-ws.data_ptr()) % 256))
+    p = ctypes.c_void_p
+    g = wn.Grid.cube(4).to_c()
+    occ = torch.ones(64, dtype=torch.uint8, device="cuda")
+    V = torch.empty((125, 3), device="cuda")
+    F = torch.empty((12 * 64, 3), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    need = lib.wn_workspace_size_cubify(ctypes.byref(g))
+    assert need == lib.wn_workspace_size(L.WN_OP_CUBIFY, 0, 0, 64)
+    assert lib.wn_cubify(p(occ.data_ptr()), ctypes.byref(g), p(V.data_ptr()), 125, p(F.data_ptr()), 768,
+                         p(cnt.data_ptr()), base, need, s) == L.WN_OK
+    torch.cuda.synchronize()
+    assert cnt.tolist() == [98, 192]  # 5^3 - 3^3 surface corners, 6 * 16 quads
+    assert lib.wn_cubify(None, ctypes.byref(g), p(V.data_ptr()), 125, p(F.data_ptr()), 768, p(cnt.data_ptr()),
+                         base, need, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_cubify(p(occ.data_ptr()), ctypes.byref(g), p(V.data_ptr()), 125, p(F.data_ptr()), 768, None,
+                         base, need, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_cubify(p(occ.data_ptr()), ctypes.byref(g), p(V.data_ptr()), 125, p(F.data_ptr()), 768,
+                         p(cnt.data_ptr()), base, need - 1, s) == L.WN_ERR_WORKSPACE
+    # capacities smaller than the surface: counts still exact, nothing written beyond
+    Fs = torch.full((11, 3), -7, dtype=torch.int32, device="cuda")
+    assert lib.wn_cubify(p(occ.data_ptr()), ctypes.byref(g), None, 0, p(Fs.data_ptr()), 10, p(cnt.data_ptr()), base,
+                         need, s) == L.WN_OK
+    torch.cuda.synchronize()
+    assert cnt.tolist() == [98, 192] and torch.all(Fs[10] == -7) and torch.all(Fs[:10] >= 0)
+    A = torch.zeros((4, 3), device="cuda")
+    d = torch.empty(4, device="cuda")
+    assert lib.wn_nn_distance(p(A.data_ptr()), 4, None, 0, p(d.data_ptr()), base, 1 << 20, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_chamfer_hausdorff(p(A.data_ptr()), 0, p(A.data_ptr()), 4, p(d.data_ptr()), base, 1 << 20,
+                                    s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_sample_surface(p(A.data_ptr()), 4, None, 0, p(A.data_ptr()), 3, p(A.data_ptr()), p(d.data_ptr()),
+                                 base, 1 << 20, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_laplacian_smooth(p(A.data_ptr()), 4, None, 0, 0.15, 10, p(A.data_ptr()), base, 1 << 20,
+                                   s) == L.WN_ERR_INVALID_ARG
+    torch.cuda.synchronize()

@@ -30,5 +30,7 @@ from .configs import (  # noqa: F401
     config3_differentiable,
     config4_batch,
     config5_trace,
+    uniform_samples,
+    evaluation_samples,
     SEEDS,
 )

@@ -24,7 +24,8 @@ from .meshgen import (
     uv_resolution_for_faces,
 )
 
-SEEDS = {"c1": 1, "c2": 2, "c3_mesh": 3, "c3_target": 4, "c4": 5, "c5_mesh": 6, "c5_arrivals": 7}
+SEEDS = {"c1": 1, "c2": 2, "c3_mesh": 3, "c3_target": 4, "c4": 5, "c5_mesh": 6, "c5_arrivals": 7,
+         "eval_reconstruction": 8, "eval_reference": 9}
 
 
 @dataclass
@@ -145,3 +146,15 @@ def config5_trace(n_requests: int, rate: float, face_lo: int = 1000, face_hi: in
         wants = bool(rm.uniform() < grad_frac)
         reqs.append(Request(i, t, faces, res, wants, int(rm.integers(0, 2**31 - 1))))
     return reqs
+
+
+def uniform_samples(n: int, seed: int) -> np.ndarray:
+    """n rows of three uniform numbers in [0, 1) (float64): the random input of surface
+    sampling, drawn here so that both sides of a comparison use the same numbers."""
+    return np.random.default_rng(seed).random((n, 3))
+
+
+def evaluation_samples(n: int = 20000):
+    """The two uniform streams of the evaluation chain (reconstruction, reference mesh);
+    20 000 samples per surface as in the paper's experiments."""
+    return uniform_samples(n, SEEDS["eval_reconstruction"]), uniform_samples(n, SEEDS["eval_reference"])
