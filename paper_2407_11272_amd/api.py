@@ -89,9 +89,10 @@ def _check_mesh(V: torch.Tensor, F: torch.Tensor):
 
 def as_mesh(V: torch.Tensor, F: torch.Tensor, device=None):
     """Cast a mesh to the library's layout (float32 vertices, int32 faces, contiguous)."""
+    V, F = torch.as_tensor(V), torch.as_tensor(F)
     device = torch.device(device) if device is not None else (V.device if V.is_cuda else torch.device("cuda"))
-    V = torch.as_tensor(V).to(device=device, dtype=torch.float32).contiguous()
-    F = torch.as_tensor(F).to(device=device, dtype=torch.int32).contiguous()
+    V = V.to(device=device, dtype=torch.float32).contiguous()
+    F = F.to(device=device, dtype=torch.int32).contiguous()
     return V, F
 
 

@@ -26,7 +26,7 @@
 
 namespace wn {
 
-constexpr int64_t kChunkRecords = 4095;  // records per work unit (a multiple of kRecTile)
+constexpr int64_t kChunkRecords = 4080;  // records per work unit (a multiple of kRecTile)
 static_assert(kChunkRecords % kRecTile == 0, "chunk must hold whole tiles");
 
 struct BMesh {

@@ -80,22 +80,26 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
                 u[j][2] = e[k][0] * e[l][1] - e[k][1] * e[l][0];
             }
             const float alpha = e[0][0] * u[0][0] + e[0][1] * u[0][1] + e[0][2] * u[0][2];
-            const float d01 = e[0][0] * e[1][0] + e[0][1] * e[1][1] + e[0][2] * e[1][2];
-            const float d12 = e[1][0] * e[2][0] + e[1][1] * e[2][1] + e[1][2] * e[2][2];
-            const float d20 = e[2][0] * e[0][0] + e[2][1] * e[0][1] + e[2][2] * e[0][2];
-            const float beta = 1.0f + d01 + d12 + d20;
+            float dd[3];  // dd[j] = e_k . e_l for (j, k, l) cyclic
+            dd[2] = e[0][0] * e[1][0] + e[0][1] * e[1][1] + e[0][2] * e[1][2];
+            dd[0] = e[1][0] * e[2][0] + e[1][1] * e[2][1] + e[1][2] * e[2][2];
+            dd[1] = e[2][0] * e[0][0] + e[2][1] * e[0][1] + e[2][2] * e[0][2];
+            const float beta = 1.0f + dd[2] + dd[0] + dd[1];
             const float den = alpha * alpha + beta * beta;
             const float gk = (den > 0.0f) ? q.w * __builtin_amdgcn_rcpf(den) : 0.0f;
+            // The projected vector of corner j, w - (w . e_j) e_j with w = beta u_j -
+            // alpha (e_k + e_l), equals beta u_j - alpha E - alpha (e_k . e_l) e_j, where
+            // E = e_0 + e_1 + e_2 (because e_j . u_j = alpha and e_j . (e_k + e_l) =
+            // beta - 1 - e_k . e_l).
+            float E[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) E[d] = e[0][d] + e[1][d] + e[2][d];
+            const float gb = gk * beta, ga = gk * alpha;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const int k = (j + 1) % 3, l = (j + 2) % 3;
-                float w[3];
+                const float cb = gb * ri[j], ca = ga * ri[j], cd = ca * dd[j];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) w[d] = beta * u[j][d] - alpha * (e[k][d] + e[l][d]);
-                const float we = w[0] * e[j][0] + w[1] * e[j][1] + w[2] * e[j][2];
-                const float coef = gk * ri[j];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) ts[3 * j + d] += coef * (w[d] - we * e[j][d]);
+                for (int d = 0; d < 3; ++d) ts[3 * j + d] += cb * u[j][d] - ca * E[d] - cd * e[j][d];
             }
         }
 #pragma unroll

@@ -34,6 +34,8 @@ constexpr float kPi = 3.14159265358979323846f;
 constexpr float kHalfPi = 1.57079632679489662f;
 constexpr float kInv2Pi = 0.159154943091895336f;
 constexpr float kFltMin = 1.17549435e-38f;
+constexpr float kTwoPi = 6.28318530717958648f;
+constexpr float kPairMax = 4.2535296e37f;  // 2^125: the reciprocal of a larger value is not normal
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kFaceTile = 64;    // faces staged in LDS per tile (3 float4 each)
@@ -44,7 +46,7 @@ constexpr int kWsHeader = 256;   // bytes reserved at the start of every workspa
 struct VRec {
     float4 p, n;
 };
-constexpr int kRecTile = 63;  // records staged in LDS per tile (a multiple of 3)
+constexpr int kRecTile = 60;  // records staged in LDS per tile (a multiple of 6, at most 64)
 
 // Face record in device memory (adjoint): 12 floats = 3 float4.
 //   a = (v0.x, v0.y, v0.z, v1.x)  b = (v1.y, v1.z, v2.x, v2.y)  c = (v2.z, N.x, N.y, N.z)
@@ -183,12 +185,11 @@ struct Slot {
     float x[PPL], y[PPL], z[PPL], r[PPL], dprev[PPL], rprev[PPL];
 };
 
-// Record v enters slot C (after B, which follows A).  If it completes a face, that face
-// is (A, B, C); its half solid angle at each point is added to ts.
+// Record v enters slot C (after B): R = v - q, r = |R|, and the dot and length products
+// with B, per query point.
 template <int PPL>
-__device__ __forceinline__ void push_record(const float4 v, const bool face, const float4 n, const Slot<PPL> &A,
-                                            const Slot<PPL> &B, Slot<PPL> &C, const float (&qx)[PPL],
-                                            const float (&qy)[PPL], const float (&qz)[PPL], float (&ts)[PPL]) {
+__device__ __forceinline__ void enter_vertex(const float4 v, const Slot<PPL> &B, Slot<PPL> &C, const float (&qx)[PPL],
+                                             const float (&qy)[PPL], const float (&qz)[PPL]) {
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         C.x[p] = v.x - qx[p];
@@ -198,16 +199,79 @@ __device__ __forceinline__ void push_record(const float4 v, const bool face, con
         C.dprev[p] = B.x[p] * C.x[p] + B.y[p] * C.y[p] + B.z[p] * C.z[p];
         C.rprev[p] = B.r[p] * C.r[p];
     }
-    if (face) {
+}
+
+// Scale-free Eq. 7 terms of the face (A, B, C) with normal n: alpha' = R_A . N and
+// beta' = r_A r_B r_C + (R_A.R_B) r_C + (R_B.R_C) r_A + (R_C.R_A) r_B; alpha' = 0 when a
+// vertex coincides with the point.
+template <int PPL>
+__device__ __forceinline__ void face_terms(const float4 n, const Slot<PPL> &A, const Slot<PPL> &B, const Slot<PPL> &C,
+                                           float (&al)[PPL], float (&be)[PPL]) {
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            const float dca = C.x[p] * A.x[p] + C.y[p] * A.y[p] + C.z[p] * A.z[p];
-            const float pr = B.rprev[p] * C.r[p];  // r_A r_B r_C
-            const float beta = pr + B.dprev[p] * C.r[p] + C.dprev[p] * A.r[p] + dca * B.r[p];
-            float alpha = A.x[p] * n.x + A.y[p] * n.y + A.z[p] * n.z;
-            alpha = (pr == 0.0f) ? 0.0f : alpha;
-            ts[p] += atan2_eq8(alpha, beta);
-        }
+    for (int p = 0; p < PPL; ++p) {
+        const float dca = C.x[p] * A.x[p] + C.y[p] * A.y[p] + C.z[p] * A.z[p];
+        const float pr = B.rprev[p] * C.r[p];  // r_A r_B r_C
+        be[p] = pr + B.dprev[p] * C.r[p] + C.dprev[p] * A.r[p] + dca * B.r[p];
+        const float alpha = A.x[p] * n.x + A.y[p] * n.y + A.z[p] * n.z;
+        al[p] = (pr == 0.0f) ? 0.0f : alpha;
+    }
+}
+
+// Sum of two half solid angles from one ATAN2: the argument of the product
+// (beta0 + i alpha0)(beta1 + i alpha1) is their sum up to a multiple of 2 pi.  The two
+// angles lie in (-pi, pi]; their sum leaves that range exactly when both have the same
+// sign and the product's imaginary part has the other sign, and then the principal
+// value is off by 2 pi with the sign of the angles.  Eq. 8's zero cases (an angle of
+// exactly 0 or pi, a face seen edge-on) and products outside the normal FP32 range take
+// the two ATAN2s one by one.
+__device__ __forceinline__ float pair_angle(float a0, float b0, float a1, float b1) {
+    const float pre = b0 * b1 - a0 * a1;
+    const float pim = a0 * b1 + b0 * a1;
+    float t = atan2_eq8(pim, pre);
+    const bool n0 = a0 < 0.0f, n1 = a1 < 0.0f, np = pim < 0.0f;
+    if (n0 == n1 && n0 != np) t += n0 ? -kTwoPi : kTwoPi;
+    const float mx = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(pre), __builtin_fabsf(pim)), kFltMin);
+    if (__builtin_expect(__builtin_fabsf(a0 * a1) < kFltMin || mx > kPairMax, 0))
+        t = atan2_eq8(a0, b0) + atan2_eq8(a1, b1);
+    return t;
+}
+
+// Record v enters slot C (after B, which follows A).  If it completes a face, that face
+// is (A, B, C); its half solid angle at each point is added to ts.
+template <int PPL>
+__device__ __forceinline__ void push_record(const float4 v, const bool face, const float4 n, const Slot<PPL> &A,
+                                            const Slot<PPL> &B, Slot<PPL> &C, const float (&qx)[PPL],
+                                            const float (&qy)[PPL], const float (&qz)[PPL], float (&ts)[PPL]) {
+    enter_vertex<PPL>(v, B, C, qx, qy, qz);
+    if (face) {
+        float al[PPL], be[PPL];
+        face_terms<PPL>(n, A, B, C, al, be);
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) ts[p] += atan2_eq8(al[p], be[p]);
+    }
+}
+
+// Two consecutive records: x enters slot X2 (window X0, X1), then y enters X0 (window
+// X1, X2).  Faces they complete are added to ts, two at a time through pair_angle.
+template <int PPL>
+__device__ __forceinline__ void push_pair(const float4 vx, const float4 nx, const float4 vy, const float4 ny,
+                                          unsigned bits, Slot<PPL> &X0, Slot<PPL> &X1, Slot<PPL> &X2,
+                                          const float (&qx)[PPL], const float (&qy)[PPL], const float (&qz)[PPL],
+                                          float (&ts)[PPL]) {
+    float a0[PPL], b0[PPL], a1[PPL], b1[PPL];
+    enter_vertex<PPL>(vx, X1, X2, qx, qy, qz);
+    if (bits & 1u) face_terms<PPL>(nx, X0, X1, X2, a0, b0);
+    enter_vertex<PPL>(vy, X2, X0, qx, qy, qz);
+    if (bits & 2u) face_terms<PPL>(ny, X1, X2, X0, a1, b1);
+    if ((bits & 3u) == 3u) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) ts[p] += pair_angle(a0[p], b0[p], a1[p], b1[p]);
+    } else if (bits & 1u) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) ts[p] += atan2_eq8(a0[p], b0[p]);
+    } else if (bits & 2u) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) ts[p] += atan2_eq8(a1[p], b1[p]);
     }
 }
 
@@ -224,8 +288,8 @@ __device__ __forceinline__ unsigned long long tile_face_mask(const float4 *tile,
 // range may start anywhere in the stream.  Records are staged through `tile` (LDS,
 // 2 * kRecTile float4) by the whole workgroup; each tile's per-point sum is folded into
 // the Neumaier pair (s, c).  The result depends only on the record stream and the tile
-// boundaries.  The window's three slots rotate statically (records are taken three at
-// a time; kRecTile is a multiple of three), so no register moves are needed.
+// boundaries.  The window's three slots rotate statically (records are taken six at a
+// time; kRecTile is a multiple of six), so no register moves are needed.
 template <int PPL>
 __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int64_t r0, int64_t r1, float4 *tile,
                                             const float (&qx)[PPL], const float (&qy)[PPL], const float (&qz)[PPL],
@@ -256,20 +320,24 @@ __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int6
 #pragma unroll
         for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
         int i = 0;
-        for (; i + 3 <= nt; i += 3) {
+        // six records per step: the window's slots return to their places after six
+        for (; i + 6 <= nt; i += 6) {
             const float4 *g = tile + 2 * i;
-            const float4 v0 = g[0], n0 = g[1], v1 = g[2], n1 = g[3], v2 = g[4], n2 = g[5];
             const unsigned bits = (unsigned)(fmask >> i);
-            push_record<PPL>(v0, bits & 1u, n0, S1, S2, S0, qx, qy, qz, ts);
-            push_record<PPL>(v1, bits & 2u, n1, S2, S0, S1, qx, qy, qz, ts);
-            push_record<PPL>(v2, bits & 4u, n2, S0, S1, S2, qx, qy, qz, ts);
+            push_pair<PPL>(g[0], g[1], g[2], g[3], bits, S1, S2, S0, qx, qy, qz, ts);
+            push_pair<PPL>(g[4], g[5], g[6], g[7], bits >> 2, S0, S1, S2, qx, qy, qz, ts);
+            push_pair<PPL>(g[8], g[9], g[10], g[11], bits >> 4, S2, S0, S1, qx, qy, qz, ts);
         }
-        // a partial group only occurs in the last tile of the range
+        // a partial step only occurs in the last tile of the range
         if (i < nt) {
+            const float4 *g = tile + 2 * i;
             const unsigned bits = (unsigned)(fmask >> i);
-            push_record<PPL>(tile[2 * i], bits & 1u, tile[2 * i + 1], S1, S2, S0, qx, qy, qz, ts);
-            if (i + 1 < nt)
-                push_record<PPL>(tile[2 * i + 2], bits & 2u, tile[2 * i + 3], S2, S0, S1, qx, qy, qz, ts);
+            const int m = nt - i;
+            push_record<PPL>(g[0], bits & 1u, g[1], S1, S2, S0, qx, qy, qz, ts);
+            if (m > 1) push_record<PPL>(g[2], bits & 2u, g[3], S2, S0, S1, qx, qy, qz, ts);
+            if (m > 2) push_record<PPL>(g[4], bits & 4u, g[5], S0, S1, S2, qx, qy, qz, ts);
+            if (m > 3) push_record<PPL>(g[6], bits & 8u, g[7], S1, S2, S0, qx, qy, qz, ts);
+            if (m > 4) push_record<PPL>(g[8], bits & 16u, g[9], S2, S0, S1, qx, qy, qz, ts);
         }
 #pragma unroll
         for (int p = 0; p < PPL; ++p) neumaier_add(s[p], c[p], ts[p]);

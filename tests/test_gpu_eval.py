@@ -60,7 +60,7 @@ def test_cubify_matches_oracle(dev, orc, case):
     assert F.shape == Fr.shape and V.shape == Vr.shape
     np.testing.assert_array_equal(F.cpu().numpy(), Fr)
     scale = max(np.abs(np.asarray(g.lo)).max(), np.abs(np.asarray(g.hi)).max())
-    assert np.abs(V.cpu().numpy() - Vr).max() <= 2 * np.spacing(np.float32(scale))
+    assert np.all(np.abs(V.cpu().numpy() - Vr) <= 2 * np.spacing(np.float32(scale)))
 
 
 def test_smoothing_matches_oracle(dev, orc):
