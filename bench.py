@@ -191,58 +191,59 @@ def bench_batched(reps: int, autotune: bool):
     }
 
 
-def bench_served(n_requests: int, load: float, fwd_pairs_per_s: float, adj_pairs_per_s: float):
+def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s: float):
     """Poisson trace through the continuous-batching server and through the plain FIFO
-    one-mesh-per-launch loop; p50/p99 latency and throughput of both.  The arrival rate
-    puts the offered GPU time at ``load`` of the wall clock, with a request's GPU time
-    estimated from the measured batched forward and adjoint pair rates."""
+    one-mesh-per-launch loop, at each offered load in ``loads``; p50/p99 latency and
+    throughput of both.  A load puts the offered GPU time at that fraction of the wall
+    clock, with a request's GPU time estimated from the measured batched forward and
+    adjoint pair rates.  The same requests (meshes, grids, targets) are replayed at every
+    load; only their arrival times scale."""
     import numpy as np
     import torch
-    import paper_2407_11272_amd as wn
     import wn_inputs as wi
     from paper_2407_11272_amd.serve import (GpuExecutor, Server, ServeRequest, latency_stats,
                                             run_plain_fifo)
-    base = wi.config5_trace(n_requests, 1.0)
+    base = wi.config5_trace(n_requests, 1.0)  # arrivals at rate 1; rate r divides them by r
     mean_pairs = float(np.mean([r.faces * r.res ** 3 * (2 if r.wants_grad else 1) for r in base]))
     mean_gpu_s = float(np.mean([r.faces * r.res ** 3 * (1.0 / fwd_pairs_per_s
                                                         + (1.0 / adj_pairs_per_s if r.wants_grad else 0.0))
                                 for r in base]))
-    rate = load / mean_gpu_s
-    trace = wi.config5_trace(n_requests, rate)
-    reqs = []
-    for r in trace:
-        w = r.build()
-        reqs.append(ServeRequest(r.rid, w.V.astype(np.float32), w.F.astype(np.int32), w.grid, r.arrival,
-                                 w.occ_mode, w.target))
-    total_pairs = sum(r.pairs for r in reqs)
+    built = [(r, r.build()) for r in base]
+    total_pairs = sum(int(np.prod(w.grid.n)) * len(w.F) * (2 if r.wants_grad else 1) for r, w in built)
+    sweep = []
+    for load in loads:
+        rate = load / mean_gpu_s
+        reqs = [ServeRequest(r.rid, w.V.astype(np.float32), w.F.astype(np.int32), w.grid, r.arrival / rate,
+                             w.occ_mode, w.target) for r, w in built]
 
-    def summary(out):
-        st = latency_stats(out)
-        span = max(o.done for o in out) - min(o.arrival for o in out)
-        st["throughput_pairs_per_s"] = total_pairs / span
-        st["makespan_s"] = span
-        return st
+        def summary(out):
+            st = latency_stats(out)
+            span = max(o.done for o in out) - min(o.arrival for o in out)
+            st["throughput_pairs_per_s"] = total_pairs / span
+            st["makespan_s"] = span
+            return st
 
-    srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
-                 slots=16, quantum_pairs=2e10)
-    served = srv.run_trace(reqs)
-    s_stats = summary(served)
-    s_stats["steps"] = srv.steps
-    s_stats["peak_active"] = srv.peak_active
-    del served
-    torch.cuda.synchronize()
-    p_stats = summary(run_plain_fifo(reqs))
+        srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
+                     slots=16, quantum_pairs=2e10)
+        served = srv.run_trace(reqs)
+        s_stats = summary(served)
+        s_stats["steps"] = srv.steps
+        s_stats["peak_active"] = srv.peak_active
+        del served
+        torch.cuda.synchronize()
+        p_stats = summary(run_plain_fifo(reqs))
+        sweep.append({"load": load, "rate_req_per_s": rate, "served": s_stats, "plain_fifo": p_stats,
+                      "p50_speedup": p_stats["p50_ms"] / s_stats["p50_ms"],
+                      "p99_speedup": p_stats["p99_ms"] / s_stats["p99_ms"]})
+        print(f"# served load {load}: p50 {s_stats['p50_ms']:.0f} / {p_stats['p50_ms']:.0f} ms, "
+              f"p99 {s_stats['p99_ms']:.0f} / {p_stats['p99_ms']:.0f} ms (served / plain)", file=sys.stderr,
+              flush=True)
     return {
         "workload": f"{n_requests} Poisson requests, 1k-100k faces log-uniform, grids 64^3/128^3/256^3, "
-                    f"30% with dL/dV (sigmoid-MSE)",
-        "rate_req_per_s": rate,
-        "load": load,
+                    f"30% with dL/dV (sigmoid-MSE), offered load swept",
         "mean_pairs_per_request": mean_pairs,
         "mean_gpu_ms_per_request": mean_gpu_s * 1e3,
-        "served": s_stats,
-        "plain_fifo": p_stats,
-        "p50_speedup": p_stats["p50_ms"] / s_stats["p50_ms"],
-        "p99_speedup": p_stats["p99_ms"] / s_stats["p99_ms"],
+        "sweep": sweep,
     }
 
 
@@ -418,12 +419,13 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="headline step only")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=96)
+    ap.add_argument("--served-requests", type=int, default=64)
     ap.add_argument("--rows", default="adjoint,batched,served,naive,flip,morph,eval",
                     help="comma list of extra rows to measure (adjoint, batched, served, naive, flip, morph, eval)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
-    ap.add_argument("--served-load", type=float, default=0.8)
+    ap.add_argument("--served-loads", default="0.5,0.8,0.95",
+                    help="comma list of offered loads (fractions of the GPU's measured capacity)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the three-records-per-face comparison launches (profiling runs)")
     args = ap.parse_args()
@@ -494,7 +496,8 @@ def main():
         rows["batched"] = bench_batched(3, not args.no_autotune)
     if "served" in want and args.served_requests > 0:
         print("# bench: served row", file=sys.stderr, flush=True)
-        rows["served"] = bench_served(args.served_requests, args.served_load, rows["batched"]["batched_pairs_per_s"],
+        rows["served"] = bench_served(args.served_requests, [float(x) for x in args.served_loads.split(",")],
+                                      rows["batched"]["batched_pairs_per_s"],
                                       rows["adjoint"]["adjoint_pairs_per_s"])
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)

@@ -240,15 +240,18 @@ WN_API wn_status wn_voxelize_batched(const wn_mesh_desc *desc, int32_t n, int32_
 WN_API size_t wn_workspace_size_batched(const wn_mesh_desc *desc, int32_t n);
 
 /*
- * Launch autotuner.  Times each candidate launch configuration (query points per
- * lane 1/2/4; for WN_OP_BATCHED also persistent workgroups per CU) on the given
- * work -- desc[0] alone for WN_OP_VOXELIZE, all n meshes for WN_OP_BATCHED -- and
- * records the fastest for that shape bucket (floor(log2) of faces and points, or of
- * total pairs and mesh count).  Later calls of that op and bucket use it.  A
- * configuration never changes results, only speed.  With the environment variable
+ * Launch autotuner.  Times each candidate launch configuration -- the point tile
+ * (query points per lane 1/2/4) times the record tile (1/2/4 tiles of 60 vertex records
+ * staged in LDS per barrier); for WN_OP_BATCHED also the fastest of those with at
+ * most 2 persistent workgroups per CU -- on the given work (desc[0] alone for
+ * WN_OP_VOXELIZE, all n meshes for WN_OP_BATCHED), and records the fastest for that
+ * shape bucket (floor(log2) of faces and points, or of total pairs and mesh count).
+ * Later calls of that op and bucket use it.  A configuration never changes results,
+ * only speed: the report carries a checksum of every candidate's outputs and
+ * "identical": true when they all agree.  With the environment variable
  * WN_AUTOTUNE_CACHE naming a file, choices persist there as JSON lines.  Writes the
- * outputs of desc as a side effect, synchronises `stream`, and writes a JSON report of
- * the timings to `report` (optional, NUL-terminated, truncated to report_len).
+ * outputs of desc as a side effect, synchronises `stream`, and writes the JSON report
+ * to `report` (optional, NUL-terminated, truncated to report_len).
  */
 WN_API wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws, size_t ws_bytes,
                              void *stream, char *report, size_t report_len);

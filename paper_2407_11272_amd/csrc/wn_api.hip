@@ -117,7 +117,7 @@ namespace {
 
 wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *R, int64_t nR,
                         const wn_grid *grid, const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau,
-                        float k, void *occ, void *ws, size_t ws_bytes, void *stream, int ppl) {
+                        float k, void *occ, void *ws, size_t ws_bytes, void *stream, const TuneConfig *force) {
     if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
     if (R == nullptr) {
         if (nR != 0) return WN_ERR_INVALID_ARG;
@@ -146,10 +146,11 @@ wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF
     const int split = fwd_split_count(nR, P);
     OccParams op{occ, occ_mode, tau, k};
 
-    if (!valid_ppl(ppl)) ppl = lookup_config(WN_OP_VOXELIZE, nF, P).ppl;
+    const TuneConfig cfg = force ? *force : lookup_config(WN_OP_VOXELIZE, nF, P);
     hipError_t e = launch_ws_reset(hdr, s);
     if (e == hipSuccess) e = launch_pack_records(V, nV, F, nF, R, nR, recs, hdr, s);
-    if (e == hipSuccess) e = launch_fwd(recs, nR, make_point_src(grid, Q), P, split, W, partials, op, ppl, s);
+    if (e == hipSuccess)
+        e = launch_fwd(recs, nR, make_point_src(grid, Q), P, split, W, partials, op, cfg.ppl, cfg.depth, s);
     return hip_status(e);
 }
 
@@ -160,7 +161,8 @@ extern "C" {
 wn_status wn_voxelize(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
                       const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
                       void *ws, size_t ws_bytes, void *stream) {
-    return voxelize_impl(V, nV, F, nF, nullptr, 0, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes, stream, 0);
+    return voxelize_impl(V, nV, F, nF, nullptr, 0, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes, stream,
+                         nullptr);
 }
 
 wn_status wn_voxelize_strips(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *strips,
@@ -169,7 +171,7 @@ wn_status wn_voxelize_strips(const float *V, int64_t nV, const int32_t *F, int64
                              void *stream) {
     if (strips == nullptr) return WN_ERR_INVALID_ARG;
     return voxelize_impl(V, nV, F, nF, strips, n_records, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes,
-                         stream, 0);
+                         stream, nullptr);
 }
 
 wn_status wn_build_strips(const int32_t *F, int64_t nF, int64_t nV, int32_t *records, int64_t capacity,
@@ -281,11 +283,10 @@ wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws,
     if (op != WN_OP_VOXELIZE && op != WN_OP_BATCHED) return WN_ERR_INVALID_ARG;
     if (ws == nullptr || !aligned256(ws)) return WN_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
     std::vector<TuneConfig> cands;
-    for (int ppl : {1, 2, 4}) {
-        cands.push_back(TuneConfig{ppl, 0});
-        if (op == WN_OP_BATCHED) cands.push_back(TuneConfig{ppl, 2});
-    }
+    for (int ppl : {1, 2, 4})
+        for (int depth : {1, 2, 4}) cands.push_back(TuneConfig{ppl, 0, depth});
     int64_t a = 0, b = 0;
     if (op == WN_OP_VOXELIZE) {
         a = desc[0].nF;
@@ -301,42 +302,68 @@ wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws,
         if (op == WN_OP_VOXELIZE) {
             const wn_mesh_desc &d = desc[0];
             return voxelize_impl(d.V, d.nV, d.F, d.nF, d.strips, d.strips ? d.n_strip_records : 0, &d.grid, nullptr,
-                                 0, d.W, d.occ_mode, d.tau, d.k, d.occ, ws, ws_bytes, stream, c.ppl);
+                                 0, d.W, d.occ_mode, d.tau, d.k, d.occ, ws, ws_bytes, stream, &c);
         }
         return run_batched(desc, n, WN_BATCH_NO_GRAPH, static_cast<char *>(ws), ws_bytes, s, &c);
     };
+    // Every candidate's outputs are checksummed (sum of the bit patterns of W), so the
+    // report shows whether any configuration changed a result.
+    auto checksum = [&](unsigned long long &out) -> wn_status {
+        bool reset = true;
+        for (int32_t m = 0; m < (op == WN_OP_VOXELIZE ? 1 : n); ++m) {
+            const wn_mesh_desc &d = desc[m];
+            const int64_t P = (int64_t)d.grid.n[0] * d.grid.n[1] * d.grid.n[2];
+            if (launch_checksum(d.W, P, hdr, reset, s) != hipSuccess) return WN_ERR_HIP;
+            reset = false;
+        }
+        if (hipMemcpyAsync(&out, &hdr->checksum, sizeof out, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return WN_ERR_HIP;
+        return WN_OK;
+    };
+    const int reps = op == WN_OP_BATCHED ? 1 : 2;  // a batch is long enough to time once
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return WN_ERR_HIP;
     std::string rep = "{\"op\": " + std::to_string(op) + ", \"candidates\": [";
     float best_ms = 0.0f;
     TuneConfig best = cands[0];
     wn_status st = WN_OK;
-    for (size_t i = 0; i < cands.size() && st == WN_OK; ++i) {
-        st = run(cands[i]);  // warm-up (and code-object load)
-        if (st != WN_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { st = WN_ERR_HIP; break; }
-        for (int r = 0; r < 2 && st == WN_OK; ++r) st = run(cands[i]);
-        if (st != WN_OK) break;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = WN_ERR_HIP; break; }
+    bool identical = true;
+    unsigned long long first_sum = 0;
+    auto time_one = [&](const TuneConfig &c, size_t i) -> wn_status {
+        wn_status r = run(c);  // warm-up (and code-object load)
+        if (r != WN_OK) return r;
+        unsigned long long sum = 0;
+        if ((r = checksum(sum)) != WN_OK) return r;
+        if (i == 0) first_sum = sum;
+        identical = identical && sum == first_sum;
+        if (hipEventRecord(e0, s) != hipSuccess) return WN_ERR_HIP;
+        for (int k = 0; k < reps && r == WN_OK; ++k) r = run(c);
+        if (r != WN_OK) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return WN_ERR_HIP;
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = WN_ERR_HIP; break; }
-        ms *= 0.5f;
-        char buf[128];
-        snprintf(buf, sizeof buf, "%s{\"ppl\": %d, \"wg\": %d, \"ms\": %.4f}", i ? ", " : "", cands[i].ppl,
-                 cands[i].wg_per_cu, ms);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return WN_ERR_HIP;
+        ms /= (float)reps;
+        char buf[160];
+        snprintf(buf, sizeof buf, "%s{\"ppl\": %d, \"wg\": %d, \"depth\": %d, \"ms\": %.4f, \"checksum\": %llu}",
+                 i ? ", " : "", c.ppl, c.wg_per_cu, c.depth, ms, sum);
         rep += buf;
         if (i == 0 || ms < best_ms) {
             best_ms = ms;
-            best = cands[i];
+            best = c;
         }
-    }
+        return WN_OK;
+    };
+    for (size_t i = 0; i < cands.size() && st == WN_OK; ++i) st = time_one(cands[i], i);
+    // for a batch, also try the fastest mapping with fewer persistent workgroups per CU
+    if (st == WN_OK && op == WN_OP_BATCHED) st = time_one(TuneConfig{best.ppl, 2, best.depth}, cands.size());
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != WN_OK) return st;
     store_config(op, a, b, best);
-    char buf[128];
-    snprintf(buf, sizeof buf, "], \"chosen\": {\"ppl\": %d, \"wg\": %d, \"ms\": %.4f}}", best.ppl, best.wg_per_cu,
-             best_ms);
+    char buf[192];
+    snprintf(buf, sizeof buf, "], \"chosen\": {\"ppl\": %d, \"wg\": %d, \"depth\": %d, \"ms\": %.4f}, \"identical\": %s}",
+             best.ppl, best.wg_per_cu, best.depth, best_ms, identical ? "true" : "false");
     rep += buf;
     if (report && report_len > 0) {
         strncpy(report, rep.c_str(), report_len - 1);
@@ -404,7 +431,7 @@ wn_status wn_morph_step(float *V, int64_t nV, const int32_t *F, int64_t nF, cons
                 st = hip_status(launch_naive_fwd(V, nV, F, nF, ps, P, W, none, sub, ppl, s));
             } else {
                 st = voxelize_impl(V, nV, F, nF, nullptr, 0, grid, nullptr, 0, W, WN_OCC_NONE, tau, k, nullptr, sub,
-                                   sub_bytes, stream, ppl);
+                                   sub_bytes, stream, nullptr);
             }
             if (st != WN_OK) return st;
         }

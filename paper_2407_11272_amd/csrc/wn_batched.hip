@@ -125,9 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_batched_pack(char *ws) {
 }
 
 // Persistent workgroups: take units from the cursor until the list is exhausted.
-template <int PPL>
+template <int PPL, int DEPTH>
 __global__ __launch_bounds__(kBlock) void k_batched_persistent(char *ws) {
-    __shared__ float4 tile[kRecTile * 2];
+    __shared__ float4 tile[kRecTile * 2 * DEPTH];
     __shared__ int64_t s_unit;
     __shared__ int32_t s_group;
     const BatchHeader *bh = bheader(ws);
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_persistent(char *ws) {
             s[p] = 0.0f;
             c[p] = 0.0f;
         }
-        sum_records<PPL>(recs + 2 * mh.rec_off, r0, r1, tile, qx, qy, qz, s, c);
+        sum_records<PPL, DEPTH>(recs + 2 * mh.rec_off, r0, r1, tile, qx, qy, qz, s, c);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             const int64_t idx = base + (int64_t)p * kBlock;
@@ -343,41 +343,36 @@ struct WsState {
     size_t cap = 0;
     hipEvent_t copied = nullptr;
     bool pending = false;
-    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (ppl, persistent grid, device)
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (ppl, depth, persistent grid, device)
 };
 
 std::mutex g_mu;
 std::map<const void *, WsState> g_state;
 hipStream_t g_capture = nullptr;
 
-int persistent_grid(int ppl, int wg_per_cu) {
+int persistent_grid(int ppl, int depth, int wg_per_cu) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    if (ppl == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_persistent<1>, kBlock, 0);
-    else if (ppl == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_persistent<4>, kBlock, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_persistent<2>, kBlock, 0);
+    const hipError_t e = with_config(ppl, depth, [&](auto P, auto D) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, k_batched_persistent<decltype(P)::value, decltype(D)::value>, kBlock, 0);
+    });
     if (e != hipSuccess || per < 1) per = 1;
     if (wg_per_cu > 0 && wg_per_cu < per) per = wg_per_cu;
     return cus * per;
 }
 
-hipError_t enqueue_kernels(char *ws, int ppl, int grid, hipStream_t s) {
+hipError_t enqueue_kernels(char *ws, int ppl, int depth, int grid, hipStream_t s) {
     hipError_t e = launch_ws_reset(reinterpret_cast<WsHeader *>(ws), s);
     if (e != hipSuccess) return e;
     k_batched_pack<<<1024, kBlock, 0, s>>>(ws);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ppl == 1)
-        k_batched_persistent<1><<<grid, kBlock, 0, s>>>(ws);
-    else if (ppl == 4)
-        k_batched_persistent<4><<<grid, kBlock, 0, s>>>(ws);
-    else
-        k_batched_persistent<2><<<grid, kBlock, 0, s>>>(ws);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = with_config(ppl, depth, [&](auto P, auto D) {
+        k_batched_persistent<decltype(P)::value, decltype(D)::value><<<grid, kBlock, 0, s>>>(ws);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
     k_batched_reduce<<<2048, kBlock, 0, s>>>(ws);
     return hipGetLastError();
 }
@@ -399,12 +394,13 @@ wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws,
                                                         : (int64_t)d[m].grid.n[0] * d[m].grid.n[1] * d[m].grid.n[2]);
     }
     const TuneConfig cfg = force ? *force : lookup_config(WN_OP_BATCHED, tot_pairs, n);
-    const int ppl = valid_ppl(cfg.ppl) ? cfg.ppl : 2;
+    const int ppl = valid_ppl(cfg.ppl) ? cfg.ppl : 1;
+    const int depth = valid_depth(cfg.depth) ? cfg.depth : 1;
     Plan plan;
     if (!make_plan(d, n, ppl, plan)) return WN_ERR_INVALID_ARG;
     if (ws_bytes < plan.total_bytes) return WN_ERR_WORKSPACE;
     if (plan.n_units > (int64_t)1 << 40) return WN_ERR_UNSUPPORTED;
-    const int grid = persistent_grid(ppl, cfg.wg_per_cu);
+    const int grid = persistent_grid(ppl, depth, cfg.wg_per_cu);
     if (grid <= 0) return WN_ERR_HIP;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return WN_ERR_HIP;
@@ -428,14 +424,14 @@ wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws,
     if (hipEventRecord(st.copied, s) != hipSuccess) return WN_ERR_HIP;
     st.pending = true;
 
-    if (flags & WN_BATCH_NO_GRAPH) return enqueue_kernels(ws, ppl, grid, s) == hipSuccess ? WN_OK : WN_ERR_HIP;
+    if (flags & WN_BATCH_NO_GRAPH) return enqueue_kernels(ws, ppl, depth, grid, s) == hipSuccess ? WN_OK : WN_ERR_HIP;
 
-    auto key = std::make_tuple(ppl, grid, dev);
+    auto key = std::make_tuple(ppl, depth, grid, dev);
     auto it = st.graphs.find(key);
     if (it == st.graphs.end()) {
         if (!g_capture && hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking) != hipSuccess) return WN_ERR_HIP;
         if (hipStreamBeginCapture(g_capture, hipStreamCaptureModeRelaxed) != hipSuccess) return WN_ERR_HIP;
-        hipError_t e = enqueue_kernels(ws, ppl, grid, g_capture);
+        hipError_t e = enqueue_kernels(ws, ppl, depth, grid, g_capture);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(g_capture, &graph);
         if (e != hipSuccess || e2 != hipSuccess || !graph) {

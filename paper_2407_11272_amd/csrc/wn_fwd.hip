@@ -78,11 +78,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_records(const float *__restrict
 // All-pairs forward.  Grid: x = point blocks of kBlock * PPL points, y = record splits.
 // With split == 1 the kernel writes W (scaled by 1 / 2 pi) and the occupancy map;
 // otherwise it writes the unscaled partial sum of split y to partials[y * nQ + idx].
-template <int PPL>
+template <int PPL, int DEPTH>
 __global__ __launch_bounds__(kBlock) void k_wn_fwd(const VRec *__restrict__ recs, int64_t nR, int64_t chunk,
                                                    PointSrc ps, int64_t nQ, float *__restrict__ W,
                                                    float *__restrict__ partials, OccParams occ) {
-    __shared__ float4 tile[kRecTile * 2];
+    __shared__ float4 tile[kRecTile * 2 * DEPTH];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * (kBlock * PPL) + tid;
     const int64_t r0 = (int64_t)blockIdx.y * chunk;
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_wn_fwd(const VRec *__restrict__ recs
         s[p] = 0.0f;
         c[p] = 0.0f;
     }
-    sum_records<PPL>(reinterpret_cast<const float4 *>(recs), r0, r1, tile, qx, qy, qz, s, c);
+    sum_records<PPL, DEPTH>(reinterpret_cast<const float4 *>(recs), r0, r1, tile, qx, qy, qz, s, c);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int64_t idx = base + (int64_t)p * kBlock;
@@ -223,29 +223,38 @@ hipError_t launch_pack_records(const float *V, int64_t nV, const int32_t *F, int
     return hipGetLastError();
 }
 
-template <int PPL>
-static hipError_t launch_fwd_ppl(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t nQ, int split, float *W,
-                                 float *partials, const OccParams &occ, hipStream_t s) {
-    const int64_t pblocks = (nQ + kBlock * PPL - 1) / (kBlock * PPL);
-    const int64_t chunk = fwd_split_chunk(nR, split);
-    dim3 g((unsigned)pblocks, (unsigned)split);
-    k_wn_fwd<PPL><<<g, kBlock, 0, s>>>(recs, nR, chunk, ps, nQ, W, split > 1 ? partials : nullptr, occ);
-    return hipGetLastError();
-}
-
 hipError_t launch_fwd(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t nQ, int split, float *W,
-                      float *partials, const OccParams &occ, int ppl, hipStream_t s) {
+                      float *partials, const OccParams &occ, int ppl, int depth, hipStream_t s) {
     if (nQ <= 0) return hipSuccess;
-    hipError_t e;
-    if (ppl == 1)
-        e = launch_fwd_ppl<1>(recs, nR, ps, nQ, split, W, partials, occ, s);
-    else if (ppl == 4)
-        e = launch_fwd_ppl<4>(recs, nR, ps, nQ, split, W, partials, occ, s);
-    else
-        e = launch_fwd_ppl<2>(recs, nR, ps, nQ, split, W, partials, occ, s);
+    const int64_t chunk = fwd_split_chunk(nR, split);
+    hipError_t e = with_config(ppl, depth, [&](auto P, auto D) {
+        constexpr int kP = decltype(P)::value, kD = decltype(D)::value;
+        const int64_t pblocks = (nQ + kBlock * kP - 1) / (kBlock * kP);
+        k_wn_fwd<kP, kD><<<dim3((unsigned)pblocks, (unsigned)split), kBlock, 0, s>>>(
+            recs, nR, chunk, ps, nQ, W, split > 1 ? partials : nullptr, occ);
+        return hipGetLastError();
+    });
     if (e != hipSuccess || split <= 1) return e;
     const int64_t rblocks = (nQ + kBlock - 1) / kBlock;
     k_wn_reduce<<<dim3((unsigned)rblocks), kBlock, 0, s>>>(partials, split, nQ, kInv2Pi, W, occ);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_checksum(const uint32_t *__restrict__ x, int64_t n,
+                                                     unsigned long long *__restrict__ out) {
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += x[i];
+    if (acc) atomicAdd(out, acc);  // integer sums: the result does not depend on the order
+}
+
+__global__ void k_checksum_reset(WsHeader *hdr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) hdr->checksum = 0ull;
+}
+
+hipError_t launch_checksum(const float *x, int64_t n, WsHeader *hdr, bool reset, hipStream_t s) {
+    if (reset) k_checksum_reset<<<1, 64, 0, s>>>(hdr);
+    if (n > 0) k_checksum<<<1024, kBlock, 0, s>>>(reinterpret_cast<const uint32_t *>(x), n, &hdr->checksum);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "wn.h"
@@ -59,7 +60,8 @@ struct WsHeader {
     int32_t bad_index;            // set to non-zero by a pack kernel on an out-of-range face index
     int32_t pad0;
     unsigned long long cursor;    // work-unit cursor of the persistent kernel
-    int32_t pad[60];
+    unsigned long long checksum;  // output checksum of an autotuner candidate
+    int32_t pad[58];
 };
 static_assert(sizeof(WsHeader) == kWsHeader, "header size");
 
@@ -96,25 +98,6 @@ __device__ __forceinline__ float atan2_eq8(float y, float x) {
 
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Half solid angle t_f(q) of one face record at point q (see the header comment).
-__device__ __forceinline__ float half_solid_angle(const float4 &a, const float4 &b, const float4 &c,
-                                                  float qx, float qy, float qz) {
-    const float r0x = a.x - qx, r0y = a.y - qy, r0z = a.z - qz;
-    const float r1x = a.w - qx, r1y = b.x - qy, r1z = b.y - qz;
-    const float r2x = b.z - qx, r2y = b.w - qy, r2z = c.x - qz;
-    const float l0 = fast_sqrt(r0x * r0x + r0y * r0y + r0z * r0z);
-    const float l1 = fast_sqrt(r1x * r1x + r1y * r1y + r1z * r1z);
-    const float l2 = fast_sqrt(r2x * r2x + r2y * r2y + r2z * r2z);
-    const float d01 = r0x * r1x + r0y * r1y + r0z * r1z;
-    const float d12 = r1x * r2x + r1y * r2y + r1z * r2z;
-    const float d20 = r2x * r0x + r2y * r0y + r2z * r0z;
-    const float p = l0 * l1 * l2;
-    const float beta = p + d01 * l2 + d12 * l0 + d20 * l1;
-    float alpha = r0x * c.y + r0y * c.z + r0z * c.w;
-    alpha = (p == 0.0f) ? 0.0f : alpha;
-    return atan2_eq8(alpha, beta);
-}
-
 // Neumaier step: (s, c) += x.
 __device__ __forceinline__ void neumaier_add(float &s, float &c, float x) {
     const float t = s + x;
@@ -148,35 +131,6 @@ struct PointSrc {
         }
     }
 };
-
-// Sum over faces [f0, f1) of the half solid angles at PPL points per lane.  The whole
-// workgroup stages kFaceTile face records at a time through `tile` (LDS, kFaceTile * 3
-// float4) and every lane reads each record (broadcast).  Each tile's per-point sum is
-// folded into the Neumaier pair (s, c), so the summation order -- and the result --
-// depends only on the face order and the tile boundaries, not on PPL or the launch.
-template <int PPL>
-__device__ __forceinline__ void sum_faces(const float4 *__restrict__ src, int32_t f0, int32_t f1, float4 *tile,
-                                          const float (&qx)[PPL], const float (&qy)[PPL], const float (&qz)[PPL],
-                                          float (&s)[PPL], float (&c)[PPL]) {
-    const int tid = threadIdx.x;
-    for (int32_t t0 = f0; t0 < f1; t0 += kFaceTile) {
-        const int nt = min(kFaceTile, f1 - t0);
-        __syncthreads();
-        if (tid < 3 * nt) tile[tid] = src[3 * (int64_t)t0 + tid];
-        __syncthreads();
-        float ts[PPL];
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
-#pragma unroll 2
-        for (int i = 0; i < nt; ++i) {
-            const float4 a = tile[3 * i], b = tile[3 * i + 1], cc = tile[3 * i + 2];
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) ts[p] += half_solid_angle(a, b, cc, qx[p], qy[p], qz[p]);
-        }
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) neumaier_add(s[p], c[p], ts[p]);
-    }
-}
 
 // One vertex of the record window, per query point: R = v - q, r = |R|, and the dot
 // product and length product with the previous record's vertex.
@@ -286,11 +240,12 @@ __device__ __forceinline__ unsigned long long tile_face_mask(const float4 *tile,
 // Sum of the half solid angles of the faces completed by records [r0, r1), at PPL
 // points per lane.  The two records before r0 (if any) prime the vertex window, so a
 // range may start anywhere in the stream.  Records are staged through `tile` (LDS,
-// 2 * kRecTile float4) by the whole workgroup; each tile's per-point sum is folded into
-// the Neumaier pair (s, c).  The result depends only on the record stream and the tile
-// boundaries.  The window's three slots rotate statically (records are taken six at a
-// time; kRecTile is a multiple of six), so no register moves are needed.
-template <int PPL>
+// 2 * kRecTile * DEPTH float4: DEPTH tiles per barrier) by the whole workgroup; each
+// tile's per-point sum is folded into the Neumaier pair (s, c).  The result depends only
+// on the record stream and the kRecTile boundaries, not on DEPTH.  The window's three
+// slots rotate statically (records are taken six at a time; kRecTile is a multiple of
+// six), so no register moves are needed.
+template <int PPL, int DEPTH>
 __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int64_t r0, int64_t r1, float4 *tile,
                                             const float (&qx)[PPL], const float (&qy)[PPL], const float (&qz)[PPL],
                                             float (&s)[PPL], float (&c)[PPL]) {
@@ -310,19 +265,23 @@ __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int6
         if (r0 >= 1) push_record<PPL>(src[2 * (r0 - 1)], false, zero, S0, S1, S2, qx, qy, qz, ts);
     }
     // window now: A = S1, B = S2
-    for (int64_t t0 = r0; t0 < r1; t0 += kRecTile) {
-        const int nt = (int)min((int64_t)kRecTile, r1 - t0);
+    for (int64_t t0 = r0; t0 < r1; t0 += kRecTile * DEPTH) {
+        const int nst = (int)min((int64_t)kRecTile * DEPTH, r1 - t0);
         __syncthreads();
-        if (tid < 2 * nt) tile[tid] = src[2 * t0 + tid];
+        for (int x = tid; x < 2 * nst; x += kBlock) tile[x] = src[2 * t0 + x];
         __syncthreads();
-        const unsigned long long fmask = tile_face_mask(tile, nt);
+#pragma unroll 1
+        for (int sub = 0; sub < DEPTH && sub * kRecTile < nst; ++sub) {
+        const float4 *tile_s = tile + 2 * sub * kRecTile;
+        const int nt = min(kRecTile, nst - sub * kRecTile);
+        const unsigned long long fmask = tile_face_mask(tile_s, nt);
         float ts[PPL];
 #pragma unroll
         for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
         int i = 0;
         // six records per step: the window's slots return to their places after six
         for (; i + 6 <= nt; i += 6) {
-            const float4 *g = tile + 2 * i;
+            const float4 *g = tile_s + 2 * i;
             const unsigned bits = (unsigned)(fmask >> i);
             push_pair<PPL>(g[0], g[1], g[2], g[3], bits, S1, S2, S0, qx, qy, qz, ts);
             push_pair<PPL>(g[4], g[5], g[6], g[7], bits >> 2, S0, S1, S2, qx, qy, qz, ts);
@@ -330,7 +289,7 @@ __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int6
         }
         // a partial step only occurs in the last tile of the range
         if (i < nt) {
-            const float4 *g = tile + 2 * i;
+            const float4 *g = tile_s + 2 * i;
             const unsigned bits = (unsigned)(fmask >> i);
             const int m = nt - i;
             push_record<PPL>(g[0], bits & 1u, g[1], S1, S2, S0, qx, qy, qz, ts);
@@ -341,6 +300,7 @@ __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int6
         }
 #pragma unroll
         for (int p = 0; p < PPL; ++p) neumaier_add(s[p], c[p], ts[p]);
+        }
     }
 }
 
@@ -421,7 +381,9 @@ hipError_t launch_pack(const float *V, int64_t nV, const int32_t *F, int64_t nF,
 hipError_t launch_pack_records(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *R,
                                int64_t nR, VRec *recs, WsHeader *hdr, hipStream_t s);
 hipError_t launch_fwd(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t nQ, int split,
-                      float *W, float *partials, const OccParams &occ, int ppl, hipStream_t s);
+                      float *W, float *partials, const OccParams &occ, int ppl, int depth, hipStream_t s);
+// Order-free checksum (sum of the bit patterns) of n floats into hdr->checksum.
+hipError_t launch_checksum(const float *x, int64_t n, WsHeader *hdr, bool reset, hipStream_t s);
 hipError_t launch_occ(const float *W, int64_t n, const OccParams &occ, hipStream_t s);
 // Fixed-order sum of [split][nQ] partials times `scale` into W, plus occupancy.
 hipError_t launch_split_reduce(const float *partials, int split, int64_t nQ, float scale, float *W,
@@ -480,10 +442,31 @@ wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws,
 struct TuneConfig {
     int32_t ppl;        // query points per lane: 1, 2 or 4
     int32_t wg_per_cu;  // persistent workgroups per CU (0 = as many as fit)
+    int32_t depth;      // record tiles staged in LDS per barrier: 1, 2 or 4
 };
 TuneConfig default_config(int32_t op);
 TuneConfig lookup_config(int32_t op, int64_t a, int64_t b);
 void store_config(int32_t op, int64_t a, int64_t b, const TuneConfig &c);
 bool valid_ppl(int32_t ppl);
+bool valid_depth(int32_t depth);
+
+// Calls f(PPL, DEPTH) with the configuration as compile-time constants
+// (std::integral_constant); an invalid pair returns hipErrorInvalidValue.
+template <typename Fn>
+hipError_t with_config(int32_t ppl, int32_t depth, Fn &&f) {
+    using std::integral_constant;
+    switch (ppl * 10 + depth) {
+        case 11: return f(integral_constant<int, 1>{}, integral_constant<int, 1>{});
+        case 12: return f(integral_constant<int, 1>{}, integral_constant<int, 2>{});
+        case 14: return f(integral_constant<int, 1>{}, integral_constant<int, 4>{});
+        case 21: return f(integral_constant<int, 2>{}, integral_constant<int, 1>{});
+        case 22: return f(integral_constant<int, 2>{}, integral_constant<int, 2>{});
+        case 24: return f(integral_constant<int, 2>{}, integral_constant<int, 4>{});
+        case 41: return f(integral_constant<int, 4>{}, integral_constant<int, 1>{});
+        case 42: return f(integral_constant<int, 4>{}, integral_constant<int, 2>{});
+        case 44: return f(integral_constant<int, 4>{}, integral_constant<int, 4>{});
+        default: return hipErrorInvalidValue;
+    }
+}
 
 }  // namespace wn

@@ -1,11 +1,11 @@
 // Launch-configuration cache and the autotuner entry point.
 //
-// A configuration (points per lane, persistent workgroups per CU) only changes how
-// work is mapped onto lanes and workgroups; the per-point order of the face sum is
-// fixed by the face tiles and chunks, so every configuration gives bit-identical
-// results.  Shapes are bucketed by floor(log2) of two size parameters.  With
+// A configuration (points per lane, record tiles staged per barrier, persistent
+// workgroups per CU) only changes how work is mapped onto lanes, workgroups and LDS; the
+// per-point order of the face sum is fixed by the record tiles and chunks, so every
+// configuration gives bit-identical results.  Shapes are bucketed by floor(log2) of two size parameters.  With
 // WN_AUTOTUNE_CACHE set, the cache is read from and written to that file as JSON
-// lines {"arch": "gfx950", "op": o, "a": i, "b": j, "ppl": p, "wg": w}.
+// lines {"arch": "gfx950", "op": o, "a": i, "b": j, "ppl": p, "wg": w, "depth": d}.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -53,11 +53,13 @@ void load_locked() {
     char line[512];
     while (fgets(line, sizeof line, f)) {
         char arch[32] = {0};
-        int op, a, b, ppl, wg;
-        if (sscanf(line, " {\"arch\": \"%31[^\"]\", \"op\": %d, \"a\": %d, \"b\": %d, \"ppl\": %d, \"wg\": %d}", arch,
-                   &op, &a, &b, &ppl, &wg) == 6 &&
-            strcmp(arch, "gfx950") == 0 && valid_ppl(ppl) && wg >= 0)
-            g_cache[Key{op, a, b}] = TuneConfig{ppl, wg};
+        int op, a, b, ppl, wg, depth = 1;
+        const int got = sscanf(line,
+                               " {\"arch\": \"%31[^\"]\", \"op\": %d, \"a\": %d, \"b\": %d, \"ppl\": %d, \"wg\": %d, "
+                               "\"depth\": %d}",
+                               arch, &op, &a, &b, &ppl, &wg, &depth);
+        if (got >= 6 && strcmp(arch, "gfx950") == 0 && valid_ppl(ppl) && wg >= 0 && valid_depth(depth))
+            g_cache[Key{op, a, b}] = TuneConfig{ppl, wg, depth};
     }
     fclose(f);
 }
@@ -69,8 +71,8 @@ void save_locked() {
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
     for (const auto &kv : g_cache)
-        fprintf(f, "{\"arch\": \"gfx950\", \"op\": %d, \"a\": %d, \"b\": %d, \"ppl\": %d, \"wg\": %d}\n", kv.first.op,
-                kv.first.a, kv.first.b, kv.second.ppl, kv.second.wg_per_cu);
+        fprintf(f, "{\"arch\": \"gfx950\", \"op\": %d, \"a\": %d, \"b\": %d, \"ppl\": %d, \"wg\": %d, \"depth\": %d}\n",
+                kv.first.op, kv.first.a, kv.first.b, kv.second.ppl, kv.second.wg_per_cu, kv.second.depth);
     fclose(f);
     rename(tmp.c_str(), path);
 }
@@ -78,8 +80,9 @@ void save_locked() {
 }  // namespace
 
 bool valid_ppl(int32_t ppl) { return ppl == 1 || ppl == 2 || ppl == 4; }
+bool valid_depth(int32_t depth) { return depth == 1 || depth == 2 || depth == 4; }
 
-TuneConfig default_config(int32_t) { return TuneConfig{1, 0}; }
+TuneConfig default_config(int32_t) { return TuneConfig{1, 0, 1}; }
 
 TuneConfig lookup_config(int32_t op, int64_t a, int64_t b) {
     std::lock_guard<std::mutex> lk(g_mu);

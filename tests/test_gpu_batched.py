@@ -123,12 +123,16 @@ def test_autotune_does_not_change_results(dev, tmp_path, monkeypatch):
     ref = _run([_job(V, F, g) for V, F, g in meshes])
     rep = wn.wn_autotune("batched", [_job(V, F, g) for V, F, g in meshes])
     print("autotune report", rep, flush=True)
-    assert rep["chosen"]["ppl"] in (1, 2, 4) and len(rep["candidates"]) == 6
+    # points per lane x record tiles per barrier, then the winner with fewer workgroups
+    assert rep["chosen"]["ppl"] in (1, 2, 4) and rep["chosen"]["depth"] in (1, 2, 4)
+    assert len(rep["candidates"]) == 10
+    assert rep["identical"] and len({c["checksum"] for c in rep["candidates"]}) == 1
     again = _run([_job(V, F, g) for V, F, g in meshes])
     for x, y in zip(ref, again):
         np.testing.assert_array_equal(x, y)
     rep = wn.wn_autotune("voxelize", [_job(*meshes[0])])
-    assert len(rep["candidates"]) == 3
+    assert len(rep["candidates"]) == 9
+    assert rep["identical"] and len({c["checksum"] for c in rep["candidates"]}) == 1
 
 
 def test_full_batch_64_meshes(dev, orc):
