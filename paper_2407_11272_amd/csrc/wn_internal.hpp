@@ -206,12 +206,14 @@ __device__ __forceinline__ void push_record(const float4 v, const bool face, con
 }
 
 // Two consecutive records: x enters slot X2 (window X0, X1), then y enters X0 (window
-// X1, X2).  Faces they complete are added to ts, two at a time through pair_angle.
+// X1, X2).  Faces they complete are added to ts two at a time through pair_angle: both
+// together, or a lone one with the lone face held over from an earlier pair (pa, pb;
+// `pending` is wave-uniform, like the face bits).
 template <int PPL>
 __device__ __forceinline__ void push_pair(const float4 vx, const float4 nx, const float4 vy, const float4 ny,
                                           unsigned bits, Slot<PPL> &X0, Slot<PPL> &X1, Slot<PPL> &X2,
                                           const float (&qx)[PPL], const float (&qy)[PPL], const float (&qz)[PPL],
-                                          float (&ts)[PPL]) {
+                                          float (&ts)[PPL], float (&pa)[PPL], float (&pb)[PPL], bool &pending) {
     float a0[PPL], b0[PPL], a1[PPL], b1[PPL];
     enter_vertex<PPL>(vx, X1, X2, qx, qy, qz);
     if (bits & 1u) face_terms<PPL>(nx, X0, X1, X2, a0, b0);
@@ -220,12 +222,25 @@ __device__ __forceinline__ void push_pair(const float4 vx, const float4 nx, cons
     if ((bits & 3u) == 3u) {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) ts[p] += pair_angle(a0[p], b0[p], a1[p], b1[p]);
-    } else if (bits & 1u) {
+    } else if (bits & 3u) {
+        float a[PPL], b[PPL];
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) ts[p] += atan2_eq8(a0[p], b0[p]);
-    } else if (bits & 2u) {
+        for (int p = 0; p < PPL; ++p) {
+            a[p] = (bits & 1u) ? a0[p] : a1[p];
+            b[p] = (bits & 1u) ? b0[p] : b1[p];
+        }
+        if (pending) {
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) ts[p] += atan2_eq8(a1[p], b1[p]);
+            for (int p = 0; p < PPL; ++p) ts[p] += pair_angle(pa[p], pb[p], a[p], b[p]);
+            pending = false;
+        } else {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                pa[p] = a[p];
+                pb[p] = b[p];
+            }
+            pending = true;
+        }
     }
 }
 
@@ -280,12 +295,18 @@ __device__ __forceinline__ void sum_records(const float4 *__restrict__ src, int6
         for (int p = 0; p < PPL; ++p) ts[p] = 0.0f;
         int i = 0;
         // six records per step: the window's slots return to their places after six
+        float pa[PPL], pb[PPL];
+        bool pending = false;
         for (; i + 6 <= nt; i += 6) {
             const float4 *g = tile_s + 2 * i;
             const unsigned bits = (unsigned)(fmask >> i);
-            push_pair<PPL>(g[0], g[1], g[2], g[3], bits, S1, S2, S0, qx, qy, qz, ts);
-            push_pair<PPL>(g[4], g[5], g[6], g[7], bits >> 2, S0, S1, S2, qx, qy, qz, ts);
-            push_pair<PPL>(g[8], g[9], g[10], g[11], bits >> 4, S2, S0, S1, qx, qy, qz, ts);
+            push_pair<PPL>(g[0], g[1], g[2], g[3], bits, S1, S2, S0, qx, qy, qz, ts, pa, pb, pending);
+            push_pair<PPL>(g[4], g[5], g[6], g[7], bits >> 2, S0, S1, S2, qx, qy, qz, ts, pa, pb, pending);
+            push_pair<PPL>(g[8], g[9], g[10], g[11], bits >> 4, S2, S0, S1, qx, qy, qz, ts, pa, pb, pending);
+        }
+        if (pending) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) ts[p] += atan2_eq8(pa[p], pb[p]);
         }
         // a partial step only occurs in the last tile of the range
         if (i < nt) {

@@ -85,6 +85,28 @@ def test_config2_full_size_sampled(dev, orc):
     assert np.isfinite(Wg).all()
 
 
+def test_largest_served_request_sampled(dev, orc):
+    """The largest request shape of the served workload (100 000 faces at 256^3,
+    1.7e12 pairs), in strip order and in three records per face; the oracle checks
+    1500 seeded voxels plus the first and last."""
+    import torch
+    import paper_2407_11272_amd as wn
+    req = wi.configs.Request(0, 0.0, 100_000, 256, False, 12345)
+    w = req.build()
+    V, F = wn.as_mesh(torch.as_tensor(w.V), torch.as_tensor(w.F))
+    R = torch.as_tensor(wn.wn_build_strips(np.asarray(w.F, np.int32), len(w.V))).cuda()
+    grid = wn.Grid.of(w.grid)
+    Ws = wn.wn_voxelize_strips(V, F, R, grid=grid).cpu().numpy().reshape(-1)
+    Wp = wn.wn_voxelize(V, F, grid=grid).cpu().numpy().reshape(-1)
+    assert Ws.shape == (256 ** 3,)
+    rng = np.random.default_rng(102)
+    idx = np.unique(np.concatenate([rng.integers(0, len(Ws), 1500), [0, len(Ws) - 1]]))
+    Q = orc.grid_points(w.grid)[idx]
+    _compare(orc, w.V, w.F, Q, Ws[idx], "served-max strips")
+    _compare(orc, w.V, w.F, Q, Wp[idx], "served-max plain")
+    assert np.isfinite(Ws).all() and np.isfinite(Wp).all()
+
+
 def test_config3_mesh_full_grid(dev, orc):
     """The 5120-face icosphere of the differentiable workload at 64^3 (forward)."""
     c = wi.config3_differentiable()
