@@ -94,12 +94,18 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
             float E[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) E[d] = e[0][d] + e[1][d] + e[2][d];
-            const float gb = gk * beta, ga = gk * alpha;
+            // Accumulated by three multiply-adds into each sum with the signs folded into
+            // the coefficients, so each is a two-operand accumulate (dual-issuable).
+            const float gb = gk * beta, nga = -(gk * alpha);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const float cb = gb * ri[j], ca = ga * ri[j], cd = ca * dd[j];
+                const float cb = gb * ri[j], nca = nga * ri[j], ncd = nca * dd[j];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) ts[3 * j + d] += cb * u[j][d] - ca * E[d] - cd * e[j][d];
+                for (int d = 0; d < 3; ++d) {
+                    ts[3 * j + d] = __builtin_fmaf(cb, u[j][d], ts[3 * j + d]);
+                    ts[3 * j + d] = __builtin_fmaf(nca, E[d], ts[3 * j + d]);
+                    ts[3 * j + d] = __builtin_fmaf(ncd, e[j][d], ts[3 * j + d]);
+                }
             }
         }
 #pragma unroll
