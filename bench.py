@@ -191,13 +191,15 @@ def bench_batched(reps: int, autotune: bool):
     }
 
 
-def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s: float):
+def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s: float, warmup_frac: float = 0.0):
     """Poisson trace through the continuous-batching server and through the plain FIFO
     one-mesh-per-launch loop, at each offered load in ``loads``; p50/p99 latency and
     throughput of both.  A load puts the offered GPU time at that fraction of the wall
     clock, with a request's GPU time estimated from the measured batched forward and
     adjoint pair rates.  The same requests (meshes, grids, targets) are replayed at every
-    load; only their arrival times scale."""
+    load; only their arrival times scale.  Statistics skip the first ``warmup_frac`` of
+    the requests (by arrival) and are also given per grid resolution; ``slowdown`` is a
+    request's latency over its own GPU time estimated from the same pair rates."""
     import numpy as np
     import torch
     import wn_inputs as wi
@@ -210,6 +212,10 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
                                 for r in base]))
     built = [(r, r.build()) for r in base]
     total_pairs = sum(int(np.prod(w.grid.n)) * len(w.F) * (2 if r.wants_grad else 1) for r, w in built)
+    res_of = {r.rid: r.res for r in base}
+    alone_s = {r.rid: r.faces * r.res ** 3 * (1.0 / fwd_pairs_per_s + (1.0 / adj_pairs_per_s if r.wants_grad else 0.0))
+               for r in base}
+    skip = set(sorted(res_of, key=lambda i: base[i].arrival)[:int(warmup_frac * len(base))])
     sweep = []
     for load in loads:
         rate = load / mean_gpu_s
@@ -217,11 +223,19 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
                              w.occ_mode, w.target) for r, w in built]
 
         def summary(out):
-            st = latency_stats(out)
             span = max(o.done for o in out) - min(o.arrival for o in out)
+            kept = [o for o in out if o.rid not in skip]
+            st = latency_stats(kept)
             st["throughput_pairs_per_s"] = total_pairs / span
             st["makespan_s"] = span
+            st["by_resolution"] = {str(res): latency_stats([o for o in kept if res_of[o.rid] == res])
+                                   for res in sorted(set(res_of.values()))}
+            sd = np.array([o.latency / alone_s[o.rid] for o in kept if np.isfinite(o.done)])
+            st["slowdown_p50"] = float(np.percentile(sd, 50)) if len(sd) else None
+            st["slowdown_p99"] = float(np.percentile(sd, 99)) if len(sd) else None
             return st
+
+        print(f"# served load {load}: continuous batching ({len(reqs)} requests)", file=sys.stderr, flush=True)
 
         srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
                      slots=16, quantum_pairs=2e10)
@@ -231,6 +245,7 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
         s_stats["peak_active"] = srv.peak_active
         del served
         torch.cuda.synchronize()
+        print(f"# served load {load}: plain FIFO", file=sys.stderr, flush=True)
         p_stats = summary(run_plain_fifo(reqs))
         sweep.append({"load": load, "rate_req_per_s": rate, "served": s_stats, "plain_fifo": p_stats,
                       "p50_speedup": p_stats["p50_ms"] / s_stats["p50_ms"],
@@ -240,7 +255,7 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
               flush=True)
     return {
         "workload": f"{n_requests} Poisson requests, 1k-100k faces log-uniform, grids 64^3/128^3/256^3, "
-                    f"30% with dL/dV (sigmoid-MSE), offered load swept",
+                    f"30% with dL/dV (sigmoid-MSE), offered load swept, first {warmup_frac:.0%} not counted",
         "mean_pairs_per_request": mean_pairs,
         "mean_gpu_ms_per_request": mean_gpu_s * 1e3,
         "sweep": sweep,
@@ -426,6 +441,8 @@ def main():
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-loads", default="0.5,0.8,0.95",
                     help="comma list of offered loads (fractions of the GPU's measured capacity)")
+    ap.add_argument("--served-warmup", type=float, default=0.0,
+                    help="fraction of the served requests (earliest arrivals) left out of the statistics")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the three-records-per-face comparison launches (profiling runs)")
     args = ap.parse_args()
@@ -498,7 +515,7 @@ def main():
         print("# bench: served row", file=sys.stderr, flush=True)
         rows["served"] = bench_served(args.served_requests, [float(x) for x in args.served_loads.split(",")],
                                       rows["batched"]["batched_pairs_per_s"],
-                                      rows["adjoint"]["adjoint_pairs_per_s"])
+                                      rows["adjoint"]["adjoint_pairs_per_s"], args.served_warmup)
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
         rows["naive"] = bench_naive(3)
