@@ -37,6 +37,7 @@ from .api import (  # noqa: F401
     wn_workspace_size,
 )
 from ._lib import WnError  # noqa: F401
+from .serve import GpuExecutor, Server, ServeRequest, ServeResult, run_plain_fifo  # noqa: F401
 from .autograd import (  # noqa: F401
     NaiveWindingNumber,
     SigmoidOccupancy,
