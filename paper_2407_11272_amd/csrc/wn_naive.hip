@@ -138,9 +138,10 @@ __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict_
             pts[tid] = make_float4(x, y, z, dLdW[t0 + tid]);
         }
         __syncthreads();
-        float ts[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) ts[i] = 0.0f;
+        // Per corner j the pair adds u + e_j x a, where u (the centroid part, shared by the
+        // three corners) and a = g r/|r|^3 depend on the point and e_j does not; so the
+        // tile sums U = sum u and A = sum a are formed first and corner j gets U + e_j x A.
+        float U[3] = {0.0f, 0.0f, 0.0f}, A[3] = {0.0f, 0.0f, 0.0f};
         for (int i = 0; i < nt; ++i) {
             const float4 q = pts[i];
             const float rx = cen[0] - q.x, ry = cen[1] - q.y, rz = cen[2] - q.z;
@@ -151,16 +152,19 @@ __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict_
             const float nr = N[0] * rx + N[1] * ry + N[2] * rz;
             const float kr = -nr * is2 * is3g;                  // -g <N, r> / |r|^5
             // centroid part: g (N/|r|^3 - 3 <N,r> r/|r|^5) / 3 = third * (N is3g) + kr * r
-            const float ux = third * N[0] * is3g + kr * rx;
-            const float uy = third * N[1] * is3g + kr * ry;
-            const float uz = third * N[2] * is3g + kr * rz;
-            const float ax = rx * is3g, ay = ry * is3g, az = rz * is3g;  // g r/|r|^3
+            U[0] += third * N[0] * is3g + kr * rx;
+            U[1] += third * N[1] * is3g + kr * ry;
+            U[2] += third * N[2] * is3g + kr * rz;
+            A[0] += rx * is3g;
+            A[1] += ry * is3g;
+            A[2] += rz * is3g;
+        }
+        float ts[9];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                ts[3 * j + 0] += ux + (e[j][1] * az - e[j][2] * ay);
-                ts[3 * j + 1] += uy + (e[j][2] * ax - e[j][0] * az);
-                ts[3 * j + 2] += uz + (e[j][0] * ay - e[j][1] * ax);
-            }
+        for (int j = 0; j < 3; ++j) {
+            ts[3 * j + 0] = U[0] + (e[j][1] * A[2] - e[j][2] * A[1]);
+            ts[3 * j + 1] = U[1] + (e[j][2] * A[0] - e[j][0] * A[2]);
+            ts[3 * j + 2] = U[2] + (e[j][0] * A[1] - e[j][1] * A[0]);
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) neumaier_add(s[i], c[i], ts[i]);
