@@ -35,12 +35,15 @@ PEAK_FP32 = 157.3e12   # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/cl
 PEAK_HBM = 8.0e12
 
 
-def source_hash() -> str:
+# Sources that define each profiled kernel (its code and everything it inlines).
+KERNEL_SOURCES = {"k_wn_fwd": ("wn_internal.hpp", "wn_fwd.hip")}
+
+
+def source_hash(kernel: str = "k_wn_fwd") -> str:
     h = hashlib.sha256()
     cdir = os.path.join(ROOT, "paper_2407_11272_amd", "csrc")
-    for name in sorted(os.listdir(cdir)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(cdir, name), "rb").read())
+    for name in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(cdir, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -53,7 +56,7 @@ def load_traffic(kernel: str, workload: str):
     try:
         d = json.load(open(p))
         e = d[kernel][workload]
-        if e.get("source_hash") != source_hash():
+        if e.get("source_hash") != source_hash(kernel):
             return None
         return float(e["bytes_per_launch"])
     except Exception:
@@ -262,7 +265,7 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
     }
 
 
-def bench_naive(reps: int):
+def bench_naive(reps: int, autotune: bool = True):
     """Eq. 4 naive flux sum: forward on the 19 000-face union at 128^3, adjoint on the
     5120-face icosphere at 64^3 (both with one centroid sample per face)."""
     import torch
@@ -273,6 +276,7 @@ def bench_naive(reps: int):
     V, F = wn.as_mesh(torch.as_tensor(c2.V), torch.as_tensor(c2.F))
     g2 = wn.Grid.of(c2.grid)
     W = torch.empty(tuple(g2.n), dtype=torch.float32, device="cuda")
+    tune = wn.wn_autotune("naive", [wn.MeshJob(V, F, g2, "none", W=W)]) if autotune else None
     f_s, _ = time_steps(lambda: wn.wn_voxelize_naive(V, F, grid=g2, W=W), reps, 1, stream)
     pairs_f = g2.size * len(c2.F)
     c3 = wi.config3_differentiable()
@@ -284,6 +288,7 @@ def bench_naive(reps: int):
     pairs_b = g3.size * len(c3.F)
     return {
         "forward_workload": "ellipsoid-union-19000f-128cube, one centroid sample per face",
+        "autotune": tune["chosen"] if tune else None,
         "forward_ms": f_s / reps * 1e3,
         "forward_pairs_per_s": pairs_f * reps / f_s,
         "adjoint_workload": "icosphere-s4-5120f-64cube, random dL/dW",
@@ -518,7 +523,7 @@ def main():
                                       rows["adjoint"]["adjoint_pairs_per_s"], args.served_warmup)
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
-        rows["naive"] = bench_naive(3)
+        rows["naive"] = bench_naive(3, not args.no_autotune)
     if "eval" in want:
         print("# bench: evaluation-chain row", file=sys.stderr, flush=True)
         rows["eval"] = bench_eval(3)

@@ -83,6 +83,7 @@ typedef int32_t wn_status;
 #define WN_OP_SMOOTH 7 /* wn_workspace_size(WN_OP_SMOOTH, nV, nF, 0)                              */
 #define WN_OP_SAMPLE 8 /* wn_workspace_size(WN_OP_SAMPLE, 0, nF, n samples)                       */
 #define WN_OP_NN 9     /* wn_workspace_size(WN_OP_NN, |A|, |B|, 0)                                 */
+#define WN_OP_NAIVE 10 /* wn_autotune of wn_voxelize_naive (its workspace is WN_OP_VOXELIZE's)     */
 
 /* Which integral drives a morphing iteration (wn_morph_step). */
 #define WN_INTEGRAL_GWN 0   /* Eq. 5 with Eq. 7 solid angles (wn_voxelize / wn_backward)      */
@@ -243,8 +244,9 @@ WN_API size_t wn_workspace_size_batched(const wn_mesh_desc *desc, int32_t n);
  * Launch autotuner.  Times each candidate launch configuration -- the point tile
  * (query points per lane 1/2/4) times the record tile (1/2/4 tiles of 60 vertex records
  * staged in LDS per barrier); for WN_OP_BATCHED also the fastest of those with at
- * most 2 persistent workgroups per CU -- on the given work (desc[0] alone for
- * WN_OP_VOXELIZE, all n meshes for WN_OP_BATCHED), and records the fastest for that
+ * most 2 persistent workgroups per CU; for WN_OP_NAIVE (wn_voxelize_naive) the point
+ * tile alone -- on the given work (desc[0] alone for WN_OP_VOXELIZE and WN_OP_NAIVE,
+ * all n meshes for WN_OP_BATCHED), and records the fastest for that
  * shape bucket (floor(log2) of faces and points, or of total pairs and mesh count).
  * Later calls of that op and bucket use it.  A configuration never changes results,
  * only speed: the report carries a checksum of every candidate's outputs and

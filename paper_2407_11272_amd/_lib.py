@@ -32,6 +32,7 @@ WN_OP_CUBIFY = 6
 WN_OP_SMOOTH = 7
 WN_OP_SAMPLE = 8
 WN_OP_NN = 9
+WN_OP_NAIVE = 10
 
 WN_INTEGRAL_GWN = 0
 WN_INTEGRAL_NAIVE = 1

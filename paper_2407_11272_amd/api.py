@@ -544,11 +544,11 @@ def wn_voxelize_batched(jobs, graph: bool = True, workspace: tuple | None = None
 
 
 def wn_autotune(op: str, jobs) -> dict:
-    """Time the launch candidates for ``op`` ('voxelize' uses jobs[0], 'batched' all
-    jobs) and record the fastest; returns the report (synchronises)."""
+    """Time the launch candidates for ``op`` ('voxelize' and 'naive' use jobs[0],
+    'batched' all jobs) and record the fastest; returns the report (synchronises)."""
     import json
     lib = L.load()
-    code = {"voxelize": L.WN_OP_VOXELIZE, "batched": L.WN_OP_BATCHED}[op]
+    code = {"voxelize": L.WN_OP_VOXELIZE, "batched": L.WN_OP_BATCHED, "naive": L.WN_OP_NAIVE}[op]
     arr = _descs(jobs)
     dev = jobs[0].V.device
     if code == L.WN_OP_BATCHED:

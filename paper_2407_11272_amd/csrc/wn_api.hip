@@ -226,9 +226,13 @@ wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, 
                         ws_bytes, static_cast<hipStream_t>(stream));
 }
 
-wn_status wn_voxelize_naive(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
-                            const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
-                            void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+wn_status naive_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid, const float *Q,
+                     int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ, void *ws, size_t ws_bytes,
+                     void *stream, const TuneConfig *force) {
     if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
     const int64_t P = query_count(grid, Q, nQ);
     if (P < 0) return WN_ERR_INVALID_ARG;
@@ -242,8 +246,19 @@ wn_status wn_voxelize_naive(const float *V, int64_t nV, const int32_t *F, int64_
     if (ws == nullptr || !aligned256(ws) || ws_bytes < naive_fwd_workspace(nF, P)) return WN_ERR_WORKSPACE;
     if (P == 0) return WN_OK;
     OccParams op{occ, occ_mode, tau, k};
-    return hip_status(launch_naive_fwd(V, nV, F, nF, make_point_src(grid, Q), P, W, op, static_cast<char *>(ws),
-                                       lookup_config(WN_OP_VOXELIZE, nF, P).ppl, static_cast<hipStream_t>(stream)));
+    const int ppl = (force ? *force : lookup_config(WN_OP_NAIVE, nF, P)).ppl;
+    return hip_status(launch_naive_fwd(V, nV, F, nF, make_point_src(grid, Q), P, W, op, static_cast<char *>(ws), ppl,
+                                       static_cast<hipStream_t>(stream)));
+}
+
+}  // namespace
+
+extern "C" {
+
+wn_status wn_voxelize_naive(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
+                            const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau, float k, void *occ,
+                            void *ws, size_t ws_bytes, void *stream) {
+    return naive_impl(V, nV, F, nF, grid, Q, nQ, W, occ_mode, tau, k, occ, ws, ws_bytes, stream, nullptr);
 }
 
 wn_status wn_backward_naive(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
@@ -280,15 +295,16 @@ size_t wn_workspace_size_batched(const wn_mesh_desc *desc, int32_t n) {
 wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws, size_t ws_bytes, void *stream,
                       char *report, size_t report_len) {
     if (desc == nullptr || n < 1) return WN_ERR_INVALID_ARG;
-    if (op != WN_OP_VOXELIZE && op != WN_OP_BATCHED) return WN_ERR_INVALID_ARG;
+    if (op != WN_OP_VOXELIZE && op != WN_OP_BATCHED && op != WN_OP_NAIVE) return WN_ERR_INVALID_ARG;
     if (ws == nullptr || !aligned256(ws)) return WN_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
     std::vector<TuneConfig> cands;
     for (int ppl : {1, 2, 4})
-        for (int depth : {1, 2, 4}) cands.push_back(TuneConfig{ppl, 0, depth});
+        for (int depth : {1, 2, 4})
+            if (op != WN_OP_NAIVE || depth == 1) cands.push_back(TuneConfig{ppl, 0, depth});
     int64_t a = 0, b = 0;
-    if (op == WN_OP_VOXELIZE) {
+    if (op == WN_OP_VOXELIZE || op == WN_OP_NAIVE) {
         a = desc[0].nF;
         b = (int64_t)desc[0].grid.n[0] * desc[0].grid.n[1] * desc[0].grid.n[2];
     } else {
@@ -299,6 +315,11 @@ wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws,
         b = n;
     }
     auto run = [&](const TuneConfig &c) -> wn_status {
+        if (op == WN_OP_NAIVE) {
+            const wn_mesh_desc &d = desc[0];
+            return naive_impl(d.V, d.nV, d.F, d.nF, &d.grid, nullptr, 0, d.W, d.occ_mode, d.tau, d.k, d.occ, ws,
+                              ws_bytes, stream, &c);
+        }
         if (op == WN_OP_VOXELIZE) {
             const wn_mesh_desc &d = desc[0];
             return voxelize_impl(d.V, d.nV, d.F, d.nF, d.strips, d.strips ? d.n_strip_records : 0, &d.grid, nullptr,
@@ -310,7 +331,7 @@ wn_status wn_autotune(int32_t op, const wn_mesh_desc *desc, int32_t n, void *ws,
     // report shows whether any configuration changed a result.
     auto checksum = [&](unsigned long long &out) -> wn_status {
         bool reset = true;
-        for (int32_t m = 0; m < (op == WN_OP_VOXELIZE ? 1 : n); ++m) {
+        for (int32_t m = 0; m < (op == WN_OP_BATCHED ? n : 1); ++m) {
             const wn_mesh_desc &d = desc[m];
             const int64_t P = (int64_t)d.grid.n[0] * d.grid.n[1] * d.grid.n[2];
             if (launch_checksum(d.W, P, hdr, reset, s) != hipSuccess) return WN_ERR_HIP;
@@ -421,7 +442,7 @@ wn_status wn_morph_step(float *V, int64_t nV, const int32_t *F, int64_t nF, cons
     float *dLdV = reinterpret_cast<float *>(base + l.dldv);
     float *loss_slot = reinterpret_cast<float *>(base + l.loss);
     const PointSrc ps = make_point_src(grid, nullptr);
-    const int ppl = lookup_config(WN_OP_VOXELIZE, nF, P).ppl;
+    const int ppl = lookup_config(WN_OP_NAIVE, nF, P).ppl;
     const bool naive = integral == WN_INTEGRAL_NAIVE;
     for (int32_t it = 0; it < iters; ++it) {
         wn_status st = WN_OK;
