@@ -107,6 +107,19 @@ def test_largest_served_request_sampled(dev, orc):
     assert np.isfinite(Ws).all() and np.isfinite(Wp).all()
 
 
+def test_convenience_voxelize_uses_strips_for_host_faces(dev, orc):
+    """voxelize() with host faces runs the strip order, with device faces the default
+    order; both match the oracle and each other to rounding."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere()
+    Wh = wn.voxelize(np.asarray(c.V, np.float32), c.F, grid=c.grid).cpu().numpy().reshape(-1)
+    Wd = wn.voxelize(torch.as_tensor(np.asarray(c.V, np.float32)).cuda(),
+                     torch.as_tensor(c.F, dtype=torch.int32).cuda(), grid=c.grid).cpu().numpy().reshape(-1)
+    _compare(orc, c.V, c.F, orc.grid_points(c.grid), Wh, "voxelize host faces")
+    assert np.abs(Wh - Wd).max() <= 1e-5
+
+
 def test_config3_mesh_full_grid(dev, orc):
     """The 5120-face icosphere of the differentiable workload at 64^3 (forward)."""
     c = wi.config3_differentiable()
