@@ -163,6 +163,27 @@ def test_orientation_flip_and_determinism(dev, orc):
     np.testing.assert_allclose(Wr, -W1, atol=2e-6)
 
 
+@pytest.mark.parametrize("scale", [1e-3, 1e4, 1e7, 1e11])
+def test_scale_invariance_across_the_pair_range(dev, scale):
+    """W is invariant under a common scaling of mesh and points.  Scaled by 1e7 and 1e11
+    the two-face products leave the normal FP32 range, so the per-face fallback of the
+    paired ATAN2 runs; 1e-3 and 1e4 stay on the fast path."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere()
+    V = np.asarray(c.V, np.float64)
+    R = torch.as_tensor(wn.wn_build_strips(c.F, len(V))).cuda()
+    F = torch.as_tensor(c.F, dtype=torch.int32).cuda()
+    g = c.grid
+    W1 = wn.wn_voxelize_strips(torch.as_tensor(V, dtype=torch.float32).cuda(), F, R, grid=g).cpu().numpy()
+    gs = wn.Grid(tuple(np.float32(x * scale) for x in g.lo), tuple(np.float32(x * scale) for x in g.hi), g.n)
+    Ws = wn.wn_voxelize_strips(torch.as_tensor(V * scale, dtype=torch.float32).cuda(), F, R,
+                               grid=gs).cpu().numpy()
+    err = np.abs(Ws - W1)
+    print(f"[scale {scale:g}] max|W(scaled) - W| = {err.max():.2e}", flush=True)
+    assert np.isfinite(Ws).all() and err.max() <= 1e-4
+
+
 def test_cube_closed_forms(dev, orc):
     """Closed unit cube: centre 1, vertices 1/8 (the faces at the vertex give 0), far 0."""
     V, F = wi.cube_mesh(0.0, 1.0)
