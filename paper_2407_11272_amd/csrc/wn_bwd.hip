@@ -30,6 +30,14 @@ constexpr int kPointTile = kBlock;  // points staged per tile (one per thread)
 
 // dL/dv partial sums of one face over a range of points.  Grid: x = face blocks,
 // y = point splits.  partials layout: [split][9][nF].
+//
+// Per pair the corner vector is gk r_j^-1 (beta u_j - alpha E - alpha (e_k . e_l) e_j)
+// with E = e_0 + e_1 + e_2 and gk = dL/dW / (alpha^2 + beta^2) (the projection folded
+// in: e_j . u_j = alpha and e_j . (e_k + e_l) = beta - 1 - e_k . e_l).  The first term
+// is not summed per pair.  With w = gk beta / (r_0 r_1 r_2) it is w (R_k x R_l), and
+// R_k x R_l = C_j + D_j x R_0 with D_j = v_k - v_l, C_0 = N = (v_1 - v_0) x (v_2 - v_0)
+// and C_1 = C_2 = 0, so over a tile of points it is C_j sum(w) + D_j x sum(w R_0): four
+// sums per pair instead of nine products.  alpha = (R_0 . N) / (r_0 r_1 r_2) (Eq. 7).
 __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ soup, int32_t nF, PointSrc ps,
                                                    int64_t nQ, int64_t chunkP, const float *__restrict__ dLdW,
                                                    float *__restrict__ partials) {
@@ -40,6 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
     f = live ? f : nF - 1;
     const FaceRec r = soup[f];
     const float v[3][3] = {{r.a.x, r.a.y, r.a.z}, {r.a.w, r.b.x, r.b.y}, {r.b.z, r.b.w, r.c.x}};
+    const float N[3] = {r.c.y, r.c.z, r.c.w};
 
     float s[9], c[9];
 #pragma unroll
@@ -56,30 +65,25 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
             pts[tid] = make_float4(x, y, z, dLdW[t0 + tid]);
         }
         __syncthreads();
-        float ts[9];
+        float ts[9], sw = 0.0f, sq[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < 9; ++i) ts[i] = 0.0f;
         for (int i = 0; i < nt; ++i) {
             const float4 q = pts[i];
-            float e[3][3], ri[3];
+            float R[3][3], e[3][3], ri[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const float rx = v[j][0] - q.x, ry = v[j][1] - q.y, rz = v[j][2] - q.z;
-                const float l2 = rx * rx + ry * ry + rz * rz;
+                R[j][0] = v[j][0] - q.x;
+                R[j][1] = v[j][1] - q.y;
+                R[j][2] = v[j][2] - q.z;
+                const float l2 = R[j][0] * R[j][0] + R[j][1] * R[j][1] + R[j][2] * R[j][2];
                 ri[j] = (l2 > 0.0f) ? __builtin_amdgcn_rsqf(l2) : 0.0f;
-                e[j][0] = rx * ri[j];
-                e[j][1] = ry * ri[j];
-                e[j][2] = rz * ri[j];
+                e[j][0] = R[j][0] * ri[j];
+                e[j][1] = R[j][1] * ri[j];
+                e[j][2] = R[j][2] * ri[j];
             }
-            float u[3][3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int k = (j + 1) % 3, l = (j + 2) % 3;
-                u[j][0] = e[k][1] * e[l][2] - e[k][2] * e[l][1];
-                u[j][1] = e[k][2] * e[l][0] - e[k][0] * e[l][2];
-                u[j][2] = e[k][0] * e[l][1] - e[k][1] * e[l][0];
-            }
-            const float alpha = e[0][0] * u[0][0] + e[0][1] * u[0][1] + e[0][2] * u[0][2];
+            const float rho = ri[0] * ri[1] * ri[2];
+            const float alpha = rho * (R[0][0] * N[0] + R[0][1] * N[1] + R[0][2] * N[2]);
             float dd[3];  // dd[j] = e_k . e_l for (j, k, l) cyclic
             dd[2] = e[0][0] * e[1][0] + e[0][1] * e[1][1] + e[0][2] * e[1][2];
             dd[0] = e[1][0] * e[2][0] + e[1][1] * e[2][1] + e[1][2] * e[2][2];
@@ -87,26 +91,34 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
             const float beta = 1.0f + dd[2] + dd[0] + dd[1];
             const float den = alpha * alpha + beta * beta;
             const float gk = (den > 0.0f) ? q.w * __builtin_amdgcn_rcpf(den) : 0.0f;
-            // The projected vector of corner j, w - (w . e_j) e_j with w = beta u_j -
-            // alpha (e_k + e_l), equals beta u_j - alpha E - alpha (e_k . e_l) e_j, where
-            // E = e_0 + e_1 + e_2 (because e_j . u_j = alpha and e_j . (e_k + e_l) =
-            // beta - 1 - e_k . e_l).
+            const float w = gk * beta * rho, nga = -(gk * alpha);
+            sw += w;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sq[d] = __builtin_fmaf(w, R[0][d], sq[d]);
             float E[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) E[d] = e[0][d] + e[1][d] + e[2][d];
-            // Accumulated by three multiply-adds into each sum with the signs folded into
-            // the coefficients, so each is a two-operand accumulate (dual-issuable).
-            const float gb = gk * beta, nga = -(gk * alpha);
+            // Two multiply-adds into each sum with the signs folded into the
+            // coefficients, so each is a two-operand accumulate (dual-issuable).
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const float cb = gb * ri[j], nca = nga * ri[j], ncd = nca * dd[j];
+                const float nca = nga * ri[j], ncd = nca * dd[j];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    ts[3 * j + d] = __builtin_fmaf(cb, u[j][d], ts[3 * j + d]);
                     ts[3 * j + d] = __builtin_fmaf(nca, E[d], ts[3 * j + d]);
                     ts[3 * j + d] = __builtin_fmaf(ncd, e[j][d], ts[3 * j + d]);
                 }
             }
+        }
+        // the beta u_j terms of the tile: C_j sum(w) + D_j x sum(w R_0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int k = (j + 1) % 3, l = (j + 2) % 3;
+            const float D[3] = {v[k][0] - v[l][0], v[k][1] - v[l][1], v[k][2] - v[l][2]};
+            const float cj = (j == 0) ? sw : 0.0f;
+            ts[3 * j + 0] += cj * N[0] + (D[1] * sq[2] - D[2] * sq[1]);
+            ts[3 * j + 1] += cj * N[1] + (D[2] * sq[0] - D[0] * sq[2]);
+            ts[3 * j + 2] += cj * N[2] + (D[0] * sq[1] - D[1] * sq[0]);
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) neumaier_add(s[i], c[i], ts[i]);
