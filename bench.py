@@ -194,7 +194,8 @@ def bench_batched(reps: int, autotune: bool):
     }
 
 
-def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s: float, warmup_frac: float = 0.0):
+def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s: float, warmup_frac: float = 0.0,
+                 policy: str = "edf"):
     """Poisson trace through the continuous-batching server and through the plain FIFO
     one-mesh-per-launch loop, at each offered load in ``loads``; p50/p99 latency and
     throughput of both.  A load puts the offered GPU time at that fraction of the wall
@@ -202,7 +203,9 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
     adjoint pair rates.  The same requests (meshes, grids, targets) are replayed at every
     load; only their arrival times scale.  Statistics skip the first ``warmup_frac`` of
     the requests (by arrival) and are also given per grid resolution; ``slowdown`` is a
-    request's latency over its own GPU time estimated from the same pair rates."""
+    request's latency over its own GPU time estimated from the same pair rates.  The
+    server's policy is ``policy``; its adjoint cost per pair and deadline rate come from
+    the same measured rates."""
     import numpy as np
     import torch
     import wn_inputs as wi
@@ -241,7 +244,8 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
         print(f"# served load {load}: continuous batching ({len(reqs)} requests)", file=sys.stderr, flush=True)
 
         srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
-                     slots=16, quantum_pairs=2e10)
+                     slots=16, quantum_pairs=2e10, policy=policy, adjoint_cost=fwd_pairs_per_s / adj_pairs_per_s,
+                     rate_pairs=fwd_pairs_per_s)
         served = srv.run_trace(reqs)
         s_stats = summary(served)
         s_stats["steps"] = srv.steps
@@ -259,6 +263,8 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
     return {
         "workload": f"{n_requests} Poisson requests, 1k-100k faces log-uniform, grids 64^3/128^3/256^3, "
                     f"30% with dL/dV (sigmoid-MSE), offered load swept, first {warmup_frac:.0%} not counted",
+        "policy": policy,
+        "adjoint_cost": fwd_pairs_per_s / adj_pairs_per_s,
         "mean_pairs_per_request": mean_pairs,
         "mean_gpu_ms_per_request": mean_gpu_s * 1e3,
         "sweep": sweep,
@@ -446,6 +452,8 @@ def main():
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-loads", default="0.5,0.8,0.95",
                     help="comma list of offered loads (fractions of the GPU's measured capacity)")
+    ap.add_argument("--served-policy", default="edf", choices=("edf", "fair", "age"),
+                    help="scheduler policy of the served row (earliest deadline first, or shares)")
     ap.add_argument("--served-warmup", type=float, default=0.0,
                     help="fraction of the served requests (earliest arrivals) left out of the statistics")
     ap.add_argument("--no-compare", action="store_true",
@@ -520,7 +528,8 @@ def main():
         print("# bench: served row", file=sys.stderr, flush=True)
         rows["served"] = bench_served(args.served_requests, [float(x) for x in args.served_loads.split(",")],
                                       rows["batched"]["batched_pairs_per_s"],
-                                      rows["adjoint"]["adjoint_pairs_per_s"], args.served_warmup)
+                                      rows["adjoint"]["adjoint_pairs_per_s"], args.served_warmup,
+                                      args.served_policy)
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
         rows["naive"] = bench_naive(3, not args.no_autotune)

@@ -173,6 +173,42 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
                       void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * The adjoint of wn_backward in pieces, so that a scheduler can interleave a large
+ * adjoint with other work (Section 2.4's gradients, served in slices).  The points are
+ * cut into splits of `chunk` consecutive points (chunk = 0: the size wn_backward uses,
+ * see wn_backward_chunk); each split's per-corner sums are kept apart in the workspace
+ * and added in split order at the end.  A sequence of calls on one workspace
+ *     flags WN_BWD_BEGIN (pack the faces), then point ranges [p0, p0 + n) that together
+ *     cover every split once, in any order and grouping, the last with WN_BWD_END
+ *     (add the splits, group corners per vertex, write dLdV and optionally dLdT)
+ * gives the same bits as one call (p0 = 0, n = nQ, both flags) with the same chunk, and
+ * that call with chunk = 0 is wn_backward.  Flags may be combined with a range in one
+ * call (BEGIN runs before the range, END after it).
+ *   p0:    a multiple of the chunk;  n: a multiple of the chunk, or p0 + n = nQ;
+ *   dLdW:  indexed by the global point number (only [p0, p0 + n) is read);
+ *   V, F, grid / Q, nQ, chunk: the same in every call of a sequence;
+ *   dLdV:  needed with WN_BWD_END; dLdT optional, as in wn_backward;
+ *   ws:    wn_workspace_size_backward(nV, nF, nQ, chunk) bytes, holding the sequence's
+ *          state between calls (splits not covered by a range read stale values).
+ * At most 65535 splits.  Argument errors return WN_ERR_INVALID_ARG before any launch.
+ */
+#define WN_BWD_BEGIN 1
+#define WN_BWD_END 2
+WN_API wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                                   const wn_grid *grid, const float *Q, int64_t nQ,
+                                   const float *dLdW, int64_t chunk, int64_t p0, int64_t n,
+                                   int32_t flags, float *dLdV, float *dLdT,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* The split size in points for (nF, nQ) and a requested chunk (chunk > 0 is returned
+ * as is; 0 gives the default); -1 on negative arguments. */
+WN_API int64_t wn_backward_chunk(int64_t nF, int64_t nQ, int64_t chunk);
+
+/* Workspace bytes of wn_backward_range with this chunk (0 on invalid sizes or more than
+ * 65535 splits). */
+WN_API size_t wn_workspace_size_backward(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk);
+
+/*
  * The naive discretisation of the flux integral (Section 2.1, Eq. 4): one sample per
  * face at its centroid c_f with the area-weighted normal N_f / 2,
  * N_f = (v1 - v0) x (v2 - v0):

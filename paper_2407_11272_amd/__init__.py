@@ -23,6 +23,7 @@ from .api import (  # noqa: F401
     Workspace,
     as_mesh,
     voxelize,
+    SlicedBackward,
     wn_backward,
     wn_backward_naive,
     wn_voxelize_naive,

@@ -39,6 +39,9 @@ WN_INTEGRAL_NAIVE = 1
 
 WN_BATCH_NO_GRAPH = 1
 
+WN_BWD_BEGIN = 1
+WN_BWD_END = 2
+
 #: every symbol include/wn.h declares
 EXPORTED = (
     "wn_workspace_size",
@@ -48,6 +51,9 @@ EXPORTED = (
     "wn_occupancy",
     "wn_sigmoid_mse",
     "wn_backward",
+    "wn_backward_range",
+    "wn_backward_chunk",
+    "wn_workspace_size_backward",
     "wn_voxelize_naive",
     "wn_backward_naive",
     "wn_voxelize_batched",
@@ -125,6 +131,12 @@ def load():
     lib.wn_sigmoid_mse.argtypes = [vp, vp, i64, f32, f32, vp, vp, vp, sz, vp]
     lib.wn_backward.restype = i32
     lib.wn_backward.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, vp, vp, vp, sz, vp]
+    lib.wn_backward_range.restype = i32
+    lib.wn_backward_range.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i64, i64, i64, i32, vp, vp, vp, sz, vp]
+    lib.wn_backward_chunk.restype = i64
+    lib.wn_backward_chunk.argtypes = [i64, i64, i64]
+    lib.wn_workspace_size_backward.restype = sz
+    lib.wn_workspace_size_backward.argtypes = [i64, i64, i64, i64]
     lib.wn_voxelize_naive.restype = i32
     lib.wn_voxelize_naive.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i32, f32, f32, vp, vp, sz, vp]
     lib.wn_backward_naive.restype = i32

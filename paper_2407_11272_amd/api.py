@@ -191,6 +191,68 @@ def wn_voxelize_naive(V, F, grid: Grid | None = None, Q: torch.Tensor | None = N
     return wn_voxelize(V, F, grid=grid, Q=Q, _entry="wn_voxelize_naive", **kw)
 
 
+class SlicedBackward:
+    """The adjoint of one (mesh, grid or point list) computed over point ranges in
+    separate calls (``wn_backward_range``): :meth:`begin`, then :meth:`points` for ranges
+    that together cover every split of ``chunk`` points once, then :meth:`end`.  The
+    result has the same bits as one call over all points with the same chunk; with
+    chunk 0 that is :func:`wn_backward`.  The object owns its workspace, which holds the
+    per-split sums between calls; all calls go to the current stream of V's device."""
+
+    def __init__(self, V, F, grid: Grid | None = None, Q: torch.Tensor | None = None, chunk: int = 0):
+        _check_mesh(V, F)
+        if (grid is None) == (Q is None):
+            raise ValueError("pass exactly one of grid or Q")
+        self.lib = L.load()
+        self.V, self.F, self.dev = V, F, V.device
+        if grid is not None:
+            self.grid = Grid.of(grid)
+            self._gc = self.grid.to_c()
+            self.P, self._nQ, self._qptr = self.grid.size, 0, ctypes.c_void_p(0)
+        else:
+            self.grid, self._gc = None, None
+            self.P = self._nQ = Q.shape[0]
+            self._Q = Q
+            self._qptr = _ptr(Q)
+        self.chunk = int(self.lib.wn_backward_chunk(F.shape[0], self.P, int(chunk)))
+        if self.chunk < 1:
+            raise ValueError("invalid chunk")
+        self.splits = -(-self.P // self.chunk) if self.P else 0
+        need = self.lib.wn_workspace_size_backward(V.shape[0], F.shape[0], self.P, int(chunk))
+        if need == 0:
+            raise ValueError("sizes out of range for the adjoint (at most 65535 splits)")
+        self._buf = torch.empty(need + 256, dtype=torch.uint8, device=self.dev)
+        base = self._buf.data_ptr()
+        self._ws, self._wsb = ctypes.c_void_p(base + (-base) % 256), need
+        self._req_chunk = int(chunk)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return self._wsb
+
+    def _call(self, dLdW, p0, n, flags, dLdV=None, dLdT=None):
+        g = ctypes.byref(self._gc) if self._gc is not None else None
+        st = self.lib.wn_backward_range(_ptr(self.V), self.V.shape[0], _ptr(self.F), self.F.shape[0], g, self._qptr,
+                                        self._nQ, _ptr(dLdW), self._req_chunk, int(p0), int(n), flags, _ptr(dLdV),
+                                        _ptr(dLdT), self._ws, self._wsb, _stream_handle(self.dev))
+        L.check("wn_backward_range", st)
+
+    def begin(self):
+        self._call(None, 0, 0, L.WN_BWD_BEGIN)
+
+    def points(self, p0: int, n: int, dLdW: torch.Tensor):
+        """Add points [p0, p0 + n); dLdW is indexed by the global point number."""
+        if dLdW.dtype != torch.float32 or not dLdW.is_contiguous() or dLdW.numel() != self.P or not dLdW.is_cuda:
+            raise ValueError("dLdW must be a contiguous float32 device tensor with one entry per point")
+        self._call(dLdW, p0, n, 0)
+
+    def end(self, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None) -> torch.Tensor:
+        if dLdV is None:
+            dLdV = torch.empty_like(self.V)
+        self._call(None, 0, 0, L.WN_BWD_END, dLdV, dLdT)
+        return dLdV
+
+
 def wn_backward_naive(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None, **kw):
     """Adjoint of :func:`wn_voxelize_naive`; arguments as :func:`wn_backward`."""
     return wn_backward(V, F, dLdW, grid=grid, Q=Q, _entry="wn_backward_naive", **kw)

@@ -39,10 +39,11 @@ constexpr int kPointTile = kBlock;  // points staged per tile (one per thread)
 // and C_1 = C_2 = 0, so over a tile of points it is C_j sum(w) + D_j x sum(w R_0): four
 // sums per pair instead of nine products.  alpha = (R_0 . N) / (r_0 r_1 r_2) (Eq. 7).
 __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ soup, int32_t nF, PointSrc ps,
-                                                   int64_t nQ, int64_t chunkP, const float *__restrict__ dLdW,
-                                                   float *__restrict__ partials) {
+                                                   int64_t nQ, int64_t chunkP, int32_t split0,
+                                                   const float *__restrict__ dLdW, float *__restrict__ partials) {
     __shared__ float4 pts[kPointTile];
     const int tid = threadIdx.x;
+    const int64_t sy = (int64_t)split0 + blockIdx.y;  // this block's point split
     int32_t f = (int32_t)blockIdx.x * kBlock + tid;
     const bool live = f < nF;
     f = live ? f : nF - 1;
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
 #pragma unroll
     for (int i = 0; i < 9; ++i) s[i] = c[i] = 0.0f;
 
-    const int64_t p0 = (int64_t)blockIdx.y * chunkP;
+    const int64_t p0 = sy * chunkP;
     const int64_t p1 = min(nQ, p0 + chunkP);
     for (int64_t t0 = p0; t0 < p1; t0 += kPointTile) {
         const int nt = (int)min((int64_t)kPointTile, p1 - t0);
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
     }
     if (live) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) partials[((int64_t)blockIdx.y * 9 + i) * nF + f] = s[i] + c[i];
+        for (int i = 0; i < 9; ++i) partials[(sy * 9 + i) * nF + f] = s[i] + c[i];
     }
 }
 
@@ -266,17 +267,28 @@ struct BwdPlan {
     size_t off_soup, off_part, off_T, off_keys, off_vals, off_keys2, off_vals2, off_tmp, off_vs, off_ve, total;
 };
 
-BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ) {
-    BwdPlan p{};
+}  // namespace
+
+// Points per split: the caller's chunk, or by default about 8192 waves over the face
+// waves and splits (at most 512 splits), rounded up to whole point tiles.
+int64_t bwd_chunk(int64_t nF, int64_t nQ, int64_t chunk) {
+    if (chunk > 0) return chunk;
     const int64_t face_waves = (nF + 63) / 64;
     int64_t sp = (8192 + face_waves - 1) / (face_waves > 0 ? face_waves : 1);
     if (sp > 512) sp = 512;
     const int64_t max_by_points = (nQ + kPointTile - 1) / kPointTile;
     if (sp > max_by_points) sp = max_by_points;
     if (sp < 1) sp = 1;
-    int64_t chunk = (nQ + sp - 1) / sp;
-    chunk = (chunk + kPointTile - 1) / kPointTile * kPointTile;
-    if (chunk < kPointTile) chunk = kPointTile;
+    int64_t c = (nQ + sp - 1) / sp;
+    c = (c + kPointTile - 1) / kPointTile * kPointTile;
+    return c < kPointTile ? kPointTile : c;
+}
+
+namespace {
+
+BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk_arg = 0) {
+    BwdPlan p{};
+    const int64_t chunk = bwd_chunk(nF, nQ, chunk_arg);
     p.chunkP = chunk;
     p.split = (int)((nQ + chunk - 1) / chunk);
     if (p.split < 1) p.split = 1;
@@ -318,7 +330,9 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ) { return plan_backward(nV, nF, nQ).total; }
+size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk) {
+    return plan_backward(nV, nF, nQ, chunk).total;
+}
 
 // The flip reuses the adjoint's layout with no points: the corner sort buffers, vertex
 // bounds, and the face-normal table in place of the per-split partials.
@@ -361,13 +375,40 @@ wn_status run_flip(const float *V, int64_t nV, const int32_t *F, int64_t nF, flo
 }
 
 wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps, int64_t nQ,
-                       const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes, hipStream_t s,
-                       bool naive) {
-    const BwdPlan p = plan_backward(nV, nF, nQ);
+                       const float *dLdW, int64_t chunk, int64_t p0, int64_t n, int flags, float *dLdV, float *dLdT,
+                       char *ws, size_t ws_bytes, hipStream_t s, bool naive) {
+    const BwdPlan p = plan_backward(nV, nF, nQ, chunk);
     if (ws_bytes < p.total) return WN_ERR_WORKSPACE;
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
     FaceRec *soup = reinterpret_cast<FaceRec *>(ws + p.off_soup);
     float *partials = reinterpret_cast<float *>(ws + p.off_part);
+    hipError_t e = hipSuccess;
+
+    // begin: face records (and the index check) for the whole call sequence
+    if (flags & kBwdBegin) {
+        if ((e = launch_ws_reset(hdr, s)) != hipSuccess) return WN_ERR_HIP;
+        if (nV > 0 && nF > 0 && (e = launch_pack(V, nV, F, nF, soup, hdr, s)) != hipSuccess) return WN_ERR_HIP;
+    }
+    // points [p0, p0 + n): the splits they cover (whole splits, or the ragged last one)
+    if (n > 0 && nV > 0 && nF > 0) {
+        const int64_t s0 = p0 / p.chunkP, s1 = (p0 + n + p.chunkP - 1) / p.chunkP;
+        if (naive) {
+            e = launch_naive_bwd(soup, (int32_t)nF, ps, nQ, p.chunkP, (int32_t)s0, (int32_t)(s1 - s0), dLdW, partials,
+                                 s);
+        } else {
+            k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)(s1 - s0)), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.chunkP,
+                                                                                  (int32_t)s0, dLdW, partials);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return WN_ERR_HIP;
+    }
+    if (!(flags & kBwdEnd) || nV == 0) return WN_OK;
+
+    // end: the splits added in order, then corners grouped per vertex
+    if (nF == 0) {
+        k_fill_i32<<<blocks_for(3 * nV), kBlock, 0, s>>>(reinterpret_cast<int32_t *>(dLdV), 3 * nV, 0);
+        return hipGetLastError() == hipSuccess ? WN_OK : WN_ERR_HIP;
+    }
     float *T = dLdT ? dLdT : reinterpret_cast<float *>(ws + p.off_T);
     int32_t *keys = reinterpret_cast<int32_t *>(ws + p.off_keys);
     int32_t *vals = reinterpret_cast<int32_t *>(ws + p.off_vals);
@@ -375,25 +416,7 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
     int32_t *vals2 = reinterpret_cast<int32_t *>(ws + p.off_vals2);
     int32_t *vs = reinterpret_cast<int32_t *>(ws + p.off_vs);
     int32_t *ve = reinterpret_cast<int32_t *>(ws + p.off_ve);
-
-    hipError_t e = launch_ws_reset(hdr, s);
-    if (e != hipSuccess) return WN_ERR_HIP;
-    if (nV == 0) return WN_OK;
-    if (nF == 0) {
-        k_fill_i32<<<blocks_for(3 * nV), kBlock, 0, s>>>(reinterpret_cast<int32_t *>(dLdV), 3 * nV, 0);
-        return hipGetLastError() == hipSuccess ? WN_OK : WN_ERR_HIP;
-    }
-    e = launch_pack(V, nV, F, nF, soup, hdr, s);
-    if (e != hipSuccess) return WN_ERR_HIP;
     if (nQ > 0) {
-        if (naive) {
-            e = launch_naive_bwd(soup, (int32_t)nF, ps, nQ, p.chunkP, p.split, dLdW, partials, s);
-        } else {
-            k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)p.split), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.chunkP,
-                                                                                  dLdW, partials);
-            e = hipGetLastError();
-        }
-        if (e != hipSuccess) return WN_ERR_HIP;
         k_bwd_reduce<<<blocks_for(9 * nF), kBlock, 0, s>>>(partials, p.split, (int32_t)nF, naive ? kInv8Pi : kInv2Pi,
                                                             T);
     } else {

@@ -414,11 +414,22 @@ hipError_t launch_sigmoid_mse(const float *W, const float *target, int64_t n, fl
 int loss_blocks(int64_t n);
 
 // Backward pieces (wn_bwd.hip).  `naive` selects the adjoint of the Eq. 4 sum instead of
-// the exact solid-angle field.
-size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ);
+// the exact solid-angle field.  The points are cut into splits of `chunk` points (0: the
+// default size, bwd_chunk) whose partial sums are kept apart and added in split order at
+// the end, so a call sequence BEGIN, any ranges of whole splits, END gives the same bits
+// as one call over all points with the same chunk.
+constexpr int kBwdBegin = 1, kBwdEnd = 2;
+int64_t bwd_chunk(int64_t nF, int64_t nQ, int64_t chunk);
+size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk = 0);
 wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
-                       int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes,
-                       hipStream_t s, bool naive = false);
+                       int64_t nQ, const float *dLdW, int64_t chunk, int64_t p0, int64_t n, int flags, float *dLdV,
+                       float *dLdT, char *ws, size_t ws_bytes, hipStream_t s, bool naive = false);
+inline wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
+                              int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes,
+                              hipStream_t s, bool naive = false) {
+    return run_backward(V, nV, F, nF, ps, nQ, dLdW, 0, 0, nQ, kBwdBegin | kBwdEnd, dLdV, dLdT, ws, ws_bytes, s,
+                        naive);
+}
 
 // Naive flux integral of Eq. 4 (wn_naive.hip).
 constexpr float kInv8Pi = 0.0397887357729738340f;
@@ -445,7 +456,7 @@ hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, 
                        float b2, float eps, hipStream_t s);
 // The adjoint pair kernel of Eq. 4 (defined in wn_naive.hip, launched by run_backward).
 hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int64_t chunkP,
-                            int split, const float *dLdW, float *partials, hipStream_t s);
+                            int32_t split0, int32_t nsplit, const float *dLdW, float *partials, hipStream_t s);
 
 // Flipping duplication (wn_bwd.hip).
 size_t flip_workspace(int64_t nV, int64_t nF);

@@ -106,10 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_naive_fwd(const NaiveRec *__restrict
 
 // Adjoint pair kernel: grid x = face blocks, y = point splits; partials [split][9][nF].
 __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict__ soup, int32_t nF, PointSrc ps,
-                                                      int64_t nQ, int64_t chunkP, const float *__restrict__ dLdW,
-                                                      float *__restrict__ partials) {
+                                                      int64_t nQ, int64_t chunkP, int32_t split0,
+                                                      const float *__restrict__ dLdW, float *__restrict__ partials) {
     __shared__ float4 pts[kBlock];
     const int tid = threadIdx.x;
+    const int64_t sy = (int64_t)split0 + blockIdx.y;  // this block's point split
     int32_t f = (int32_t)blockIdx.x * kBlock + tid;
     const bool live = f < nF;
     f = live ? f : nF - 1;
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict_
     float s[9], c[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) s[i] = c[i] = 0.0f;
-    const int64_t p0 = (int64_t)blockIdx.y * chunkP;
+    const int64_t p0 = sy * chunkP;
     const int64_t p1 = min(nQ, p0 + chunkP);
     for (int64_t t0 = p0; t0 < p1; t0 += kBlock) {
         const int nt = (int)min((int64_t)kBlock, p1 - t0);
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict_
     }
     if (live) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) partials[((int64_t)blockIdx.y * 9 + i) * nF + f] = s[i] + c[i];
+        for (int i = 0; i < 9; ++i) partials[(sy * 9 + i) * nF + f] = s[i] + c[i];
     }
 }
 
@@ -219,9 +220,9 @@ hipError_t launch_naive_fwd(const float *V, int64_t nV, const int32_t *F, int64_
 }
 
 hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int64_t chunkP,
-                            int split, const float *dLdW, float *partials, hipStream_t s) {
-    k_naive_bwd<<<dim3((unsigned)((nF + kBlock - 1) / kBlock), (unsigned)split), kBlock, 0, s>>>(
-        soup, nF, ps, nQ, chunkP, dLdW, partials);
+                            int32_t split0, int32_t nsplit, const float *dLdW, float *partials, hipStream_t s) {
+    k_naive_bwd<<<dim3((unsigned)((nF + kBlock - 1) / kBlock), (unsigned)nsplit), kBlock, 0, s>>>(
+        soup, nF, ps, nQ, chunkP, split0, dLdW, partials);
     return hipGetLastError();
 }
 

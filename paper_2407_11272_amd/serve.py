@@ -7,31 +7,42 @@ caller wants d(loss)/d(vertices)).  The loop
     fits in the HBM budget (a request larger than the whole budget is rejected);
   * keeps each admitted request's mesh, grid outputs and gradient buffers resident
     on the device until it completes;
-  * every scheduler step gives each request still in its forward phase a fair share
-    of a bounded amount of work (a slice of its voxels) and runs all slices in ONE
-    batched persistent launch, so requests that arrive while others are on the GPU
-    join the next step and their work overlaps;
-  * when a request's last slice has been launched, its loss and adjoint are queued on
-    a second stream (overlapping with later forward steps);
+  * cuts every request into units of work: slices of its voxels for the forward pass
+    and, for gradient requests, whole point splits of the adjoint (its per-split sums
+    are kept apart and added in split order at the end);
+  * every scheduler step spends a bounded amount of work.  Under the default
+    earliest-deadline policy each request gets a deadline at admission (its arrival
+    plus a slack proportional to its estimated service time) and the step's budget goes
+    to requests in deadline order, so short requests overtake long ones while a long
+    request, once its deadline is the earliest, is not starved.  Under the share
+    policies every request gets a slice in proportion to a weight (equal, or growing
+    with its age).  All forward slices of a step run in ONE batched persistent launch,
+    then the adjoint units, on one stream;
   * completion times come from device events, so latency = completion - arrival is
     not delayed by host polling.
 
-A voxel's winding number does not depend on which slice or batch computed it, so each
-result is bit-identical alone and in any mix.  The scheduling logic talks to the GPU
-only through an executor object; tests drive it with a simulated executor on the CPU.
+A voxel's winding number does not depend on which slice or batch computed it, and a
+request's adjoint split size depends only on its own size, so each result is
+bit-identical alone and in any mix.  The scheduling logic talks to the GPU only through
+an executor object; tests drive it with a simulated executor on the CPU.
 """
 from __future__ import annotations
 
 import collections
 import math
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
-POINT_QUANTUM = 2048  # slice sizes are multiples of this many voxels
-SHARE_POLICY = "age"  # "fair": equal shares; "age": shares grow with time since arrival
-AGE_TAU = 0.25        # seconds of waiting that double a request's share under "age"
+POINT_QUANTUM = 2048      # forward slices are multiples of this many voxels
+POLICY = "edf"            # "edf": earliest deadline first; "fair": equal shares; "age": shares grow with age
+AGE_TAU = 0.25            # seconds of waiting that double a request's share under "age"
+ADJOINT_COST = 2.8        # cost of one adjoint (point, face) pair in forward pairs
+RATE_PAIRS = 1.4e12       # forward pairs per second, for the deadline estimate
+DEADLINE_SLACK = 1.0      # deadline = arrival + DEADLINE_SLACK * estimated service + DEADLINE_BASE
+DEADLINE_BASE = 0.05      # seconds
+ADJOINT_MAX_CHUNK = 8192   # points per adjoint split (at most; small requests use smaller splits)
 
 
 @dataclass
@@ -82,9 +93,29 @@ class _Active:
     req: ServeRequest
     res: ServeResult
     footprint: int
+    adj_chunk: int = 0
+    deadline: float = 0.0
     state: object = None        # executor-owned per-request state
-    next_point: int = 0
-    launched_all: bool = False
+    next_point: int = 0         # forward: next voxel to launch
+    launched_all: bool = False  # forward: every slice launched
+    adj_next: int = 0           # adjoint: next point to launch
+    adj_ended: bool = False     # adjoint: the last unit (with the final sum) launched
+
+    @property
+    def all_launched(self) -> bool:
+        return self.launched_all and (self.adj_ended or not self.req.wants_grad)
+
+
+def _lib():
+    from . import _lib as L
+    return L.load()
+
+
+def adjoint_chunk(nF: int, P: int) -> int:
+    """Points per adjoint split of a served gradient request: the library's default for
+    (nF, P), at most ADJOINT_MAX_CHUNK, so that a step's worth of splits fills the GPU
+    whatever the face count.  Depends only on the request."""
+    return int(min(ADJOINT_MAX_CHUNK, _lib().wn_backward_chunk(max(0, nF), max(0, P), 0)))
 
 
 def footprint_bytes(req: ServeRequest, slice_points: int) -> int:
@@ -95,10 +126,10 @@ def footprint_bytes(req: ServeRequest, slice_points: int) -> int:
     chunks = max(1, -(-nF // 4096))
     b += 48 * nF + (4 * chunks * min(P, slice_points) if chunks > 1 else 0)
     if req.wants_grad:
-        # target, dL/dW, dL/dV, and the adjoint's workspace: face records, per-split corner
-        # partials (about 8192 wave64s of faces), corner sums, sort buffers, vertex bounds
-        splits = min(512, max(1, -(-8192 // max(1, -(-nF // 64)))))
-        b += 8 * P + 12 * nV + 48 * nF + 36 * nF * splits + 36 * nF + 64 * nF + 8 * nV + (1 << 20)
+        # target, dL/dW, dL/dV, and the adjoint's own workspace (face records, per-split
+        # corner sums, corner sort buffers, vertex bounds)
+        ws = _lib().wn_workspace_size_backward(nV, nF, P, adjoint_chunk(nF, P))
+        b += 8 * P + 12 * nV + int(ws) + 512
     return int(b)
 
 
@@ -106,13 +137,22 @@ class Server:
     """The scheduler.  ``executor`` performs device work; ``clock`` returns seconds."""
 
     def __init__(self, executor, hbm_budget: int = 64 << 30, slots: int = 16,
-                 quantum_pairs: float = 2.0e10, max_inflight: int = 2, clock=time.perf_counter):
+                 quantum_pairs: float = 2.0e10, max_inflight: int = 2, clock=time.perf_counter,
+                 policy: str | None = None, adjoint_cost: float = ADJOINT_COST, rate_pairs: float = RATE_PAIRS,
+                 deadline_slack: float = DEADLINE_SLACK, deadline_base: float = DEADLINE_BASE):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.slots = int(slots)
         self.quantum = float(quantum_pairs)
         self.max_inflight = int(max_inflight)
         self.clock = clock
+        self.policy = policy or POLICY
+        if self.policy not in ("edf", "fair", "age"):
+            raise ValueError("policy must be 'edf', 'fair' or 'age'")
+        self.adj_cost = float(adjoint_cost)
+        self.rate = float(rate_pairs)
+        self.slack = float(deadline_slack)
+        self.base = float(deadline_base)
         self.pending = collections.deque()   # arrived, not yet admitted
         self.active: list[_Active] = []
         self.in_use = 0
@@ -121,7 +161,7 @@ class Server:
         self.peak_in_use = 0
         self.peak_active = 0
         self.t0 = 0.0
-        self.step_log = []   # (number of requests, voxels) per launched step
+        self.step_log = []   # (number of requests, forward voxels, adjoint points) per step
 
     # ---------------------------------------------------------------- intake
     def submit(self, req: ServeRequest) -> ServeResult:
@@ -133,7 +173,14 @@ class Server:
             res.rejected = True
             res.error = f"footprint {fp} B exceeds the HBM budget {self.budget} B"
             return res
-        self.pending.append(_Active(req, res, fp))
+        a = _Active(req, res, fp)
+        nF, P = len(req.F), req.points
+        work = P * nF
+        if req.wants_grad:
+            a.adj_chunk = adjoint_chunk(nF, P)
+            work += self.adj_cost * P * nF
+        a.deadline = req.arrival + self.slack * work / self.rate + self.base
+        self.pending.append(a)
         return res
 
     def _max_slice_points(self, req: ServeRequest) -> int:
@@ -148,55 +195,88 @@ class Server:
                 break  # in order: wait for memory to free up
             self.pending.popleft()
             a.res.admitted = now
-            a.state = self.ex.admit(a.req)
+            a.state = self.ex.admit(a.req, a.adj_chunk)
             self.active.append(a)
             self.in_use += a.footprint
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             self.peak_active = max(self.peak_active, len(self.active))
 
     # ------------------------------------------------------------------ step
-    def _plan_slices(self):
-        fwd = [a for a in self.active if not a.launched_all]
-        if not fwd:
-            return []
-        if SHARE_POLICY == "age":
-            now = self.clock() - self.t0
-            w = [1.0 + max(0.0, now - a.req.arrival) / AGE_TAU for a in fwd]
+    def _plan(self):
+        """Units of work for one step: forward slices [(a, p0, n)], requests whose
+        forward completes [a], adjoint units [(a, p0, n, last)]."""
+        todo = [a for a in self.active if not a.all_launched]
+        if not todo:
+            return [], [], []
+        if self.policy == "edf":
+            order = sorted(todo, key=lambda a: (a.deadline, a.req.rid))
+            budgets = None
         else:
-            w = [1.0] * len(fwd)
-        wsum = sum(w)
-        slices = []
-        for a, wi_ in zip(fwd, w):
-            share = self.quantum * wi_ / wsum
-            nF = max(1, len(a.req.F))
-            pts = max(POINT_QUANTUM, int(share / nF) // POINT_QUANTUM * POINT_QUANTUM)
-            pts = min(pts, self._max_slice_points(a.req), a.req.points - a.next_point)
-            slices.append((a, a.next_point, pts))
-            a.next_point += pts
-            if a.next_point >= a.req.points:
-                a.launched_all = True
-        return slices
+            order = todo
+            if self.policy == "age":
+                now = self.clock() - self.t0
+                w = [1.0 + max(0.0, now - a.req.arrival) / AGE_TAU for a in todo]
+            else:
+                w = [1.0] * len(todo)
+            wsum = sum(w)
+            budgets = [self.quantum * wi_ / wsum for wi_ in w]
+        left = self.quantum
+        fwd, fdone, adj = [], [], []
+        for i, a in enumerate(order):
+            b = left if budgets is None else budgets[i]
+            if budgets is None and b <= 0:
+                break
+            must = budgets is not None or i == 0   # the head (or every share) always progresses
+            nF, P = max(1, len(a.req.F)), a.req.points
+            spent = 0.0
+            if not a.launched_all:
+                pts = int(b / nF) // POINT_QUANTUM * POINT_QUANTUM
+                if pts < POINT_QUANTUM and must:
+                    pts = POINT_QUANTUM
+                pts = min(pts, self._max_slice_points(a.req), P - a.next_point)
+                if pts > 0:
+                    fwd.append((a, a.next_point, pts))
+                    a.next_point += pts
+                    spent += pts * nF
+                if a.next_point >= P:
+                    a.launched_all = True
+                    fdone.append(a)
+            if a.launched_all and a.req.wants_grad and not a.adj_ended:
+                unit = a.adj_chunk * nF * self.adj_cost
+                k = int((b - spent) // unit)
+                if k < 1 and must and spent == 0:
+                    k = 1
+                if k > 0 or P == 0:
+                    n = min(k * a.adj_chunk, P - a.adj_next)
+                    last = a.adj_next + n >= P
+                    adj.append((a, a.adj_next, n, last))
+                    a.adj_next += n
+                    a.adj_ended = last
+                    spent += n * nF * self.adj_cost
+            if budgets is None:
+                left -= spent
+        return fwd, fdone, adj
 
     def step(self) -> bool:
-        """Admit, launch one batched forward step, queue finished requests' gradients,
-        retire completed requests.  Returns False when there is nothing left to do."""
+        """Admit, launch one step (a batched forward launch and adjoint units), retire
+        completed requests.  Returns False when there is nothing left to do."""
         self._admit(self.clock() - self.t0)
-        slices = self._plan_slices()
-        if slices:
+        fwd, fdone, adj = self._plan()
+        if fwd or fdone or adj:
             self.ex.wait_inflight(self.max_inflight - 1)
-            self.ex.launch_forward([(a.state, a.req, p0, n) for a, p0, n in slices])
+            self.ex.launch_step([(a.state, a.req, p0, n) for a, p0, n in fwd],
+                                [(a.state, a.req) for a in fdone],
+                                [(a.state, a.req, p0, n, last) for a, p0, n, last in adj])
             self.steps += 1
-            self.step_log.append((len(slices), sum(n for _, _, n in slices)))
-            for a, _, _ in slices:
-                if a.launched_all:
-                    self.ex.finish(a.state, a.req)
+            reqs = {id(a) for a, _, _ in fwd} | {id(a) for a, _, _, _ in adj}
+            self.step_log.append((len(reqs), sum(n for _, _, n in fwd), sum(n for _, _, n, _ in adj)))
         self._retire()
         return bool(self.active or self.pending)
 
     def _retire(self):
         keep = []
         for a in self.active:
-            t = self.ex.done_time(a.state) if a.launched_all else None
+            t = self.ex.done_time(a.state) if a.all_launched else None
             if t is None:
                 keep.append(a)
                 continue
@@ -207,7 +287,7 @@ class Server:
 
     def drain(self, idle_sleep: float = 2e-4):
         while self.step():
-            if not any(not a.launched_all for a in self.active):
+            if all(a.all_launched for a in self.active):
                 self.ex.idle(idle_sleep)
 
     # ------------------------------------------------------------ trace driver
@@ -226,7 +306,7 @@ class Server:
             busy = self.step()
             if not busy and i < len(reqs):
                 self.ex.idle(min(idle_sleep, max(0.0, reqs[i].arrival - (self.clock() - t0))))
-            elif busy and not any(not a.launched_all for a in self.active):
+            elif busy and all(a.all_launched for a in self.active):
                 self.ex.idle(idle_sleep)
         self.ex.sync()
         return [self.results[r.rid] for r in reqs]
@@ -249,8 +329,9 @@ def latency_stats(results) -> dict:
 # ============================================================== GPU executor
 
 class GpuExecutor:
-    """Device side of the server: uploads, batched forward steps on one stream, loss
-    and adjoint on a second stream, completion times from timing events."""
+    """Device side of the server: uploads, then per step one batched forward launch, the
+    loss of requests whose forward completed, and adjoint units, in order on one stream;
+    completion times from timing events."""
 
     def __init__(self, device="cuda", graph: bool = True, strips: bool = True):
         import torch
@@ -258,7 +339,6 @@ class GpuExecutor:
         self.strips = strips
         self.dev = torch.device(device)
         self.fwd = torch.cuda.Stream(self.dev)
-        self.aux = torch.cuda.Stream(self.dev)
         self.graph = graph
         self.inflight = collections.deque()
         self.ref = None
@@ -272,7 +352,7 @@ class GpuExecutor:
         self.ref.synchronize()
         self.t_ref = time.perf_counter() - t0
 
-    def admit(self, req: ServeRequest):
+    def admit(self, req: ServeRequest, adj_chunk: int = 0):
         import paper_2407_11272_amd as wn
         torch = self.torch
         st = {}
@@ -294,43 +374,46 @@ class GpuExecutor:
                 T = torch.from_numpy(np.ascontiguousarray(req.target, dtype=np.float32)).pin_memory()
                 st["target"] = T.to(self.dev, non_blocking=True)
                 st["hold"] = (V, F, T)
+                st["dLdW"] = torch.empty(req.points, dtype=torch.float32, device=self.dev)
+                st["adj"] = wn.SlicedBackward(st["V"], st["F"], grid=job.grid, chunk=adj_chunk)
         return st
 
     def wait_inflight(self, keep: int):
         while len(self.inflight) > max(0, keep):
             self.inflight.popleft().synchronize()
 
-    def launch_forward(self, slices):
+    def _done_event(self, st):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(self.fwd)
+        st["done"] = ev
+
+    def launch_step(self, fwd, fdone, adj):
         import paper_2407_11272_amd as wn
         torch = self.torch
-        jobs = []
-        for st, req, p0, n in slices:
-            base = st["job"]
-            jobs.append(wn.MeshJob(base.V, base.F, base.grid, base.occupancy, base.tau, base.k, base.W, base.occ,
-                                   point_begin=p0, point_count=n, strips=base.strips))
         with torch.cuda.stream(self.fwd):
-            wn.wn_voxelize_batched(jobs, graph=self.graph)
+            if fwd:
+                jobs = []
+                for st, req, p0, n in fwd:
+                    base = st["job"]
+                    jobs.append(wn.MeshJob(base.V, base.F, base.grid, base.occupancy, base.tau, base.k, base.W,
+                                           base.occ, point_begin=p0, point_count=n, strips=base.strips))
+                wn.wn_voxelize_batched(jobs, graph=self.graph)
+            for st, req in fdone:
+                if req.wants_grad:
+                    W = st["job"].W.reshape(-1)
+                    st["loss"], _ = wn.wn_sigmoid_mse(W, st["target"], req.tau, req.k, dLdW=st["dLdW"])
+                    st["adj"].begin()
+                else:
+                    self._done_event(st)
+            for st, req, p0, n, last in adj:
+                if n > 0:
+                    st["adj"].points(p0, n, st["dLdW"])
+                if last:
+                    st["dLdV"] = st["adj"].end()
+                    self._done_event(st)
             ev = torch.cuda.Event()
             ev.record(self.fwd)
         self.inflight.append(ev)
-
-    def finish(self, st, req: ServeRequest):
-        import paper_2407_11272_amd as wn
-        torch = self.torch
-        fwd_done = torch.cuda.Event(enable_timing=True)
-        fwd_done.record(self.fwd)
-        if not req.wants_grad:
-            st["done"] = fwd_done
-            return
-        with torch.cuda.stream(self.aux):
-            self.aux.wait_event(fwd_done)
-            job = st["job"]
-            W = job.W.reshape(-1)
-            st["loss"], dLdW = wn.wn_sigmoid_mse(W, st["target"], req.tau, req.k)
-            st["dLdV"] = wn.wn_backward(job.V, job.F, dLdW, grid=job.grid)
-            done = torch.cuda.Event(enable_timing=True)
-            done.record(self.aux)
-        st["done"] = done
 
     def done_time(self, st):
         ev = st.get("done")

@@ -55,3 +55,20 @@ def test_no_cpu_fallback_on_host_tensors():
     import torch
     with pytest.raises(ValueError):
         wn.wn_voxelize(torch.zeros((3, 3)), torch.zeros((1, 3), dtype=torch.int32), grid=wn.Grid.cube(2))
+
+
+def test_backward_split_size_and_sliced_workspace_are_host_only():
+    lib = L.load()
+    # the default split size: whole 256-point tiles; a requested size is returned as is
+    d = lib.wn_backward_chunk(5120, 64 ** 3, 0)
+    assert d >= 256 and d % 256 == 0
+    assert lib.wn_backward_chunk(5120, 64 ** 3, 1000) == 1000
+    assert lib.wn_backward_chunk(-1, 10, 0) == -1 and lib.wn_backward_chunk(1, 10, -5) == -1
+    # the default sliced workspace is wn_backward's; smaller splits need more partial sums
+    assert lib.wn_workspace_size_backward(2562, 5120, 64 ** 3, 0) == wn.wn_workspace_size(L.WN_OP_BACKWARD, 2562,
+                                                                                          5120, 64 ** 3)
+    small = lib.wn_workspace_size_backward(2562, 5120, 64 ** 3, 256)
+    assert small >= 36 * 5120 * (64 ** 3 // 256)
+    # at most 65535 splits
+    assert lib.wn_workspace_size_backward(10, 10, 65536, 1) == 0
+    assert lib.wn_workspace_size_backward(10, 10, 65535, 1) > 0

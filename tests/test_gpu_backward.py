@@ -174,3 +174,101 @@ def test_backward_edge_cases(dev, orc):
     assert guard.sum() == 0
     np.testing.assert_allclose(tg.cpu().numpy(), Tr, rtol=1e-3, atol=1e-4 * np.abs(Tr).max())
     np.testing.assert_allclose(dg.cpu().numpy(), Dr, rtol=1e-3, atol=1e-4 * np.abs(Dr).max())
+
+
+def test_sliced_adjoint_equals_one_call_and_the_oracle(dev, orc):
+    """wn_backward_range: ranges of whole splits in any order and grouping give the same
+    bits as one call with the same split size; split size 0 is wn_backward bit for bit;
+    and the sliced result holds the oracle's bar (i)."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable(res=32, open_variant=True)
+    Vt, Ft = _to_dev(c)
+    P = c.grid.size
+    g = torch.randn(P, device="cuda", generator=torch.Generator("cuda").manual_seed(11))
+    # chunk 0: the same as wn_backward
+    sb0 = wn.SlicedBackward(Vt, Ft, grid=c.grid)
+    sb0.begin()
+    sb0.points(0, P, g)
+    T0 = torch.empty((len(c.F), 3, 3), device="cuda")
+    D0 = sb0.end(dLdT=T0)
+    Dw, Tw = wn.wn_backward(Vt, Ft, g, grid=c.grid, want_dLdT=True)
+    torch.cuda.synchronize()
+    assert torch.equal(D0, Dw) and torch.equal(T0, Tw)
+    # chunk 1280 (not a multiple of the 256-point tile): 26 splits, the last ragged
+    chunk = 1280
+    one = wn.SlicedBackward(Vt, Ft, grid=c.grid, chunk=chunk)
+    assert one.chunk == chunk and one.splits == -(-P // chunk)
+    one.begin()
+    one.points(0, P, g)
+    T1 = torch.empty_like(T0)
+    D1 = one.end(dLdT=T1)
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        cuts = np.sort(rng.choice(np.arange(1, one.splits), size=6, replace=False))
+        bounds = [0] + [int(x) * chunk for x in cuts] + [P]
+        ranges = [(bounds[i], bounds[i + 1] - bounds[i]) for i in range(len(bounds) - 1)]
+        rng.shuffle(ranges)
+        sb = wn.SlicedBackward(Vt, Ft, grid=c.grid, chunk=chunk)
+        sb.begin()
+        for p0, n in ranges:
+            sb.points(p0, n, g)
+        T2 = torch.empty_like(T0)
+        D2 = sb.end(dLdT=T2)
+        torch.cuda.synchronize()
+        print(f"[sliced] trial {trial}: {len(ranges)} ranges, order {[p0 // chunk for p0, _ in ranges]}", flush=True)
+        assert torch.equal(D1, D2) and torch.equal(T1, T2)
+    # the split size changes only the summation order: the oracle's bar (i)
+    Tr, _ = orc.grad(_f32(c.V), c.F, orc.grid_points(c.grid), g.cpu().numpy().astype(np.float64))
+    _check_T(T1.cpu().numpy().astype(np.float64).reshape(-1), Tr.reshape(-1), "sliced chunk 1280")
+
+
+def test_sliced_adjoint_point_list_and_argument_errors(dev, orc):
+    import ctypes
+    import torch
+    import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd import _lib as L
+    rng = np.random.default_rng(9)
+    Vs = rng.uniform(-0.5, 0.5, (9, 3))
+    Fs = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 8], [0, 4, 8]])
+    Q = rng.uniform(-0.6, 0.6, (1000, 3)).astype(np.float32)
+    gq = rng.normal(size=1000).astype(np.float32)
+    Vt, Ft = wn.as_mesh(torch.as_tensor(Vs), torch.as_tensor(Fs))
+    Qt, gt = torch.as_tensor(Q).cuda(), torch.as_tensor(gq).cuda()
+    sb = wn.SlicedBackward(Vt, Ft, Q=Qt, chunk=256)
+    sb.begin()
+    sb.points(768, 232, gt)   # the ragged last split first
+    sb.points(0, 768, gt)
+    D = sb.end()
+    Dw = wn.wn_backward(Vt, Ft, gt, Q=Qt)
+    torch.cuda.synchronize()
+    _, Dr = orc.grad(_f32(Vs), Fs, Q.astype(np.float64), gq.astype(np.float64))
+    np.testing.assert_allclose(D.cpu().numpy(), Dr, rtol=1e-3, atol=1e-4 * np.abs(Dr).max())
+    np.testing.assert_allclose(D.cpu().numpy(), Dw.cpu().numpy(), rtol=1e-4, atol=1e-5 * np.abs(Dr).max())
+    # argument errors, before any launch
+    lib = L.load()
+    p = ctypes.c_void_p
+    s = p(torch.cuda.current_stream().cuda_stream)
+    need = lib.wn_workspace_size_backward(9, 4, 1000, 256)
+    ws = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    base = p(ws.data_ptr() + (-ws.data_ptr()) % 256)
+    dV = torch.empty_like(Vt)
+
+    def call(p0, n, flags=0, chunk=256, wsb=need, dLdV=dV):
+        return lib.wn_backward_range(p(Vt.data_ptr()), 9, p(Ft.data_ptr()), 4, None, p(Qt.data_ptr()), 1000,
+                                     p(gt.data_ptr()), chunk, p0, n, flags, p(dLdV.data_ptr()) if dLdV is not None
+                                     else None, None, base, wsb, s)
+
+    assert call(0, 0, L.WN_BWD_BEGIN) == L.WN_OK
+    assert call(100, 256) == L.WN_ERR_INVALID_ARG          # p0 not on a split boundary
+    assert call(0, 300) == L.WN_ERR_INVALID_ARG            # n not whole splits and not the end
+    assert call(768, 233) == L.WN_ERR_INVALID_ARG          # past the last point
+    assert call(0, 256, 4) == L.WN_ERR_INVALID_ARG         # unknown flag
+    assert call(0, 0, L.WN_BWD_END, dLdV=None) == L.WN_ERR_INVALID_ARG
+    assert call(0, 256, chunk=-1) == L.WN_ERR_INVALID_ARG
+    assert call(0, 256, wsb=need - 1) == L.WN_ERR_WORKSPACE
+    Q2 = torch.zeros((70000, 3), device="cuda")
+    g2 = torch.zeros(70000, device="cuda")
+    assert lib.wn_backward_range(p(Vt.data_ptr()), 9, p(Ft.data_ptr()), 4, None, p(Q2.data_ptr()), 70000,
+                                 p(g2.data_ptr()), 1, 0, 1, 0, None, None, base, need, s) == L.WN_ERR_INVALID_ARG
+    torch.cuda.synchronize()

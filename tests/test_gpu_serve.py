@@ -49,8 +49,9 @@ def test_mix_equals_alone_and_plain(dev, orc):
     assert any(r.wants_grad for r in reqs) and not all(r.wants_grad for r in reqs)
     srv, mix = _serve(reqs, slots=6, quantum_pairs=2e8)
     print(f"steps={srv.steps} peak_active={srv.peak_active} mixed steps="
-          f"{sum(1 for n, _ in srv.step_log if n > 1)}", flush=True)
-    assert srv.peak_active > 1 and any(n > 1 for n, _ in srv.step_log)
+          f"{sum(1 for n, _, _ in srv.step_log if n > 1)} adjoint units={sum(1 for *_, a in srv.step_log if a)}",
+          flush=True)
+    assert srv.peak_active > 1 and any(n > 1 for n, _, _ in srv.step_log)
     for r, m in zip(reqs, mix):
         assert np.isfinite(m.done) and not m.rejected
         _, alone = _serve([r], slots=1, quantum_pairs=5e8)

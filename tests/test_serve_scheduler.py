@@ -1,15 +1,18 @@
 """CPU tests of the continuous-batching scheduler against a simulated executor.
 
-The simulated executor runs on a virtual clock: a forward step takes (pairs / rate)
-seconds of device time, gradients run on a second virtual stream after the request's
-forward finishes.  No GPU and no winding numbers are involved; these tests check
-admission by footprint, slot limits, in-order admission, slice coverage, that steps
-mix several requests, and that small requests are not stuck behind large ones.
+The simulated executor runs on a virtual clock: a step takes (forward pairs +
+adjoint cost x adjoint pairs) / rate seconds of device time.  No GPU and no winding
+numbers are involved (the library is loaded only for its host-side size functions);
+these tests check admission by footprint, slot limits, in-order admission, that the
+forward slices and adjoint units of every request partition its points and come in the
+right order, that steps mix several requests, that short requests overtake long ones
+under every policy, and that a long request is not starved by a stream of short ones.
 """
 import numpy as np
 import pytest
 
-from paper_2407_11272_amd.serve import Server, ServeRequest, footprint_bytes, latency_stats
+from paper_2407_11272_amd.serve import (ADJOINT_COST, ADJOINT_MAX_CHUNK, Server, ServeRequest, adjoint_chunk,
+                                        footprint_bytes, latency_stats)
 from wn_inputs import Grid
 
 
@@ -22,44 +25,51 @@ class VClock:
 
 
 class FakeExecutor:
-    def __init__(self, clock: VClock, rate: float = 5e11, step_overhead: float = 1e-4):
+    def __init__(self, clock: VClock, rate: float = 5e11, step_overhead: float = 1e-4,
+                 adjoint_cost: float = ADJOINT_COST):
         self.clock = clock
         self.rate = rate
         self.overhead = step_overhead
-        self.fwd_free = 0.0
-        self.aux_free = 0.0
+        self.adj_cost = adjoint_cost
+        self.busy_until = 0.0
         self.inflight = []
         self.slices = {}
+        self.adj = {}
+        self.fwd_done_step = {}
         self.steps = []
 
     def start(self, t0):
         pass
 
-    def admit(self, req):
+    def admit(self, req, adj_chunk=0):
         self.slices[req.rid] = []
-        return {"rid": req.rid}
+        self.adj[req.rid] = []
+        return {"rid": req.rid, "chunk": adj_chunk}
 
     def wait_inflight(self, keep):
         while len(self.inflight) > max(0, keep):
             t = self.inflight.pop(0)
             self.clock.t = max(self.clock.t, t)
 
-    def launch_forward(self, slices):
-        pairs = sum(n * len(req.F) for _, req, _, n in slices)
-        start = max(self.fwd_free, self.clock.t)
-        self.fwd_free = start + self.overhead + pairs / self.rate
-        self.inflight.append(self.fwd_free)
-        self.steps.append([req.rid for _, req, _, _ in slices])
-        for st, req, p0, n in slices:
-            self.slices[req.rid].append((p0, n))
-
-    def finish(self, st, req):
-        done = self.fwd_free
-        if req.wants_grad:
-            start = max(self.aux_free, done)
-            self.aux_free = start + req.points * len(req.F) / self.rate
-            done = self.aux_free
-        st["done"] = done
+    def launch_step(self, fwd, fdone, adj):
+        pairs = sum(n * len(req.F) for _, req, _, n in fwd)
+        pairs += self.adj_cost * sum(n * len(req.F) for _, req, _, n, _ in adj)
+        start = max(self.busy_until, self.clock.t)
+        end = start + self.overhead + pairs / self.rate
+        self.busy_until = end
+        self.inflight.append(end)
+        k = len(self.steps)
+        self.steps.append([req.rid for _, req, _, _ in fwd] + [req.rid for _, req, _, _, _ in adj])
+        for st, req, p0, n in fwd:
+            self.slices[req.rid].append((p0, n, k))
+        for st, req in fdone:
+            self.fwd_done_step[req.rid] = k
+            if not req.wants_grad:
+                st["done"] = end
+        for st, req, p0, n, last in adj:
+            self.adj[req.rid].append((p0, n, last, k))
+            if last:
+                st["done"] = end
 
     def done_time(self, st):
         d = st.get("done")
@@ -72,7 +82,7 @@ class FakeExecutor:
         self.clock.t += max(seconds, 1e-4)
 
     def sync(self):
-        self.clock.t = max(self.clock.t, self.fwd_free, self.aux_free)
+        self.clock.t = max(self.clock.t, self.busy_until)
 
 
 def _req(rid, faces, res, arrival, grad=False):
@@ -91,25 +101,49 @@ def _run(reqs, **kw):
     return srv, ex, out
 
 
-def test_every_request_completes_and_slices_partition_the_grid():
+@pytest.mark.parametrize("policy", ["edf", "fair", "age"])
+def test_every_request_completes_and_units_partition_the_grid(policy):
     rng = np.random.default_rng(0)
     reqs = [_req(i, int(rng.integers(1000, 60000)), int(rng.choice([32, 64, 128])), float(i) * 0.01,
                  grad=bool(i % 3 == 0)) for i in range(40)]
-    srv, ex, out = _run(reqs, slots=8, quantum_pairs=5e9)
+    srv, ex, out = _run(reqs, slots=8, quantum_pairs=5e9, policy=policy)
     assert all(np.isfinite(r.done) and not r.rejected for r in out)
     for r in reqs:
         sl = sorted(ex.slices[r.rid])
         pos = 0
-        for p0, n in sl:
+        for p0, n, _ in sl:
             assert p0 == pos and n > 0
             pos += n
         assert pos == r.points
         # slices are whole quanta of 2048 voxels except the last
-        assert all(n % 2048 == 0 for _, n in sl[:-1])
+        assert all(n % 2048 == 0 for _, n, _ in sl[:-1])
+        last_fwd_step = max(k for _, _, k in sl)
+        assert ex.fwd_done_step[r.rid] == last_fwd_step
+        units = ex.adj[r.rid]
+        if not r.wants_grad:
+            assert units == []
+            continue
+        # adjoint units: whole splits in order, after the forward, the last one flagged
+        chunk = adjoint_chunk(len(r.F), r.points)
+        pos = 0
+        for i, (p0, n, last, k) in enumerate(units):
+            assert p0 == pos and n > 0 and k >= last_fwd_step
+            assert last == (i == len(units) - 1)
+            assert n % chunk == 0 or p0 + n == r.points
+            pos += n
+        assert pos == r.points
     for r in out:
         assert r.done >= r.arrival and r.admitted >= r.arrival - 1e-12
     st = latency_stats(out)
     assert st["count"] == 40 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_adjoint_chunk_depends_only_on_the_request():
+    # small requests use the library's split size (many splits, to fill the GPU alone);
+    # large ones at most ADJOINT_MAX_CHUNK points per split
+    assert adjoint_chunk(1000, 64 ** 3) < ADJOINT_MAX_CHUNK
+    assert adjoint_chunk(100000, 256 ** 3) == ADJOINT_MAX_CHUNK
+    assert adjoint_chunk(5000, 64 ** 3) == adjoint_chunk(5000, 64 ** 3)
 
 
 def test_footprint_admission_and_rejection():
@@ -124,6 +158,13 @@ def test_footprint_admission_and_rejection():
     assert srv.peak_active <= 2  # only two small requests fit at once
 
 
+def test_gradient_footprint_counts_the_adjoint_splits():
+    r = _req(0, 100000, 256, 0.0, grad=True)
+    splits = -(-r.points // adjoint_chunk(len(r.F), r.points))
+    assert footprint_bytes(r, 10 ** 9) > 36 * len(r.F) * splits
+    assert footprint_bytes(r, 10 ** 9) > footprint_bytes(_req(0, 100000, 256, 0.0), 10 ** 9)
+
+
 def test_slot_limit_and_in_order_admission():
     reqs = [_req(i, 5000, 64, 0.0) for i in range(12)]
     srv, ex, out = _run(reqs, slots=3, quantum_pairs=1e9)
@@ -133,12 +174,13 @@ def test_slot_limit_and_in_order_admission():
     assert all(np.isfinite(r.done) for r in out)
 
 
-def test_steps_mix_requests_and_small_ones_overtake_large():
+@pytest.mark.parametrize("policy", ["edf", "fair", "age"])
+def test_steps_mix_requests_and_small_ones_overtake_large(policy):
     """A small request arriving during a large one shares the next steps with it and
     finishes long before it (with FIFO it would wait for the whole large one)."""
     large = _req(0, 100000, 256, 0.0)
     smalls = [_req(i, 2000, 64, 0.05 + 0.01 * i) for i in range(1, 4)]
-    srv, ex, out = _run([large] + smalls, slots=8, quantum_pairs=1e10)
+    srv, ex, out = _run([large] + smalls, slots=8, quantum_pairs=1e10, policy=policy)
     res = {r.rid: r for r in out}
     assert any(len(set(s)) > 1 for s in ex.steps), "no step combined requests"
     service_large = large.points * len(large.F) / ex.rate
@@ -149,11 +191,36 @@ def test_steps_mix_requests_and_small_ones_overtake_large():
 
 def test_gradient_requests_finish_after_their_forward():
     reqs = [_req(0, 8000, 64, 0.0, grad=True), _req(1, 8000, 64, 0.0)]
-    srv, ex, out = _run(reqs, slots=4)
+    srv, ex, out = _run(reqs, slots=4, quantum_pairs=5e8)
     res = {r.rid: r for r in out}
     assert res[0].done > res[1].done
+    assert ex.adj[0][0][3] >= ex.fwd_done_step[0]
+
+
+def test_edf_large_gradient_request_is_not_starved():
+    """A large gradient request under a steady stream of short requests: under the
+    deadline policy it finishes within a few times its own service time, while every
+    short request still finishes long before it would behind the large one."""
+    big = _req(0, 50000, 128, 0.0, grad=True)
+    service = big.points * len(big.F) * (1 + ADJOINT_COST) / 5e11
+    smalls = [_req(i, 3000, 64, 0.004 * i) for i in range(1, int(3 * service / 0.004))]
+    srv, ex, out = _run([big] + smalls, slots=16, quantum_pairs=2e9, policy="edf")
+    res = {r.rid: r for r in out}
+    assert res[0].latency < 3.0 * service
+    lat_small = np.array([res[i].latency for i in range(1, len(smalls) + 1)])
+    assert np.percentile(lat_small, 50) < 0.2 * service
+    # the adjoint ran in several units, and short requests ran between the large one's
+    # forward and its last adjoint unit
+    assert len(ex.adj[0]) > 1
+    k0, k1 = min(k for _, _, k in ex.slices[0]), ex.adj[0][-1][3]
+    assert any(set(s) - {0} for s in ex.steps[k0:k1 + 1])
 
 
 def test_idle_server_returns():
     srv, ex, out = _run([], slots=2)
     assert out == [] and srv.steps == 0
+
+
+def test_unknown_policy_is_rejected():
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(VClock()), policy="lifo")
