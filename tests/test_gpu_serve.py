@@ -107,3 +107,37 @@ def test_budget_rejection_on_device(dev):
     assert out[0].rejected
     assert all(np.isfinite(o.done) for o in out[1:])
     assert srv.peak_in_use <= budget
+
+
+def test_degenerate_requests_on_device(dev):
+    """No faces, an empty grid, a one-voxel grid: every request completes; gradients
+    equal the sliced adjoint run directly with the request's split size."""
+    import torch
+    import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd.serve import ServeRequest, adjoint_chunk
+    c1 = wi.config1_icosphere()
+    V = np.asarray(c1.V, np.float32)
+    F = np.delete(np.asarray(c1.F, np.int32), np.arange(0, len(c1.F), 20), axis=0)  # open: rims carry gradient
+    g16 = wi.Grid.cube(16)
+    g0 = wi.Grid((-0.5,) * 3, (0.5,) * 3, (0, 4, 4))
+    g1 = wi.Grid((-0.5,) * 3, (0.5,) * 3, (1, 1, 1))
+    t16 = (np.random.default_rng(1).uniform(size=g16.size) > 0.5).astype(np.float32)
+    reqs = [ServeRequest(0, V, F[:0], g16, 0.0, "threshold", None),
+            ServeRequest(1, V, F[:0], g16, 0.0, "sigmoid", t16),
+            ServeRequest(2, V, F, g0, 0.0, "sigmoid", np.zeros(0, np.float32)),
+            ServeRequest(3, V, F, g1, 0.0, "sigmoid", np.ones(1, np.float32)),
+            ServeRequest(4, V, F, g16, 0.0, "sigmoid", t16)]
+    srv, out = _serve(reqs, slots=4, quantum_pairs=2e8)
+    assert all(np.isfinite(o.done) and not o.rejected for o in out)
+    assert float(out[0].W.abs().max()) == 0.0
+    assert float(out[1].dLdV.abs().max()) == 0.0 and float(out[2].dLdV.abs().max()) == 0.0
+    for r, o in zip(reqs[3:], out[3:]):
+        Vd, Fd = wn.as_mesh(torch.as_tensor(r.V), torch.as_tensor(r.F))
+        loss, dLdW = wn.wn_sigmoid_mse(o.W.reshape(-1), torch.as_tensor(r.target).cuda(), r.tau, r.k)
+        sb = wn.SlicedBackward(Vd, Fd, grid=wn.Grid.of(r.grid), chunk=adjoint_chunk(len(r.F), r.points))
+        sb.begin()
+        sb.points(0, r.points, dLdW)
+        D = sb.end()
+        torch.cuda.synchronize()
+        assert torch.equal(D, o.dLdV) and torch.equal(loss, o.loss)
+    assert float(out[4].dLdV.abs().max()) > 0.0

@@ -224,3 +224,23 @@ def test_idle_server_returns():
 def test_unknown_policy_is_rejected():
     with pytest.raises(ValueError):
         Server(FakeExecutor(VClock()), policy="lifo")
+
+
+@pytest.mark.parametrize("policy", ["edf", "fair", "age"])
+def test_degenerate_requests_complete(policy):
+    """No faces, an empty grid, and a one-voxel grid, with and without gradients."""
+    def req(rid, faces, n, grad):
+        V = np.zeros((max(3, faces // 2 + 2), 3), np.float32)
+        F = np.zeros((faces, 3), np.int32)
+        g = Grid((-0.5,) * 3, (0.5,) * 3, (n, n, n))
+        return ServeRequest(rid, V, F, g, 0.001 * rid, "sigmoid" if grad else "threshold",
+                            np.zeros(g.size, np.float32) if grad else None)
+    reqs = [req(0, 0, 16, False), req(1, 0, 16, True), req(2, 500, 0, False), req(3, 500, 0, True),
+            req(4, 500, 1, True), req(5, 2000, 32, True)]
+    srv, ex, out = _run(reqs, slots=4, quantum_pairs=1e8, policy=policy)
+    assert all(np.isfinite(r.done) and not r.rejected for r in out)
+    for r in reqs:
+        assert sum(n for _, n, _ in ex.slices[r.rid]) == r.points
+        if r.wants_grad:
+            units = ex.adj[r.rid]
+            assert units and units[-1][2] and sum(n for _, n, _, _ in units) == r.points
