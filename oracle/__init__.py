@@ -14,9 +14,9 @@ Paper sections followed (arXiv 2407.11272):
     or soft occupancy uses a threshold or a sigmoid around 0.5;
   * Section 2.4 (mesh morphing): the voxel loss drives the vertices through Adam
     (Kingma and Ba, 2015, Algorithm 1), written out in numpy FP64;
-  * Section 3 (evaluation): occupancy -> cube surface ("cubified") -> Laplacian
-    smoothing (10 iterations, lambda = 0.15) -> 20 000 surface samples -> Chamfer and
-    Hausdorff distances to the original mesh.
+  * Section 3 (evaluation): occupancy -> cube surface ("cubified"), or marching cubes
+    of the field -> Laplacian smoothing (10 iterations, lambda = 0.15) -> 20 000
+    surface samples -> Chamfer and Hausdorff distances to the original mesh.
 """
 from __future__ import annotations
 
@@ -401,6 +401,181 @@ def cubify(occ, grid):
     lo = np.asarray(grid.lo, np.float64)
     h = (np.asarray(grid.hi, np.float64) - lo) / np.asarray(grid.n, np.float64)
     return lo + ci * h, F
+
+
+# ---------------------------------------------------------------- marching cubes
+#
+# The reconstruction the paper names when it motivates its metric (Section 3): the
+# surface between field values above a level (inside) and at or below it (outside).
+# Derived here from a rule on the cell faces rather than from a printed case table:
+#   * on every face of a cell, walking its corners counter-clockwise as seen from outside
+#     the cell, the face's crossed edges alternate between entries (outside -> inside)
+#     and exits; each entry is joined to the next exit, so where two diagonal corners are
+#     inside, the segments cut each inside corner off on its own (both cells sharing the
+#     face see the same segments, so the surface is closed);
+#   * every crossed cell edge ends one segment and starts one, so the segments close into
+#     loops, each started at its lowest local edge number and split into a fan;
+#   * the direction of the segments is fixed once so that faces point outward.
+
+def _mc_cell():
+    corners = [np.array((a, b, c), np.float64) for c in (0, 1) for b in (0, 1) for a in (0, 1)]  # a + 2b + 4c
+    edges = []                                   # local edge -> (corner, corner)
+    for axis in range(3):
+        o1, o2 = [d for d in range(3) if d != axis]
+        for hi2 in (0, 1):
+            for hi1 in (0, 1):
+                lo_c = [0, 0, 0]
+                lo_c[o1], lo_c[o2] = hi1, hi2
+                hi_c = list(lo_c)
+                hi_c[axis] = 1
+                edges.append((lo_c[0] + 2 * lo_c[1] + 4 * lo_c[2], hi_c[0] + 2 * hi_c[1] + 4 * hi_c[2]))
+    faces = []                                   # corner lists, counter-clockwise from outside
+    for axis in range(3):
+        for side in (0, 1):
+            n = np.zeros(3)
+            n[axis] = 1.0 if side else -1.0
+            cs = [i for i in range(8) if corners[i][axis] == side]
+            cen = sum(corners[i] for i in cs) / 4
+            u = np.zeros(3)
+            u[(axis + 1) % 3] = 1.0
+            v = np.cross(n, u)
+            cs.sort(key=lambda i: np.arctan2((corners[i] - cen) @ v, (corners[i] - cen) @ u))
+            faces.append(cs)
+    return corners, edges, faces
+
+
+def _mc_loops(case):
+    """Loops of crossed local edges of one inside/outside pattern of the 8 corners,
+    each starting at its lowest edge number and following the segments' direction."""
+    corners, edges, faces = _mc_cell()
+    inside = [(case >> i) & 1 == 1 for i in range(8)]
+    edge_of = {frozenset(e): k for k, e in enumerate(edges)}
+    succ = {}
+    for cs in faces:
+        walk = []
+        for t in range(4):
+            a, b = cs[t], cs[(t + 1) % 4]
+            if inside[a] != inside[b]:
+                walk.append((edge_of[frozenset((a, b))], inside[b]))   # True: entry
+        for t, (e, entry) in enumerate(walk):
+            if entry:
+                succ[e] = next(walk[(t + s) % len(walk)][0] for s in range(1, len(walk) + 1)
+                               if not walk[(t + s) % len(walk)][1])
+    loops, seen = [], set()
+    for start in sorted(succ):
+        if start in seen:
+            continue
+        loop = [start]
+        seen.add(start)
+        while succ[loop[-1]] != start:
+            loop.append(succ[loop[-1]])
+            seen.add(loop[-1])
+        loops.append(loop)
+    return loops
+
+
+def _mc_fan(loop):
+    """A loop split into a fan from its first vertex whose diagonals all join crossings
+    lying on no common cell face (a diagonal inside a face could coincide with the
+    neighbouring cell's triangles); one exists for every loop of every pattern."""
+    _, edges, faces = _mc_cell()
+    on = [{f for f, cs in enumerate(faces) if edges[e][0] in cs and edges[e][1] in cs} for e in loop]
+    m = len(loop)
+    for s in range(m):
+        if all(not (on[s] & on[j]) for j in range(m) if (j - s) % m not in (0, 1, m - 1)):
+            r = loop[s:] + loop[:s]
+            return [(r[0], r[i], r[i + 1]) for i in range(1, m - 1)]
+    raise AssertionError("no valid fan")
+
+
+_MC_TRIS = {}
+
+
+def _mc_case(case):
+    """Triangles (local edge triples) of one pattern, facing outward."""
+    if case not in _MC_TRIS:
+        tris = [t for loop in _mc_loops(case) for t in _mc_fan(loop)]
+        _MC_TRIS[case] = [(t[0], t[2], t[1]) for t in tris] if _MC_FLIP else tris
+    return _MC_TRIS[case]
+
+
+def _mc_needs_flip():
+    """Whether the segment direction gives inward faces: test one corner inside."""
+    corners, edges, _ = _mc_cell()
+    t = _mc_fan(_mc_loops(1)[0])[0]
+    mid = [0.5 * (corners[edges[e][0]] + corners[edges[e][1]]) for e in t]
+    return bool(np.cross(mid[1] - mid[0], mid[2] - mid[0]) @ (mid[0] - corners[0]) < 0)
+
+
+_MC_FLIP = _mc_needs_flip()
+
+
+def marching_cubes(values, grid, iso: float = 0.5):
+    """Marching cubes of a field sampled at the grid's voxel centres (C order), at level
+    ``iso`` > 0: the surface between values > iso and values <= iso, the grid surrounded
+    by one layer of zeros so that the surface is closed.  Vertices: one per crossed edge
+    between neighbouring centres of the padded lattice, at the linear interpolation of
+    the two values, numbered by edge (3 * padded lattice index + axis).  Faces: cell by
+    cell in padded C order, each cell's triangles in case order, facing outward.
+    Returns (V [nV, 3] float64, F [nF, 3] int64)."""
+    if not iso > 0:
+        raise ValueError("iso must be > 0 (the padding is 0)")
+    n = tuple(int(x) for x in grid.n)
+    f = np.pad(np.asarray(values, np.float64).reshape(n), 1)
+    ins = f > iso
+    N = f.shape
+    lo = np.asarray(grid.lo, np.float64)
+    h = (np.asarray(grid.hi, np.float64) - lo) / np.asarray(n, np.float64)
+    flags = np.zeros(N + (3,), bool)
+    for axis in range(3):
+        sl = [slice(None)] * 3
+        sl2 = [slice(None)] * 3
+        sl[axis] = slice(0, N[axis] - 1)
+        sl2[axis] = slice(1, N[axis])
+        fl = [slice(None)] * 3 + [axis]
+        fl[axis] = slice(0, N[axis] - 1)
+        flags[tuple(fl)] = ins[tuple(sl)] != ins[tuple(sl2)]
+    vid = np.cumsum(flags.reshape(-1)) - 1            # vertex id of each crossed edge
+    eid = np.flatnonzero(flags.reshape(-1))
+    p = eid // 3
+    axis = eid % 3
+    P = np.stack(np.unravel_index(p, N), 1)
+    Q = P.copy()
+    Q[np.arange(len(Q)), axis] += 1
+    fa, fb = f[tuple(P.T)], f[tuple(Q.T)]
+    t = (iso - fa) / (fb - fa)
+    V = lo + (P - 1 + 0.5) * h
+    V[np.arange(len(V)), axis] += t * h[axis]
+    # cells
+    C = tuple(x - 1 for x in N)
+    case = np.zeros(C, np.int64)
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                case |= ins[a:a + C[0], b:b + C[1], c:c + C[2]].astype(np.int64) << (a + 2 * b + 4 * c)
+    _, edges, _ = _mc_cell()
+    keys, tris = [], []
+    cell_lin = np.arange(case.size).reshape(C)
+    for k in np.unique(case):
+        tl = _mc_case(int(k))
+        if not tl:
+            continue
+        cells = np.argwhere(case == k)               # C order
+        for ti, tri in enumerate(tl):
+            g = []
+            for e in tri:
+                c0, c1 = edges[e]
+                off = np.array((c0 & 1, (c0 >> 1) & 1, (c0 >> 2) & 1))
+                ax = int(np.flatnonzero(np.array((c1 & 1, (c1 >> 1) & 1, (c1 >> 2) & 1)) - off)[0])
+                pt = cells + off
+                lin = (pt[:, 0] * N[1] + pt[:, 1]) * N[2] + pt[:, 2]
+                g.append(vid[3 * lin + ax])
+            tris.append(np.stack(g, 1))
+            keys.append(cell_lin[tuple(cells.T)] * 16 + ti)
+    if not tris:
+        return V, np.zeros((0, 3), np.int64)
+    order = np.argsort(np.concatenate(keys), kind="stable")
+    return V, np.concatenate(tris)[order].astype(np.int64)
 
 
 def vertex_neighbours(nV, F):

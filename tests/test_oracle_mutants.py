@@ -121,10 +121,18 @@ PY_MUTANTS = [
      "0.25 * ((cx * cx + cy * cy) + cz * cz)"),
     ("chamfer_hausdorff", "chamfer_one_way", "dab.mean() + dba.mean()", "dab.mean()"),
     ("chamfer_hausdorff", "hausdorff_one_way", "max(dab.max(), dba.max())", "dab.max()"),
+    ("_mc_loops", "mc_join_inside_corners", "for s in range(1, len(walk) + 1)", "for s in range(len(walk) - 1, 0, -1)"),
+    ("_mc_fan", "mc_fan_from_first_vertex", "        if all(not (on[s] & on[j])", "        if s == 0 or all(not (on[s] & on[j])"),
+    ("_mc_case", "mc_inward_faces", "if _MC_FLIP else tris", "if not _MC_FLIP else tris"),
+    ("marching_cubes", "mc_interpolation_sign", "t = (iso - fa) / (fb - fa)", "t = (fa - iso) / (fb - fa)"),
+    ("marching_cubes", "mc_level_inclusive", "ins = f > iso", "ins = f >= iso"),
+    ("marching_cubes", "mc_padding_inside", "reshape(n), 1)", "reshape(n), 1, constant_values=1.0)"),
+    ("marching_cubes", "mc_vertex_numbering", "vid = np.cumsum(flags.reshape(-1)) - 1", "vid = np.cumsum(flags.reshape(-1))"),
 ]
 
 PY_PIN_TESTS = [fn for fn in PIN_TESTS
-                if any(k in fn.__name__ for k in ("adam", "morph", "cubify", "laplacian", "sampling", "nn_dist"))]
+                if any(k in fn.__name__ for k in ("adam", "morph", "cubify", "laplacian", "sampling", "nn_dist",
+                                                  "marching"))]
 
 
 @pytest.mark.parametrize("func,name,old,new", PY_MUTANTS, ids=[m[1] for m in PY_MUTANTS])

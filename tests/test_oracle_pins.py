@@ -729,6 +729,111 @@ def test_cubify_winding_number_is_the_occupancy(orc):
     assert V.shape == (0, 3) and F.shape == (0, 3)
 
 
+def _directed_edges_pair_up(F):
+    """Every directed edge is used once and its reverse once: a closed, consistently
+    oriented 2-manifold (no edge shared by more than two faces)."""
+    d = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+    u, cnt = np.unique(d, axis=0, return_counts=True)
+    rev = set(map(tuple, u[:, ::-1]))
+    return bool(np.all(cnt == 1)) and all(tuple(x) in rev for x in u)
+
+
+def _components(nV, F):
+    parent = list(range(nV))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+    for a, b, c in F:
+        for u, v in ((a, b), (b, c)):
+            ru, rv = find(int(u)), find(int(v))
+            if ru != rv:
+                parent[ru] = rv
+    return len({find(int(x)) for x in np.unique(F)})
+
+
+def test_marching_cubes_separates_inside_from_outside(orc):
+    """For random fields the surface is a closed oriented 2-manifold, and its winding
+    number at every voxel centre is exactly [value > iso] (Eq. 3): it separates the
+    centres and faces outward, grid-boundary voxels included."""
+    orc._MC_TRIS.clear()
+    rng = np.random.default_rng(52)
+    for shape, iso in (((6, 5, 4), 0.5), ((3, 7, 5), 0.3), ((5, 5, 5), 0.8), ((2, 2, 2), 0.5)):
+        g = wi.Grid((-1.0, -0.5, 0.0), (1.0, 0.5, 2.0), shape)
+        f = rng.random(shape)
+        V, F = orc.marching_cubes(f, g, iso)
+        assert _directed_edges_pair_up(F)
+        W = orc.winding(V, F, orc.grid_points(g))
+        assert np.abs(W - (f.reshape(-1) > iso)).max() < 1e-9
+    V, F = orc.marching_cubes(np.zeros((3, 3, 3)), wi.Grid.cube(3), 0.5)
+    assert V.shape == (0, 3) and F.shape == (0, 3)
+    with pytest.raises(ValueError):
+        orc.marching_cubes(np.zeros((3, 3, 3)), wi.Grid.cube(3), 0.0)
+
+
+def test_marching_cubes_single_voxel_diagonal_pair_and_strict_level(orc):
+    """One voxel above the level gives an octahedron with its 6 vertices halfway to the
+    neighbouring centres; two voxels touching only along an edge stay two separate
+    closed surfaces (inside corners are cut off on their own on an ambiguous face); a
+    value exactly at the level counts as outside, so the crossing lands on its centre."""
+    orc._MC_TRIS.clear()
+    g = wi.Grid((0.0, 0.0, 0.0), (3.0, 3.0, 3.0), (3, 3, 3))  # centres at 0.5, 1.5, 2.5
+    f = np.zeros((3, 3, 3))
+    f[1, 1, 1] = 1.0
+    V, F = orc.marching_cubes(f, g, 0.5)
+    assert V.shape == (6, 3) and F.shape == (8, 3)
+    d = np.sort(np.abs(V - 1.5), axis=1)
+    np.testing.assert_allclose(d, np.tile([0.0, 0.0, 0.5], (6, 1)), atol=1e-15)
+    assert abs(signed_volume(V, F) - 4 / 3 * 0.5 ** 3) < 1e-15
+    f[:] = 0.0
+    f[0, 0, 1] = f[1, 1, 1] = 1.0
+    V, F = orc.marching_cubes(f, g, 0.5)
+    assert _directed_edges_pair_up(F) and _components(len(V), F) == 2
+    f[:] = 0.0
+    f[1, 1, 1], f[1, 1, 2] = 1.0, 0.5
+    V, F = orc.marching_cubes(f, g, 0.5)
+    assert V.shape == (6, 3) and F.shape == (8, 3)
+    assert np.any(np.all(V == [1.5, 1.5, 2.5], axis=1))
+
+
+def test_marching_cubes_every_corner_pattern(orc):
+    """Each of the 256 inside/outside patterns of one cell (a 2 x 2 x 2 grid of 0/1
+    values), and a dense random pattern: closed oriented 2-manifolds whose winding
+    number is 1 at the inside centres and 0 at the others."""
+    orc._MC_TRIS.clear()
+    g = wi.Grid.cube(2)
+    Q = orc.grid_points(g)
+    for case in range(256):
+        f = np.array([(case >> (a + 2 * b + 4 * c)) & 1 for a in (0, 1) for b in (0, 1) for c in (0, 1)], float)
+        V, F = orc.marching_cubes(f.reshape(2, 2, 2), g, 0.5)
+        assert _directed_edges_pair_up(F), case
+        assert np.abs(orc.winding(V, F, Q) - f).max() < 1e-9, case
+    rng = np.random.default_rng(53)
+    g = wi.Grid.cube(9)
+    f = (rng.random((9, 9, 9)) < 0.5).astype(float)
+    V, F = orc.marching_cubes(f, g, 0.5)
+    assert _directed_edges_pair_up(F)
+    assert np.abs(orc.winding(V, F, orc.grid_points(g)) - f.reshape(-1)).max() < 1e-9
+
+
+def test_marching_cubes_sphere(orc):
+    """A sphere's distance field: vertices within 1e-3 of the radius at h = 1/24 (linear
+    interpolation of a smooth field, error O(h^2)), area within 1 % of 4 pi r^2, and the
+    enclosed volume within 2 % of 4/3 pi r^3."""
+    orc._MC_TRIS.clear()
+    g = wi.Grid.cube(24)
+    Q = orc.grid_points(g)
+    r = 0.3
+    V, F = orc.marching_cubes(0.5 + (r - np.linalg.norm(Q, axis=1)), g, 0.5)
+    assert _directed_edges_pair_up(F)
+    assert np.abs(np.linalg.norm(V, axis=1) - r).max() < 1e-3
+    area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
+    assert abs(area / (4 * math.pi * r * r) - 1) < 0.01
+    assert abs(signed_volume(V, F) / (4 / 3 * math.pi * r ** 3) - 1) < 0.02
+
+
 def test_laplacian_smoothing_closed_forms(orc):
     """Umbrella smoothing of regular solids shrinks them radially by a known factor per
     iteration: octahedron 1 - lam (neighbour mean is the centre), icosahedron
