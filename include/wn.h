@@ -362,6 +362,31 @@ WN_API wn_status wn_cubify(const uint8_t *occ, const wn_grid *grid, float *V, in
                            int64_t capF, int64_t *counts, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Marching cubes (the reconstruction Section 3 names when it motivates the measure) of a
+ * field f (float [P], C order like the grid points, e.g. W or a soft occupancy) at a
+ * level iso > 0: the surface between values > iso (inside) and values <= iso, the
+ * centres surrounded by one layer of zeros so that it is closed.  Cells join 8
+ * neighbouring centres; the triangles of each corner pattern come from one rule (on every
+ * cell face, counter-clockwise from outside, each entry crossing is joined to the next
+ * exit, which cuts inside corners off on their own; loops start at their lowest local
+ * edge and are fanned from their first vertex with no diagonal inside a cell face).
+ *   Vertices: one per crossed lattice edge, at the linear interpolation of the two
+ *     values, numbered by edge id 3 * (padded lattice index) + axis, where the padded
+ *     lattice has (n + 2) points per axis, point i at lo + (i - 1/2) h.
+ *   Faces: cell by cell in padded C order, each cell's triangles in table order, facing
+ *     outward (from inside to outside values).
+ * Writes counts[0] = nV, counts[1] = nF (device int64 [2]) and the first capV vertices
+ * (float [capV][3]) and capF faces (int32 [capF][3]).  Bounds: nV <= 3 L, nF <= 5 C with
+ * L = (nx+2)(ny+2)(nz+2) lattice points (3 L < 2^31) and C = (nx+1)(ny+1)(nz+1) cells.
+ * NaN values count as outside.  Workspace: wn_workspace_size_marching(grid) (0 when the
+ * grid is invalid or too large).
+ */
+WN_API size_t wn_workspace_size_marching(const wn_grid *grid);
+WN_API wn_status wn_marching_cubes(const float *f, const wn_grid *grid, float iso, float *V, int64_t capV,
+                                   int32_t *F, int64_t capF, int64_t *counts, void *ws, size_t ws_bytes,
+                                   void *stream);
+
+/*
  * Laplacian smoothing with the umbrella operator, `iters` Jacobi steps
  *   v <- v + lam (mean of the vertices joined to v by a face edge - v);
  * vertices without neighbours stay.  Each vertex adds its neighbours in increasing id

@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     wn_adam,
     wn_morph_step,
     wn_cubify,
+    wn_marching_cubes,
     wn_laplacian_smooth,
     wn_sample_surface,
     wn_nn_distance,

@@ -64,6 +64,8 @@ EXPORTED = (
     "wn_morph_step",
     "wn_workspace_size_cubify",
     "wn_cubify",
+    "wn_workspace_size_marching",
+    "wn_marching_cubes",
     "wn_laplacian_smooth",
     "wn_sample_surface",
     "wn_nn_distance",
@@ -158,6 +160,10 @@ def load():
     lib.wn_workspace_size_cubify.argtypes = [gp]
     lib.wn_cubify.restype = i32
     lib.wn_cubify.argtypes = [vp, gp, vp, i64, vp, i64, vp, vp, sz, vp]
+    lib.wn_workspace_size_marching.restype = sz
+    lib.wn_workspace_size_marching.argtypes = [gp]
+    lib.wn_marching_cubes.restype = i32
+    lib.wn_marching_cubes.argtypes = [vp, gp, f32, vp, i64, vp, i64, vp, vp, sz, vp]
     lib.wn_laplacian_smooth.restype = i32
     lib.wn_laplacian_smooth.argtypes = [vp, i64, vp, i64, f32, i32, vp, vp, sz, vp]
     lib.wn_sample_surface.restype = i32

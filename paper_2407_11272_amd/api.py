@@ -441,6 +441,41 @@ def wn_cubify(occ: torch.Tensor, grid: Grid):
     return V[:nV], F[:nF]
 
 
+def wn_marching_cubes(f: torch.Tensor, grid: Grid, iso: float = 0.5):
+    """Marching cubes of a field at the grid's voxel centres (float32, or uint8/bool read
+    as 0/1; grid.size values) at level ``iso`` > 0: (V [nV, 3], F [nF, 3]), closed by a
+    layer of zeros around the grid.  Reads the two counts back (one synchronisation)."""
+    grid = Grid.of(grid)
+    f = f.reshape(-1)
+    if f.dtype in (torch.bool, torch.uint8):
+        f = f.to(torch.float32)
+    if not (f.is_cuda and f.dtype == torch.float32 and f.is_contiguous() and f.numel() == grid.size):
+        raise ValueError("f must be a contiguous float32 (or uint8/bool) device tensor with one value per voxel")
+    dev = f.device
+    g = grid.to_c()
+    lib = L.load()
+    need = lib.wn_workspace_size_marching(ctypes.byref(g))
+    if need == 0:
+        raise ValueError("grid too large for marching cubes")
+    n = [int(x) for x in grid.n]
+    capV = 3 * (n[0] + 2) * (n[1] + 2) * (n[2] + 2)
+    capF = 5 * (n[0] + 1) * (n[1] + 1) * (n[2] + 1)
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    ws, wsb = Workspace.get(need, dev)
+    # first pass: counts only; then outputs of the exact size
+    st = lib.wn_marching_cubes(_ptr(f), ctypes.byref(g), float(iso), None, 0, None, 0, _ptr(counts), ws, wsb,
+                               _stream_handle(dev))
+    L.check("wn_marching_cubes", st)
+    nV, nF = (int(x) for x in counts.cpu())
+    assert nV <= capV and nF <= capF
+    V = torch.empty((nV, 3), dtype=torch.float32, device=dev)
+    F = torch.empty((nF, 3), dtype=torch.int32, device=dev)
+    st = lib.wn_marching_cubes(_ptr(f), ctypes.byref(g), float(iso), _ptr(V), nV, _ptr(F), nF, _ptr(counts), ws, wsb,
+                               _stream_handle(dev))
+    L.check("wn_marching_cubes", st)
+    return V, F
+
+
 def wn_laplacian_smooth(V: torch.Tensor, F: torch.Tensor, lam: float = 0.15, iters: int = 10) -> torch.Tensor:
     """Umbrella-operator Laplacian smoothing (Jacobi steps); returns new vertices."""
     _check_mesh(V, F)
@@ -491,11 +526,18 @@ def wn_chamfer_hausdorff(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
 
 
 def evaluate_occupancy(occ: torch.Tensor, grid: Grid, V_ref: torch.Tensor, F_ref: torch.Tensor,
-                       u_rec: torch.Tensor, u_ref: torch.Tensor, lam: float = 0.15, iters: int = 10):
-    """The paper's accuracy measure of an occupancy grid: cube surface, Laplacian
-    smoothing, surface samples of the result and of the reference mesh (uniform numbers
-    u_rec, u_ref), then (Chamfer, Hausdorff) as a device float64 [2]."""
-    Vc, Fc = wn_cubify(occ, grid)
+                       u_rec: torch.Tensor, u_ref: torch.Tensor, lam: float = 0.15, iters: int = 10,
+                       mesher: str = "cubes", iso: float = 0.5):
+    """The paper's accuracy measure of an occupancy grid: cube surface (``mesher="cubes"``,
+    of a uint8 occupancy) or marching cubes (``"marching"``, of any field at ``iso``),
+    Laplacian smoothing, surface samples of the result and of the reference mesh
+    (uniform numbers u_rec, u_ref), then (Chamfer, Hausdorff) as a device float64 [2]."""
+    if mesher == "cubes":
+        Vc, Fc = wn_cubify(occ, grid)
+    elif mesher == "marching":
+        Vc, Fc = wn_marching_cubes(occ, grid, iso)
+    else:
+        raise ValueError("mesher must be 'cubes' or 'marching'")
     Vs = wn_laplacian_smooth(Vc, Fc, lam, iters)
     Pa, _ = wn_sample_surface(Vs, Fc, u_rec)
     Pb, _ = wn_sample_surface(V_ref, F_ref, u_ref)

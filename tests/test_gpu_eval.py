@@ -188,3 +188,116 @@ def test_eval_argument_errors(dev):
     assert lib.wn_laplacian_smooth(p(A.data_ptr()), 4, None, 0, 0.15, 10, p(A.data_ptr()), base, 1 << 20,
                                    s) == L.WN_ERR_INVALID_ARG
     torch.cuda.synchronize()
+
+
+def _fields():
+    rng = np.random.default_rng(65)
+    out = []
+    for n, iso in (((6, 5, 4), 0.5), ((9, 9, 9), 0.3), ((2, 2, 2), 0.5), ((13, 7, 5), 0.8), ((1, 1, 1), 0.5)):
+        g = wi.Grid((-1.0, -0.25, 0.5), (1.0, 0.5, 2.5), n)
+        out.append((f"random{n}", g, rng.random(n).astype(np.float32).reshape(-1), iso))
+    c = wi.config1_icosphere(32)
+    W = orc_winding_grid_cache(c)
+    out.append(("icosphere W 32^3", c.grid, W, 0.5))
+    c2, occ = _union_occupancy(64)
+    out.append(("union occupancy 64^3", c2.grid, occ.astype(np.float32), 0.5))
+    return out
+
+
+_W_CACHE = {}
+
+
+def orc_winding_grid_cache(c):
+    import oracle
+    if "c1" not in _W_CACHE:
+        _W_CACHE["c1"] = oracle.winding_grid(np.asarray(c.V, np.float32).astype(np.float64), c.F,
+                                             c.grid).astype(np.float32)
+    return _W_CACHE["c1"]
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_marching_cubes_matches_oracle(dev, orc, case):
+    """Faces (integer work) bit-exact; vertices (one FP32 interpolation and one FMA) within
+    a few ulp of the coordinate range; every directed edge paired with its reverse."""
+    import paper_2407_11272_amd as wn
+    name, g, f, iso = _fields()[case]
+    V, F = wn.wn_marching_cubes(_cuda(f), g, iso)
+    Vr, Fr = orc.marching_cubes(f.astype(np.float64), g, iso)
+    print(f"[marching {name}] nV={len(Vr)} nF={len(Fr)}", flush=True)
+    assert F.shape == Fr.shape and V.shape == Vr.shape
+    Fg = F.cpu().numpy()
+    np.testing.assert_array_equal(Fg, Fr)
+    scale = max(np.abs(np.asarray(g.lo)).max(), np.abs(np.asarray(g.hi)).max())
+    assert np.all(np.abs(V.cpu().numpy() - Vr) <= 4 * np.spacing(np.float32(scale)))
+    if len(Fg):
+        d = np.concatenate([Fg[:, [0, 1]], Fg[:, [1, 2]], Fg[:, [2, 0]]])
+        u, cnt = np.unique(d, axis=0, return_counts=True)
+        assert np.all(cnt == 1) and len(np.unique(np.concatenate([u, u[:, ::-1]]), axis=0)) == len(u)
+
+
+def test_marching_cubes_edge_cases(dev):
+    import ctypes
+    import torch
+    import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd import _lib as L
+    lib = L.load()
+    # an empty grid and an all-outside field give nothing
+    V, F = wn.wn_marching_cubes(torch.zeros(0, device="cuda"), wi.Grid((0, 0, 0), (1, 1, 1), (0, 3, 3)))
+    assert V.shape == (0, 3) and F.shape == (0, 3)
+    V, F = wn.wn_marching_cubes(torch.zeros(27, device="cuda"), wi.Grid.cube(3))
+    assert V.shape == (0, 3) and F.shape == (0, 3)
+    # one inside voxel: the octahedron; small capacities write only what fits
+    g = wi.Grid.cube(3)
+    f = torch.zeros(27, device="cuda")
+    f[13] = 1.0
+    gc = wn.Grid.of(g).to_c()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    need = lib.wn_workspace_size_marching(ctypes.byref(gc))
+    ws = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    base = ctypes.c_void_p(ws.data_ptr() + ((-ws.data_ptr()) % 256))
+    Vb = torch.full((4, 3), -7.0, device="cuda")
+    Fb = torch.full((8, 3), -7, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    p = ctypes.c_void_p
+    assert lib.wn_marching_cubes(p(f.data_ptr()), ctypes.byref(gc), 0.5, p(Vb.data_ptr()), 3, p(Fb.data_ptr()), 5,
+                                 p(cnt.data_ptr()), base, need, s) == L.WN_OK
+    torch.cuda.synchronize()
+    assert cnt.tolist() == [6, 8]
+    assert torch.all(Vb[3] == -7.0) and torch.all(Fb[5:] == -7)
+    assert torch.all(Vb[:3] != -7.0) and torch.all(Fb[:5] >= 0)
+    # argument errors before any launch
+    for iso in (0.0, -1.0, float("nan"), float("inf")):
+        assert lib.wn_marching_cubes(p(f.data_ptr()), ctypes.byref(gc), iso, None, 0, None, 0, p(cnt.data_ptr()),
+                                     base, need, s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_marching_cubes(None, ctypes.byref(gc), 0.5, None, 0, None, 0, p(cnt.data_ptr()), base, need,
+                                 s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_marching_cubes(p(f.data_ptr()), ctypes.byref(gc), 0.5, None, 0, None, 0, None, base, need,
+                                 s) == L.WN_ERR_INVALID_ARG
+    assert lib.wn_marching_cubes(p(f.data_ptr()), ctypes.byref(gc), 0.5, None, 0, None, 0, p(cnt.data_ptr()), base,
+                                 need - 1, s) == L.WN_ERR_WORKSPACE
+    assert lib.wn_marching_cubes(p(f.data_ptr()), ctypes.byref(gc), 0.5, None, 1, None, 0, p(cnt.data_ptr()), base,
+                                 need, s) == L.WN_ERR_INVALID_ARG
+    big = wn.Grid.cube(1000).to_c()
+    assert lib.wn_workspace_size_marching(ctypes.byref(big)) == 0
+    torch.cuda.synchronize()
+
+
+def test_evaluation_chain_marching_matches_oracle(dev, orc):
+    """The chain with marching cubes of W (level 0.5) of the 1280-face icosphere at 64^3
+    in place of the cube surface; the same bars as the cube-surface chain."""
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere(64)
+    V32 = np.asarray(c.V, np.float32)
+    W = orc.winding_grid(V32.astype(np.float64), c.F, c.grid).astype(np.float32)
+    ua, ub = wi.evaluation_samples()
+    m = wn.evaluate_occupancy(_cuda(W), c.grid, _cuda(V32), _cuda(np.asarray(c.F, np.int32)), _cuda(ua),
+                              _cuda(ub), mesher="marching").cpu().numpy()
+    Vm, Fm = orc.marching_cubes(W.astype(np.float64), c.grid, 0.5)
+    Vs = orc.laplacian_smooth(Vm.astype(np.float32).astype(np.float64), Fm)
+    Pa, _ = orc.sample_surface(Vs, Fm, ua)
+    Pb, _ = orc.sample_surface(V32.astype(np.float64), c.F, ub)
+    cd, hd = orc.chamfer_hausdorff(Pa, Pb)
+    print(f"[eval chain marching 64^3] Chamfer {m[0]:.6f} vs {cd:.6f}, Hausdorff {m[1]:.6f} vs {hd:.6f}", flush=True)
+    h = 1.0 / 64
+    assert abs(m[0] - cd) <= 0.02 * cd and abs(m[1] - hd) <= h
+    assert cd < h and hd < 2 * h
