@@ -172,9 +172,13 @@ __global__ __launch_bounds__(kBlock) void k_loss_final(const float *__restrict__
 // ---------------------------------------------------------------- launchers
 
 int fwd_split_count(int64_t nR, int64_t nQ) {
-    // Aim for about 8192 wave64s; never give a split fewer than 2 tiles of records.
+    // Aim for about 131072 wave64s of (point block, record split) units, about 16
+    // rounds of resident workgroups, so that the last, partly filled round costs little
+    // (one round of 8192 point blocks left the GPU 5-10 % idle at the end); never give a
+    // split fewer than 2 tiles of records.  Depends only on (nR, nQ), so results do not
+    // depend on the launch configuration.
     const int64_t waves = (nQ + 63) / 64;
-    int64_t s = (8192 + waves - 1) / (waves > 0 ? waves : 1);
+    int64_t s = (131072 + waves - 1) / (waves > 0 ? waves : 1);
     const int64_t max_by_faces = (nR + 2 * kRecTile - 1) / (2 * kRecTile);
     if (s > max_by_faces) s = max_by_faces;
     if (s > 64) s = 64;

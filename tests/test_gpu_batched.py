@@ -81,10 +81,14 @@ def test_small_batch_vs_oracle_and_plain(dev, orc):
 
 def test_single_chunk_mesh_matches_plain_bitwise(dev):
     """A mesh of at most one chunk (<= 4096 faces) on a grid large enough that the plain
-    launch does not split the faces: both sum the same tiles in the same order."""
+    launch does not split the faces (at least 131072 point waves: 256^3): both sum the
+    same tiles in the same order."""
     import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd import _lib as L
     c = wi.config1_icosphere()
-    j = _job(c.V, c.F, wi.Grid.cube(128))
+    j = _job(c.V, c.F, wi.Grid.cube(256))
+    # no split: the plain workspace holds no per-split partials
+    assert wn.wn_workspace_size(L.WN_OP_VOXELIZE, len(c.V), len(c.F), 256 ** 3) < 256 ** 3 * 4
     Wb = _run([j])[0]
     Wp = wn.wn_voxelize(j.V, j.F, grid=j.grid).cpu().numpy().reshape(-1)
     np.testing.assert_array_equal(Wp, Wb)
@@ -211,7 +215,7 @@ def test_batched_strips_alone_mix_and_plain(dev):
         plain_trivial = wn.wn_voxelize(j.V, j.F, grid=j.grid).cpu().numpy().reshape(-1)
         assert np.abs(plain_trivial - mix[i]).max() <= 2e-6
     V, F = wi.icosphere(3)
-    j = _job(0.4 * V, F, wi.Grid.cube(128))
+    j = _job(0.4 * V, F, wi.Grid.cube(256))   # enough point waves for an unsplit plain launch
     j.strips = torch.as_tensor(wn.wn_build_strips(F, len(V))).cuda()
     b = _run([j])[0]
     p = wn.wn_voxelize_strips(j.V, j.F, j.strips, grid=j.grid).cpu().numpy().reshape(-1)
