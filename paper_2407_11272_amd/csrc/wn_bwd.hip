@@ -269,13 +269,15 @@ struct BwdPlan {
 
 }  // namespace
 
-// Points per split: the caller's chunk, or by default about 8192 waves over the face
-// waves and splits (at most 512 splits), rounded up to whole point tiles.
+// Points per split: the caller's chunk, or by default about 32768 waves over the face
+// waves and splits (at most 4096 splits), rounded up to whole point tiles.  Several
+// rounds of resident workgroups keep the last, partly filled round short; more splits
+// than that cost more in the per-split sums than they save.
 int64_t bwd_chunk(int64_t nF, int64_t nQ, int64_t chunk) {
     if (chunk > 0) return chunk;
     const int64_t face_waves = (nF + 63) / 64;
-    int64_t sp = (8192 + face_waves - 1) / (face_waves > 0 ? face_waves : 1);
-    if (sp > 512) sp = 512;
+    int64_t sp = (32768 + face_waves - 1) / (face_waves > 0 ? face_waves : 1);
+    if (sp > 4096) sp = 4096;
     const int64_t max_by_points = (nQ + kPointTile - 1) / kPointTile;
     if (sp > max_by_points) sp = max_by_points;
     if (sp < 1) sp = 1;
