@@ -496,8 +496,8 @@ def main():
                     help="skip the three-records-per-face comparison launches (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by voxel slabs with no collective; see the design notes)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported (the path would shard by voxel "
+              "slabs, each GPU writing its own slab of W, with no collective)", file=sys.stderr)
         sys.exit(2)
 
     import torch
