@@ -145,11 +145,10 @@ def wn_build_strips(F, nV: int | None = None):
     Fh = np.ascontiguousarray(torch.as_tensor(F).cpu().numpy(), dtype=np.int32).reshape(-1, 3)
     nV = int(Fh.max()) + 1 if nV is None and len(Fh) else int(nV or 0)
     n = ctypes.c_int64(0)
-    L.check("wn_build_strips", lib.wn_build_strips(Fh.ctypes.data, len(Fh), nV, None, 0, ctypes.byref(n)))
-    out = np.empty((n.value, 2), dtype=np.int32)
-    L.check("wn_build_strips", lib.wn_build_strips(Fh.ctypes.data, len(Fh), nV, out.ctypes.data, n.value,
+    out = np.empty((3 * len(Fh), 2), dtype=np.int32)   # at most 3 records per face: one call
+    L.check("wn_build_strips", lib.wn_build_strips(Fh.ctypes.data, len(Fh), nV, out.ctypes.data, len(out),
                                                    ctypes.byref(n)))
-    return out
+    return out[:n.value].copy()
 
 
 def wn_voxelize_strips(V, F, strips: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None,

@@ -180,6 +180,9 @@ class Server:
             a.adj_chunk = adjoint_chunk(nF, P)
             work += self.adj_cost * P * nF
         a.deadline = req.arrival + self.slack * work / self.rate + self.base
+        prep = getattr(self.ex, "prepare", None)
+        if prep is not None:
+            prep(req)   # host-side work that can start before admission (strip order)
         self.pending.append(a)
         return res
 
@@ -334,6 +337,7 @@ class GpuExecutor:
     completion times from timing events."""
 
     def __init__(self, device="cuda", graph: bool = True, strips: bool = True):
+        import concurrent.futures
         import torch
         self.torch = torch
         self.strips = strips
@@ -343,6 +347,15 @@ class GpuExecutor:
         self.inflight = collections.deque()
         self.ref = None
         self.t_ref = 0.0
+        # strip orders are built on host threads from submission on (the builder is a C
+        # call that releases the interpreter lock), off the loop that keeps the GPU fed
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=2)
+        self.strip_jobs = {}
+
+    def prepare(self, req: ServeRequest):
+        import paper_2407_11272_amd as wn
+        if self.strips and len(req.F):
+            self.strip_jobs[req.rid] = self.pool.submit(wn.wn_build_strips, req.F, len(req.V))
 
     def start(self, t0: float):
         torch = self.torch
@@ -364,7 +377,9 @@ class GpuExecutor:
             st["hold"] = (V, F)
             R = None
             if self.strips and len(req.F):
-                Rh = torch.from_numpy(wn.wn_build_strips(req.F, len(req.V))).pin_memory()
+                job = self.strip_jobs.pop(req.rid, None)
+                rec = job.result() if job is not None else wn.wn_build_strips(req.F, len(req.V))
+                Rh = torch.from_numpy(rec).pin_memory()
                 R = Rh.to(self.dev, non_blocking=True)
                 st["hold_strips"] = Rh
             job = wn.MeshJob(st["V"], st["F"], wn.Grid.of(req.grid), req.occupancy, req.tau, req.k, strips=R)
