@@ -3,8 +3,9 @@
 Requests arrive over time (a mesh, a grid, and optionally a loss target when the
 caller wants d(loss)/d(vertices)).  The loop
 
-  * admits arrivals in order while a slot is free and the request's device footprint
-    fits in the HBM budget (a request larger than the whole budget is rejected);
+  * admits arrivals in order while a slot is free (a slot is held until the request's
+    work is all launched) and the request's device footprint fits in the HBM budget (a
+    request larger than the whole budget is rejected);
   * keeps each admitted request's mesh, grid outputs and gradient buffers resident
     on the device until it completes;
   * cuts every request into units of work: slices of its voxels for the forward pass
@@ -191,8 +192,15 @@ class Server:
         pts = max(POINT_QUANTUM, int(per) // POINT_QUANTUM * POINT_QUANTUM)
         return min(pts, req.points)
 
+    def _working(self) -> int:
+        """Admitted requests with work still to launch.  A request whose work is all
+        launched gives its slot back at once (its memory stays counted until it
+        completes), so the next one is admitted while its last steps run and the GPU
+        does not drain between them."""
+        return sum(1 for a in self.active if not a.all_launched)
+
     def _admit(self, now: float):
-        while self.pending and len(self.active) < self.slots:
+        while self.pending and self._working() < self.slots:
             a = self.pending[0]
             if self.in_use + a.footprint > self.budget:
                 break  # in order: wait for memory to free up
@@ -202,7 +210,7 @@ class Server:
             self.active.append(a)
             self.in_use += a.footprint
             self.peak_in_use = max(self.peak_in_use, self.in_use)
-            self.peak_active = max(self.peak_active, len(self.active))
+            self.peak_active = max(self.peak_active, self._working())
 
     # ------------------------------------------------------------------ step
     def _plan(self):
