@@ -115,8 +115,11 @@ def _lib():
 def adjoint_chunk(nF: int, P: int) -> int:
     """Points per adjoint split of a served gradient request: the library's default for
     (nF, P), at most ADJOINT_MAX_CHUNK, so that a step's worth of splits fills the GPU
-    whatever the face count.  Depends only on the request."""
-    return int(min(ADJOINT_MAX_CHUNK, _lib().wn_backward_chunk(max(0, nF), max(0, P), 0)))
+    whatever the face count, and large enough for at most 65535 splits.  Depends only on
+    the request."""
+    c = int(min(ADJOINT_MAX_CHUNK, _lib().wn_backward_chunk(max(0, nF), max(0, P), 0)))
+    least = -(-max(0, P) // 65535)
+    return max(c, -(-least // 256) * 256)
 
 
 def footprint_bytes(req: ServeRequest, slice_points: int) -> int:
@@ -130,6 +133,8 @@ def footprint_bytes(req: ServeRequest, slice_points: int) -> int:
         # target, dL/dW, dL/dV, and the adjoint's own workspace (face records, per-split
         # corner sums, corner sort buffers, vertex bounds)
         ws = _lib().wn_workspace_size_backward(nV, nF, P, adjoint_chunk(nF, P))
+        if ws == 0:
+            raise ValueError("sizes out of range for the adjoint")
         b += 8 * P + 12 * nV + int(ws) + 512
     return int(b)
 
@@ -169,7 +174,12 @@ class Server:
         res = ServeResult(req.rid, req.arrival)
         self.results[req.rid] = res
         max_slice = self._max_slice_points(req)
-        fp = footprint_bytes(req, max_slice)
+        try:
+            fp = footprint_bytes(req, max_slice)
+        except ValueError as err:
+            res.rejected = True
+            res.error = str(err)
+            return res
         if fp > self.budget:
             res.rejected = True
             res.error = f"footprint {fp} B exceeds the HBM budget {self.budget} B"

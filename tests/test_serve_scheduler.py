@@ -244,3 +244,10 @@ def test_degenerate_requests_complete(policy):
         if r.wants_grad:
             units = ex.adj[r.rid]
             assert units and units[-1][2] and sum(n for _, n, _, _ in units) == r.points
+
+
+def test_adjoint_split_count_stays_within_the_library_limit():
+    # a huge grid: the split size grows so that there are at most 65535 splits
+    P = 1024 ** 3
+    c = adjoint_chunk(100000, P)
+    assert c % 256 == 0 and -(-P // c) <= 65535
