@@ -17,8 +17,9 @@ caller wants d(loss)/d(vertices)).  The loop
     to requests in deadline order, so short requests overtake long ones while a long
     request, once its deadline is the earliest, is not starved.  Under the share
     policies every request gets a slice in proportion to a weight (equal, or growing
-    with its age).  All forward slices of a step run in ONE batched persistent launch,
-    then the adjoint units, on one stream;
+    with its age).  All forward slices of a step run in ONE batched persistent launch;
+    the step's losses and adjoint units follow it on a second stream, overlapping with
+    the next step's forward;
   * completion times come from device events, so latency = completion - arrival is
     not delayed by host polling.
 
@@ -350,9 +351,9 @@ def latency_stats(results) -> dict:
 # ============================================================== GPU executor
 
 class GpuExecutor:
-    """Device side of the server: uploads, then per step one batched forward launch, the
-    loss of requests whose forward completed, and adjoint units, in order on one stream;
-    completion times from timing events."""
+    """Device side of the server: uploads, then per step one batched forward launch on
+    the forward stream, and the loss of requests whose forward completed and adjoint
+    units on a second stream after that forward; completion times from timing events."""
 
     def __init__(self, device="cuda", graph: bool = True, strips: bool = True):
         import concurrent.futures
@@ -361,6 +362,7 @@ class GpuExecutor:
         self.strips = strips
         self.dev = torch.device(device)
         self.fwd = torch.cuda.Stream(self.dev)
+        self.aux = torch.cuda.Stream(self.dev)   # losses and adjoint units (default priority)
         self.graph = graph
         self.inflight = collections.deque()
         self.ref = None
@@ -415,12 +417,16 @@ class GpuExecutor:
         while len(self.inflight) > max(0, keep):
             self.inflight.popleft().synchronize()
 
-    def _done_event(self, st):
+    def _done_event(self, st, stream):
         ev = self.torch.cuda.Event(enable_timing=True)
-        ev.record(self.fwd)
+        ev.record(stream)
         st["done"] = ev
 
     def launch_step(self, fwd, fdone, adj):
+        """The step's batched forward on the forward stream; its losses and adjoint units
+        on the second stream after that forward, so that they overlap with the next
+        step's forward and each launch's last, partly filled round is filled by the
+        other stream's work."""
         import paper_2407_11272_amd as wn
         torch = self.torch
         with torch.cuda.stream(self.fwd):
@@ -432,20 +438,28 @@ class GpuExecutor:
                                            base.occ, point_begin=p0, point_count=n, strips=base.strips))
                 wn.wn_voxelize_batched(jobs, graph=self.graph)
             for st, req in fdone:
-                if req.wants_grad:
-                    W = st["job"].W.reshape(-1)
-                    st["loss"], _ = wn.wn_sigmoid_mse(W, st["target"], req.tau, req.k, dLdW=st["dLdW"])
-                    st["adj"].begin()
-                else:
-                    self._done_event(st)
+                if not req.wants_grad:
+                    self._done_event(st, self.fwd)
+            fev = torch.cuda.Event()
+            fev.record(self.fwd)
+        grads = [(st, req) for st, req in fdone if req.wants_grad]
+        if not grads and not adj:
+            self.inflight.append(fev)
+            return
+        self.aux.wait_event(fev)
+        with torch.cuda.stream(self.aux):
+            for st, req in grads:
+                W = st["job"].W.reshape(-1)
+                st["loss"], _ = wn.wn_sigmoid_mse(W, st["target"], req.tau, req.k, dLdW=st["dLdW"])
+                st["adj"].begin()
             for st, req, p0, n, last in adj:
                 if n > 0:
                     st["adj"].points(p0, n, st["dLdW"])
                 if last:
                     st["dLdV"] = st["adj"].end()
-                    self._done_event(st)
+                    self._done_event(st, self.aux)
             ev = torch.cuda.Event()
-            ev.record(self.fwd)
+            ev.record(self.aux)
         self.inflight.append(ev)
 
     def done_time(self, st):
