@@ -137,8 +137,19 @@ __global__ __launch_bounds__(kBlock) void k_bwd_reduce(const float *__restrict__
     if (t >= (int64_t)nF * 9) return;
     const int32_t i = (int32_t)(t / nF);
     const int32_t f = (int32_t)(t - (int64_t)i * nF);
+    const float *p = partials + (int64_t)i * nF + f;
+    const int64_t stride = (int64_t)9 * nF;  // from one split to the next
     float s = 0.0f, c = 0.0f;
-    for (int32_t k = 0; k < split; ++k) neumaier_add(s, c, partials[((int64_t)k * 9 + i) * nF + f]);
+    int32_t k = 0;
+    // eight loads in flight, then added in split order (the same order as one at a time)
+    for (; k + 8 <= split; k += 8) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = p[(int64_t)(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) neumaier_add(s, c, x[u]);
+    }
+    for (; k < split; ++k) neumaier_add(s, c, p[(int64_t)k * stride]);
     T[(int64_t)f * 9 + i] = (s + c) * scale;
 }
 
