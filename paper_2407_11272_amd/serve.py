@@ -146,7 +146,8 @@ class Server:
     def __init__(self, executor, hbm_budget: int = 64 << 30, slots: int = 16,
                  quantum_pairs: float = 2.0e10, max_inflight: int = 2, clock=time.perf_counter,
                  policy: str | None = None, adjoint_cost: float = ADJOINT_COST, rate_pairs: float = RATE_PAIRS,
-                 deadline_slack: float = DEADLINE_SLACK, deadline_base: float = DEADLINE_BASE):
+                 deadline_slack: float = DEADLINE_SLACK, deadline_base: float = DEADLINE_BASE,
+                 admit_per_step: int = 2):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.slots = int(slots)
@@ -160,6 +161,9 @@ class Server:
         self.rate = float(rate_pairs)
         self.slack = float(deadline_slack)
         self.base = float(deadline_base)
+        # admissions per step: each uploads a mesh from the host, so a burst of arrivals
+        # is admitted a few at a time while the GPU works on the admitted ones
+        self.admit_per_step = max(1, int(admit_per_step))
         self.pending = collections.deque()   # arrived, not yet admitted
         self.active: list[_Active] = []
         self.in_use = 0
@@ -211,11 +215,13 @@ class Server:
         return sum(1 for a in self.active if not a.all_launched)
 
     def _admit(self, now: float):
-        while self.pending and self._working() < self.slots:
+        admitted = 0
+        while self.pending and self._working() < self.slots and admitted < self.admit_per_step:
             a = self.pending[0]
             if self.in_use + a.footprint > self.budget:
                 break  # in order: wait for memory to free up
             self.pending.popleft()
+            admitted += 1
             a.res.admitted = now
             a.state = self.ex.admit(a.req, a.adj_chunk)
             self.active.append(a)
