@@ -174,6 +174,24 @@ def test_slot_limit_and_in_order_admission():
     assert all(np.isfinite(r.done) for r in out)
 
 
+@pytest.mark.parametrize("per_step", [0, 1, 2, 5])
+def test_a_burst_is_admitted_a_few_per_step(per_step):
+    """Arrivals are admitted at most `admit_per_step` per scheduler step (at least one), in
+    arrival order, and every request still completes."""
+    reqs = [_req(i, 5000, 64, 0.0) for i in range(12)]
+    srv, ex, out = _run(reqs, slots=16, quantum_pairs=1e12, admit_per_step=per_step)
+    limit = max(1, per_step)
+    first_step = {}
+    for k, rids in enumerate(ex.steps):
+        for rid in rids:
+            first_step.setdefault(rid, k)
+    per = np.bincount(list(first_step.values()))
+    assert per.max() <= limit and per[0] == limit
+    order = [rid for rid, _ in sorted(first_step.items(), key=lambda kv: (kv[1], kv[0]))]
+    assert order == sorted(order)
+    assert all(np.isfinite(r.done) for r in out)
+
+
 @pytest.mark.parametrize("policy", ["edf", "fair", "age"])
 def test_steps_mix_requests_and_small_ones_overtake_large(policy):
     """A small request arriving during a large one shares the next steps with it and
