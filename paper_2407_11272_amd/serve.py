@@ -147,7 +147,7 @@ class Server:
                  quantum_pairs: float = 2.0e10, max_inflight: int = 2, clock=time.perf_counter,
                  policy: str | None = None, adjoint_cost: float = ADJOINT_COST, rate_pairs: float = RATE_PAIRS,
                  deadline_slack: float = DEADLINE_SLACK, deadline_base: float = DEADLINE_BASE,
-                 admit_per_step: int = 2):
+                 admit_ms: float = 4.0):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.slots = int(slots)
@@ -161,9 +161,11 @@ class Server:
         self.rate = float(rate_pairs)
         self.slack = float(deadline_slack)
         self.base = float(deadline_base)
-        # admissions per step: each uploads a mesh from the host, so a burst of arrivals
-        # is admitted a few at a time while the GPU works on the admitted ones
-        self.admit_per_step = max(1, int(admit_per_step))
+        # host time per step for admissions (at least one is admitted): each uploads a mesh
+        # (and a gradient request its target), so a burst of large arrivals is spread over
+        # steps while the GPU works on those already admitted, and small ones still enter
+        # many at a time
+        self.admit_s = max(0.0, float(admit_ms)) / 1e3
         self.pending = collections.deque()   # arrived, not yet admitted
         self.active: list[_Active] = []
         self.in_use = 0
@@ -215,8 +217,11 @@ class Server:
         return sum(1 for a in self.active if not a.all_launched)
 
     def _admit(self, now: float):
+        t_start = self.clock()
         admitted = 0
-        while self.pending and self._working() < self.slots and admitted < self.admit_per_step:
+        while self.pending and self._working() < self.slots:
+            if admitted and self.clock() - t_start >= self.admit_s:
+                break
             a = self.pending[0]
             if self.in_use + a.footprint > self.budget:
                 break  # in order: wait for memory to free up

@@ -26,8 +26,9 @@ class VClock:
 
 class FakeExecutor:
     def __init__(self, clock: VClock, rate: float = 5e11, step_overhead: float = 1e-4,
-                 adjoint_cost: float = ADJOINT_COST):
+                 adjoint_cost: float = ADJOINT_COST, upload_s: float = 0.0):
         self.clock = clock
+        self.upload_s = upload_s
         self.rate = rate
         self.overhead = step_overhead
         self.adj_cost = adjoint_cost
@@ -42,6 +43,7 @@ class FakeExecutor:
         pass
 
     def admit(self, req, adj_chunk=0):
+        self.clock.t += self.upload_s   # host time of the upload
         self.slices[req.rid] = []
         self.adj[req.rid] = []
         return {"rid": req.rid, "chunk": adj_chunk}
@@ -93,9 +95,9 @@ def _req(rid, faces, res, arrival, grad=False):
     return ServeRequest(rid, V, F, g, arrival, "sigmoid" if grad else "threshold", target)
 
 
-def _run(reqs, **kw):
+def _run(reqs, upload_s=0.0, **kw):
     clock = VClock()
-    ex = FakeExecutor(clock)
+    ex = FakeExecutor(clock, upload_s=upload_s)
     srv = Server(ex, clock=clock, **kw)
     out = srv.run_trace(reqs, idle_sleep=1e-3)
     return srv, ex, out
@@ -174,19 +176,19 @@ def test_slot_limit_and_in_order_admission():
     assert all(np.isfinite(r.done) for r in out)
 
 
-@pytest.mark.parametrize("per_step", [0, 1, 2, 5])
-def test_a_burst_is_admitted_a_few_per_step(per_step):
-    """Arrivals are admitted at most `admit_per_step` per scheduler step (at least one), in
-    arrival order, and every request still completes."""
+@pytest.mark.parametrize("admit_ms,upload_ms,per_step", [(4.0, 0.0, 12), (4.0, 3.0, 2), (4.0, 1.5, 3),
+                                                           (0.0, 1.0, 1), (10.0, 20.0, 1)])
+def test_admissions_per_step_follow_the_host_time_budget(admit_ms, upload_ms, per_step):
+    """Each step admits arrivals in order until their uploads have used `admit_ms` of host
+    time (at least one per step); every request still completes."""
     reqs = [_req(i, 5000, 64, 0.0) for i in range(12)]
-    srv, ex, out = _run(reqs, slots=16, quantum_pairs=1e12, admit_per_step=per_step)
-    limit = max(1, per_step)
+    srv, ex, out = _run(reqs, upload_s=upload_ms / 1e3, slots=16, quantum_pairs=1e12, admit_ms=admit_ms)
     first_step = {}
     for k, rids in enumerate(ex.steps):
         for rid in rids:
             first_step.setdefault(rid, k)
     per = np.bincount(list(first_step.values()))
-    assert per.max() <= limit and per[0] == limit
+    assert per[0] == per_step and per.max() <= per_step
     order = [rid for rid, _ in sorted(first_step.items(), key=lambda kv: (kv[1], kv[0]))]
     assert order == sorted(order)
     assert all(np.isfinite(r.done) for r in out)
