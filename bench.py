@@ -195,7 +195,7 @@ def bench_batched(reps: int, autotune: bool):
 
 
 def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s: float, warmup_frac: float = 0.0,
-                 policy: str = "edf"):
+                 policy: str = "edf", step_pairs: float | None = None):
     """Poisson trace through the continuous-batching server and through the plain FIFO
     one-mesh-per-launch loop, at each offered load in ``loads``; p50/p99 latency and
     throughput of both.  A load puts the offered GPU time at that fraction of the wall
@@ -209,8 +209,9 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
     import numpy as np
     import torch
     import wn_inputs as wi
-    from paper_2407_11272_amd.serve import (GpuExecutor, Server, ServeRequest, latency_stats,
+    from paper_2407_11272_amd.serve import (STEP_PAIRS, GpuExecutor, Server, ServeRequest, latency_stats,
                                             run_plain_fifo)
+    step_pairs = STEP_PAIRS if step_pairs is None else float(step_pairs)
     base = wi.config5_trace(n_requests, 1.0)  # arrivals at rate 1; rate r divides them by r
     mean_pairs = float(np.mean([r.faces * r.res ** 3 * (2 if r.wants_grad else 1) for r in base]))
     mean_gpu_s = float(np.mean([r.faces * r.res ** 3 * (1.0 / fwd_pairs_per_s
@@ -244,7 +245,7 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
         print(f"# served load {load}: continuous batching ({len(reqs)} requests)", file=sys.stderr, flush=True)
 
         srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
-                     slots=16, quantum_pairs=2e10, policy=policy, adjoint_cost=fwd_pairs_per_s / adj_pairs_per_s,
+                     slots=16, quantum_pairs=step_pairs, policy=policy, adjoint_cost=fwd_pairs_per_s / adj_pairs_per_s,
                      rate_pairs=fwd_pairs_per_s)
         served = srv.run_trace(reqs)
         s_stats = summary(served)
@@ -274,7 +275,7 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
 
     print("# served burst: continuous batching", file=sys.stderr, flush=True)
     srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
-                 slots=16, quantum_pairs=2e10, policy=policy, adjoint_cost=fwd_pairs_per_s / adj_pairs_per_s,
+                 slots=16, quantum_pairs=step_pairs, policy=policy, adjoint_cost=fwd_pairs_per_s / adj_pairs_per_s,
                  rate_pairs=fwd_pairs_per_s)
     b_served = burst(srv.run_trace(reqs))
     torch.cuda.synchronize()
@@ -289,6 +290,7 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
         "workload": f"{n_requests} Poisson requests, 1k-100k faces log-uniform, grids 64^3/128^3/256^3, "
                     f"30% with dL/dV (sigmoid-MSE), offered load swept, first {warmup_frac:.0%} not counted",
         "policy": policy,
+        "step_pairs": step_pairs,
         "adjoint_cost": fwd_pairs_per_s / adj_pairs_per_s,
         "mean_pairs_per_request": mean_pairs,
         "mean_gpu_ms_per_request": mean_gpu_s * 1e3,
@@ -490,6 +492,8 @@ def main():
                     help="comma list of offered loads (fractions of the GPU's measured capacity)")
     ap.add_argument("--served-policy", default="edf", choices=("edf", "fair", "age"),
                     help="scheduler policy of the served row (earliest deadline first, or shares)")
+    ap.add_argument("--served-step-pairs", type=float, default=None,
+                    help="pairs of work per scheduler step (default: the server's)")
     ap.add_argument("--served-warmup", type=float, default=0.0,
                     help="fraction of the served requests (earliest arrivals) left out of the statistics")
     ap.add_argument("--no-compare", action="store_true",
@@ -572,7 +576,7 @@ def main():
         rows["served"] = bench_served(args.served_requests, [float(x) for x in args.served_loads.split(",")],
                                       rows["batched"]["batched_pairs_per_s"],
                                       rows["adjoint"]["adjoint_pairs_per_s"], args.served_warmup,
-                                      args.served_policy)
+                                      args.served_policy, args.served_step_pairs)
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
         rows["naive"] = bench_naive(3, not args.no_autotune)

@@ -38,6 +38,7 @@ from dataclasses import dataclass
 import numpy as np
 
 POINT_QUANTUM = 2048      # forward slices are multiples of this many voxels
+STEP_PAIRS = 4.0e10       # point-face pairs of work per scheduler step (adjoint pairs weighted)
 POLICY = "edf"            # "edf": earliest deadline first; "fair": equal shares; "age": shares grow with age
 AGE_TAU = 0.25            # seconds of waiting that double a request's share under "age"
 ADJOINT_COST = 2.8        # cost of one adjoint (point, face) pair in forward pairs
@@ -144,7 +145,7 @@ class Server:
     """The scheduler.  ``executor`` performs device work; ``clock`` returns seconds."""
 
     def __init__(self, executor, hbm_budget: int = 64 << 30, slots: int = 16,
-                 quantum_pairs: float = 2.0e10, max_inflight: int = 2, clock=time.perf_counter,
+                 quantum_pairs: float = STEP_PAIRS, max_inflight: int = 2, clock=time.perf_counter,
                  policy: str | None = None, adjoint_cost: float = ADJOINT_COST, rate_pairs: float = RATE_PAIRS,
                  deadline_slack: float = DEADLINE_SLACK, deadline_base: float = DEADLINE_BASE,
                  admit_ms: float = 4.0):
