@@ -1,13 +1,18 @@
 """Build the gfx950 shared library ``libwn.so`` in-tree with hipcc.
 
 Usage: ``python -m paper_2407_11272_amd.build`` (or ``build()`` from Python).
+Each ``csrc/*.hip`` file is compiled to an object of its own (in parallel), then the
+objects are linked into the shared library.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
+import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -16,33 +21,48 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwn.so")
 ARCH = "gfx950"
 
-HIPCC_FLAGS = [
+COMPILE_FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-result",
     # packed FP32 instructions stay off: the kernels are written for scalar FP32
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden",
 ]
+LINK_FLAGS = [f"--offload-arch={ARCH}", "-shared", "-fPIC"]
 
 
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False, out: str | None = None) -> str:
+def build(verbose: bool = False, out: str | None = None, jobs: int | None = None) -> str:
     out = out or LIB
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = out + f".tmp{os.getpid()}"
-    cmd = [hipcc, *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, out)
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1))
+    tmpdir = tempfile.mkdtemp(prefix="wn_build_")
+    try:
+        def compile_one(src):
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            cmd = [hipcc, *COMPILE_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            return obj
+
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as pool:
+            objs = list(pool.map(compile_one, sources()))
+        tmp = out + f".tmp{os.getpid()}"
+        cmd = [hipcc, *LINK_FLAGS, "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, out)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return out
 
 
