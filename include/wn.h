@@ -424,8 +424,31 @@ WN_API wn_status wn_chamfer_hausdorff(const float *A, int64_t nA, const float *B
                                       void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): wn_voxelize_strips without the
+ * workspace arguments.  The workspace lives in a fixed device array of
+ * WN_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from the first call on
+ * that GPU until the process ends; the call allocates nothing.  Inputs and outputs are
+ * the caller's, with the meaning, layout and results of wn_voxelize_strips (bit-identical
+ * to it).  A stream of n_records records over nQ points needs the workspace
+ * wn_voxelize_strips would need, at most wn_workspace_size(WN_OP_VOXELIZE, nV,
+ * ceil(n_records / 3), nQ) bytes; a larger request returns WN_ERR_WORKSPACE before
+ * anything is enqueued.  Every call on one GPU shares that GPU's array (the last call's
+ * contents stay), so calls that may overlap on one GPU -- on different streams, or from
+ * different threads without ordering -- race and must not be issued.  Its device error
+ * record (an index out of range) is read with wn_get_device_error(NULL, stream) on the
+ * same GPU.
+ */
+#define WN_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+WN_API wn_status wn_voxelize_strips_noalloc(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                                            const int32_t *strips, int64_t n_records, const wn_grid *grid,
+                                            const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau,
+                                            float k, void *occ, void *stream);
+
+/*
  * Reads and clears the device-side error record that the most recent call using
- * this workspace left (a face index out of range).  Synchronises `stream`.
+ * this workspace left (a face index out of range); ws = NULL reads the record of
+ * wn_voxelize_strips_noalloc on the current GPU.  Synchronises `stream`.
  * Returns WN_OK or WN_ERR_BAD_INDEX.
  */
 WN_API wn_status wn_get_device_error(void *ws, void *stream);

@@ -39,6 +39,8 @@ WN_INTEGRAL_NAIVE = 1
 
 WN_BATCH_NO_GRAPH = 1
 
+WN_NOALLOC_SCRATCH_BYTES = 96 << 20
+
 WN_BWD_BEGIN = 1
 WN_BWD_END = 2
 
@@ -70,6 +72,7 @@ EXPORTED = (
     "wn_sample_surface",
     "wn_nn_distance",
     "wn_chamfer_hausdorff",
+    "wn_voxelize_strips_noalloc",
     "wn_get_device_error",
     "wn_status_string",
     "wn_version",
@@ -172,6 +175,8 @@ def load():
     lib.wn_nn_distance.argtypes = [vp, i64, vp, i64, vp, vp, sz, vp]
     lib.wn_chamfer_hausdorff.restype = i32
     lib.wn_chamfer_hausdorff.argtypes = [vp, i64, vp, i64, vp, vp, sz, vp]
+    lib.wn_voxelize_strips_noalloc.restype = i32
+    lib.wn_voxelize_strips_noalloc.argtypes = [vp, i64, vp, i64, vp, i64, gp, vp, i64, vp, i32, f32, f32, vp, vp]
     lib.wn_get_device_error.restype = i32
     lib.wn_get_device_error.argtypes = [vp, vp]
     lib.wn_status_string.restype = ctypes.c_char_p

@@ -114,7 +114,7 @@ size_t wn_workspace_size(int32_t op, int64_t nV, int64_t nF, int64_t nQ) {
 
 }  // extern "C"
 
-namespace {
+namespace wn {
 
 wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *R, int64_t nR,
                         const wn_grid *grid, const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau,
@@ -155,7 +155,9 @@ wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF
     return hip_status(e);
 }
 
-}  // namespace
+size_t voxelize_workspace(int64_t nR, int64_t nQ) { return voxelize_ws(nR, nQ); }
+
+}  // namespace wn
 
 extern "C" {
 
@@ -554,7 +556,11 @@ wn_status wn_chamfer_hausdorff(const float *A, int64_t nA, const float *B, int64
 }
 
 wn_status wn_get_device_error(void *ws, void *stream) {
-    if (ws == nullptr || !aligned256(ws)) return WN_ERR_INVALID_ARG;
+    if (ws == nullptr) {  // the record of wn_voxelize_strips_noalloc on the current device
+        const wn_status st = noalloc_header(&ws);
+        if (st != WN_OK) return st;
+    }
+    if (!aligned256(ws)) return WN_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     WsHeader *hdr = static_cast<WsHeader *>(ws);
     int32_t flag = 0;

@@ -463,6 +463,18 @@ size_t flip_workspace(int64_t nV, int64_t nF);
 wn_status run_flip(const float *V, int64_t nV, const int32_t *F, int64_t nF, float eps, float *V2, int32_t *F2,
                    char *ws, size_t ws_bytes, hipStream_t s);
 
+// The forward entry point's checks and launch sequence (wn_api.hip): R == nullptr for
+// three records per face; `force` overrides the tuned launch configuration.  The
+// workspace of a stream of nR records over nQ points is voxelize_workspace(nR, nQ).
+struct TuneConfig;
+wn_status voxelize_impl(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *R, int64_t nR,
+                        const wn_grid *grid, const float *Q, int64_t nQ, float *W, int32_t occ_mode, float tau,
+                        float k, void *occ, void *ws, size_t ws_bytes, void *stream, const TuneConfig *force);
+size_t voxelize_workspace(int64_t nR, int64_t nQ);
+// Device address of the allocation-free entry point's scratch array on the current
+// device (wn_noalloc.hip); its header carries that entry point's device error record.
+wn_status noalloc_header(void **out);
+
 // Batched pieces (wn_batched.hip).
 size_t batched_workspace(const wn_mesh_desc *d, int32_t n);
 wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws, size_t ws_bytes,
