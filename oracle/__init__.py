@@ -589,12 +589,29 @@ def vertex_neighbours(nV, F):
     return np.cumsum(off), e[:, 1]
 
 
-def laplacian_smooth(V, F, lam: float = 0.15, iters: int = 10):
-    """Umbrella-operator Laplacian smoothing, Jacobi form: every iteration moves each
-    vertex by lam times (mean of its edge neighbours - itself); isolated vertices stay."""
+def enclosed_volume(V, F) -> float:
+    """Signed volume enclosed by a closed, outward-wound surface: the sum over faces of
+    the signed tetrahedra (origin, v0, v1, v2), v0 . (v1 x v2) / 6 (divergence theorem)."""
+    V = np.asarray(V, np.float64)
+    F = np.asarray(F, np.int64).reshape(-1, 3)
+    if len(F) == 0:
+        return 0.0
+    a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    return float(np.sum(np.einsum("ij,ij->i", a, np.cross(b, c)))) / 6.0
+
+
+def laplacian_smooth(V, F, lam: float = 0.15, iters: int = 10, keep_volume: bool = True):
+    """Laplacian filter of Section 3 (the smoothing applied to each cubified occupancy):
+    umbrella operator in Jacobi form, every iteration moving each vertex by lam times
+    (mean of its edge neighbours - itself), isolated vertices staying.  With keep_volume
+    (the filter's default in the tool the paper names) every iteration is followed by a
+    uniform scaling about the origin by (V0 / V)^(1/3), V0 the volume enclosed before the
+    first iteration and V the volume after this one, so the enclosed volume stays V0; the
+    scaling is skipped when V0 / V is not positive and finite (no enclosed volume)."""
     V = np.array(V, dtype=np.float64)
     off, nbr = vertex_neighbours(len(V), F)
     deg = np.diff(off)
+    vol0 = enclosed_volume(V, F) if keep_volume else 0.0
     for _ in range(iters):
         S = np.zeros_like(V)
         for c in range(3):
@@ -603,6 +620,11 @@ def laplacian_smooth(V, F, lam: float = 0.15, iters: int = 10):
         mean = np.zeros_like(V)
         mean[has] = S[has] / deg[has, None]
         V = np.where(has[:, None], V + lam * (mean - V), V)
+        if keep_volume:
+            vol = enclosed_volume(V, F)
+            ratio = vol0 / vol if vol != 0.0 else 0.0
+            if ratio > 0.0 and np.isfinite(ratio):
+                V = V * np.cbrt(ratio)
     return V
 
 

@@ -113,6 +113,20 @@ PY_MUTANTS = [
     ("cubify", "cubify_interior_faces", "bnd = ~pad[", "bnd = pad["),
     ("laplacian_smooth", "smooth_full_step", "V + lam * (mean - V)", "V + lam * mean"),
     ("laplacian_smooth", "smooth_unnormalised", "S[has] / deg[has, None]", "S[has] / 6.0"),
+    ("laplacian_smooth", "smooth_volume_no_cube_root", "V = V * np.cbrt(ratio)", "V = V * ratio"),
+    ("laplacian_smooth", "smooth_volume_about_centroid", "V = V * np.cbrt(ratio)",
+     "V = V.mean(0) + (V - V.mean(0)) * np.cbrt(ratio)"),
+    ("laplacian_smooth", "smooth_volume_never_kept", "if ratio > 0.0 and np.isfinite(ratio):", "if False:"),
+    ("enclosed_volume", "volume_factor", "))) / 6.0", "))) / 3.0"),
+    ("enclosed_volume", "volume_cross_order", "np.cross(b, c)", "np.cross(c, b)"),
+    ("vertex_normals", "normals_uniform_weights", "acc[f[j]] += n", "acc[f[j]] += n / np.linalg.norm(n)"),
+    ("vertex_normals", "normals_reversed", "n = np.cross(V[f[1]] - V[f[0]], V[f[2]] - V[f[0]])",
+     "n = np.cross(V[f[2]] - V[f[0]], V[f[1]] - V[f[0]])"),
+    ("vertex_normals", "normals_first_corner_only", "for j in range(3):\n            acc[f[j]] += n",
+     "for j in range(1):\n            acc[f[j]] += n"),
+    ("flip_duplicate", "flip_copy_not_reversed", "F[:, [0, 2, 1]] + len(V)", "F[:, [0, 1, 2]] + len(V)"),
+    ("flip_duplicate", "flip_moved_outward", "V - eps * N", "V + eps * N"),
+    ("flip_duplicate", "flip_copy_offset", "+ len(V)\n", "+ len(V) - 1\n"),
     ("vertex_neighbours", "smooth_duplicate_edges", "e = np.unique(e, axis=0)", "e = e[np.argsort(e[:, 0], kind='stable')]"),
     ("sample_surface", "sample_cdf_side", 'side="right"', 'side="left"'),
     ("sample_surface", "sample_no_reflection", "r1[flip], r2[flip] = 1.0 - r1[flip], 1.0 - r2[flip]",
@@ -132,7 +146,7 @@ PY_MUTANTS = [
 
 PY_PIN_TESTS = [fn for fn in PIN_TESTS
                 if any(k in fn.__name__ for k in ("adam", "morph", "cubify", "laplacian", "sampling", "nn_dist",
-                                                  "marching"))]
+                                                  "marching", "volume", "normals", "flip"))]
 
 
 @pytest.mark.parametrize("func,name,old,new", PY_MUTANTS, ids=[m[1] for m in PY_MUTANTS])

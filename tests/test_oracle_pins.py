@@ -461,6 +461,25 @@ def test_vertex_normals_closed_forms(orc):
     assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-2
 
 
+def test_vertex_normals_are_area_weighted(orc):
+    """A vertex shared by two faces of unequal area: the right-angled faces
+    (0, e_x, e_y) (normal e_z, |N| = 1) and (0, 3 e_y, e_z) (normal e_x, |N| = 3) give
+    vertex 0 the normal (3, 0, 1) / sqrt(10); uniform or angle weights (both corner
+    angles are right angles) would give (1, 0, 1) / sqrt(2).  Algorithm 2 moves the copy
+    of vertex 0 by -eps times that normal and reverses the copied faces."""
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 3, 0], [0, 0, 1]], float)
+    F = np.array([[0, 1, 2], [0, 3, 4]])
+    N = orc.vertex_normals(V, F)
+    np.testing.assert_allclose(N[0], np.array([3.0, 0.0, 1.0]) / math.sqrt(10), atol=1e-15)
+    np.testing.assert_allclose(N[1], [0, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(N[3], [1, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(N[2], [0, 0, 1], atol=1e-15)
+    V2, F2 = orc.flip_duplicate(V, F, 0.05)
+    np.testing.assert_allclose(V2[5], -0.05 * np.array([3.0, 0.0, 1.0]) / math.sqrt(10), atol=1e-15)
+    np.testing.assert_array_equal(V2[:5], V)
+    np.testing.assert_array_equal(F2, [[0, 1, 2], [0, 3, 4], [5, 7, 6], [5, 9, 8]])
+
+
 def test_flip_duplicate_of_octahedron_is_a_shell(orc):
     """Algorithm 2 on the closed octahedron: V' = (1 - eps) V exactly, so Sigma^-2 is the
     octahedron minus a concentric one: W = 1 in the slab between them, 0 inside the
@@ -835,16 +854,61 @@ def test_marching_cubes_sphere(orc):
 
 
 def test_laplacian_smoothing_closed_forms(orc):
-    """Umbrella smoothing of regular solids shrinks them radially by a known factor per
-    iteration: octahedron 1 - lam (neighbour mean is the centre), icosahedron
-    1 - lam + lam / sqrt(5) (neighbours at cos = 1/sqrt 5).  lam = 0 is the identity."""
+    """Umbrella smoothing of regular solids (without the volume rescale) shrinks them
+    radially by a known factor per iteration: octahedron 1 - lam (neighbour mean is the
+    centre), icosahedron 1 - lam + lam / sqrt(5) (neighbours at cos = 1/sqrt 5).
+    lam = 0 is the identity."""
     V, F = wi.octahedron_mesh(1.0)
-    S = orc.laplacian_smooth(V, F, 0.15, 10)
+    S = orc.laplacian_smooth(V, F, 0.15, 10, keep_volume=False)
     np.testing.assert_allclose(S, V * (1 - 0.15) ** 10, atol=1e-15)
     V, F = wi.icosphere(0)
-    S = orc.laplacian_smooth(V, F, 0.15, 10)
+    S = orc.laplacian_smooth(V, F, 0.15, 10, keep_volume=False)
     np.testing.assert_allclose(S, V * (1 - 0.15 + 0.15 / math.sqrt(5)) ** 10, atol=1e-14)
-    np.testing.assert_array_equal(orc.laplacian_smooth(V, F, 0.0, 10), V)
+    np.testing.assert_array_equal(orc.laplacian_smooth(V, F, 0.0, 10, keep_volume=False), V)
+    np.testing.assert_allclose(orc.laplacian_smooth(V, F, 0.0, 10), V, atol=1e-15)
+
+
+def test_enclosed_volume_closed_forms(orc):
+    """Divergence-theorem volume: unit cube 1, regular octahedron |x|+|y|+|z| <= r
+    (4/3) r^3, independent of a translation of a closed surface, negative when the faces
+    are reversed, and 0 for an open flat patch."""
+    V, F = wi.cube_mesh(0.0, 1.0)
+    assert orc.enclosed_volume(V, F) == pytest.approx(1.0, abs=1e-15)
+    assert orc.enclosed_volume(V + [3.0, -2.0, 5.0], F) == pytest.approx(1.0, abs=1e-13)
+    assert orc.enclosed_volume(V, F[:, ::-1]) == pytest.approx(-1.0, abs=1e-15)
+    V, F = wi.octahedron_mesh(0.7)
+    assert orc.enclosed_volume(V, F) == pytest.approx(4 / 3 * 0.7 ** 3, rel=1e-14)
+    P = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], float)
+    assert orc.enclosed_volume(P, np.array([[0, 1, 2], [1, 3, 2]])) == 0.0
+
+
+def test_laplacian_smoothing_keeps_enclosed_volume(orc):
+    """With the volume rescale (the default), each Jacobi step is followed by a uniform
+    scaling about the origin back to the starting volume:
+      * a regular octahedron or icosahedron centred at the origin only shrinks radially,
+        so the rescale undoes the step exactly: they are fixed points;
+      * an octahedron centred at c shrinks about c by 1 - lam, then is scaled about the
+        origin by 1 / (1 - lam): its shape is kept and its centre moves to c / (1 - lam)
+        each step (scaling about the centroid would leave it in place);
+      * the cube surface of a random voxel set keeps its volume while its vertices move."""
+    lam = 0.15
+    for V, F in (wi.octahedron_mesh(1.0), wi.icosphere(0)):
+        np.testing.assert_allclose(orc.laplacian_smooth(V, F, lam, 10), V, atol=1e-14)
+    V, F = wi.octahedron_mesh(0.2)
+    c = np.array([0.3, -0.1, 0.05])
+    S = orc.laplacian_smooth(V + c, F, lam, 4)
+    np.testing.assert_allclose(S, V + c / (1 - lam) ** 4, atol=1e-14)
+    rng = np.random.default_rng(61)
+    occ = (rng.random((6, 5, 7)) < 0.45).astype(np.uint8)
+    grid = wi.Grid((-0.5, -0.4, -0.6), (0.5, 0.6, 0.4), (6, 5, 7))
+    Vc, Fc = orc.cubify(occ, grid)
+    vol0 = orc.enclosed_volume(Vc, Fc)
+    assert vol0 == pytest.approx(occ.sum() * (1 / 6) * (1 / 5) * (1 / 7), rel=1e-12)
+    S = orc.laplacian_smooth(Vc, Fc, lam, 10)
+    assert orc.enclosed_volume(S, Fc) == pytest.approx(vol0, rel=1e-12)
+    assert np.abs(S - Vc).max() > 1e-3
+    S0 = orc.laplacian_smooth(Vc, Fc, lam, 10, keep_volume=False)
+    assert orc.enclosed_volume(S0, Fc) < 0.9 * vol0
 
 
 def test_laplacian_smoothing_keeps_planar_grid_interior(orc):
@@ -858,13 +922,14 @@ def test_laplacian_smoothing_keeps_planar_grid_interior(orc):
         for j in range(n - 1):
             a, b, c, d = i * n + j, (i + 1) * n + j, (i + 1) * n + j + 1, i * n + j + 1
             F += [[a, b, c], [a, c, d]]
-    S = orc.laplacian_smooth(V, np.array(F), 0.3, 1)
+    S = orc.laplacian_smooth(V, np.array(F), 0.3, 1, keep_volume=False)
+    np.testing.assert_array_equal(orc.laplacian_smooth(V, np.array(F), 0.3, 1), S)  # no volume: no rescale
     inner = (x.ravel() > 0) & (x.ravel() < n - 1) & (y.ravel() > 0) & (y.ravel() < n - 1)
     np.testing.assert_allclose(S[inner], V[inner], atol=1e-15)
     assert np.abs(S[~inner] - V[~inner]).max() > 0.05
     # two triangles sharing edge (1, 2): each neighbour counts once however many faces share it
     K = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [2, 2, 1]], float)
-    S = orc.laplacian_smooth(K, np.array([[0, 1, 2], [1, 3, 2]]), 0.3, 1)
+    S = orc.laplacian_smooth(K, np.array([[0, 1, 2], [1, 3, 2]]), 0.3, 1, keep_volume=False)
     np.testing.assert_allclose(S[1], K[1] + 0.3 * ((K[0] + K[2] + K[3]) / 3 - K[1]), atol=1e-15)
     np.testing.assert_allclose(S[0], K[0] + 0.3 * ((K[1] + K[2]) / 2 - K[0]), atol=1e-15)
 
