@@ -175,38 +175,40 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
 /*
  * The adjoint of wn_backward in pieces, so that a scheduler can interleave a large
  * adjoint with other work (Section 2.4's gradients, served in slices).  The points are
- * cut into splits of `chunk` consecutive points (chunk = 0: the size wn_backward uses,
- * see wn_backward_chunk); each split's per-corner sums are kept apart in the workspace
- * and added in split order at the end.  A sequence of calls on one workspace
- *     flags WN_BWD_BEGIN (pack the faces), then point ranges [p0, p0 + n) that together
- *     cover every split once, in any order and grouping, the last with WN_BWD_END
- *     (add the splits, group corners per vertex, write dLdV and optionally dLdT)
- * gives the same bits as one call (p0 = 0, n = nQ, both flags) with the same chunk, and
- * that call with chunk = 0 is wn_backward.  Flags may be combined with a range in one
- * call (BEGIN runs before the range, END after it).
- *   p0:    a multiple of the chunk;  n: a multiple of the chunk, or p0 + n = nQ;
+ * taken in tiles of WN_BWD_TILE consecutive points, dealt in turn to the S =
+ * wn_backward_splits(nF, nQ) splits of the adjoint (tile t to split t mod S); each split
+ * keeps compensated running sums per face corner in the workspace between calls, and the
+ * splits are added in split order at the end.  A sequence of calls on one workspace
+ *     flags WN_BWD_BEGIN (pack the faces), then consecutive point ranges [p0, p0 + n) in
+ *     increasing order that together cover [0, nQ) exactly once, the last with
+ *     WN_BWD_END (add the splits, group corners per vertex, write dLdV and optionally
+ *     dLdT)
+ * gives the same bits as one call (p0 = 0, n = nQ, both flags), which is wn_backward.
+ * Flags may be combined with a range in one call (BEGIN runs before the range, END
+ * after it).  Ranges out of order or overlapping give wrong sums (a range that reaches a
+ * split's first tile restarts that split); the library does not detect it.
+ *   p0:    a multiple of WN_BWD_TILE;  n: a multiple of WN_BWD_TILE, or p0 + n = nQ;
  *   dLdW:  indexed by the global point number (only [p0, p0 + n) is read);
- *   V, F, grid / Q, nQ, chunk: the same in every call of a sequence;
+ *   V, F, grid / Q, nQ: the same in every call of a sequence;
  *   dLdV:  needed with WN_BWD_END; dLdT optional, as in wn_backward;
- *   ws:    wn_workspace_size_backward(nV, nF, nQ, chunk) bytes, holding the sequence's
- *          state between calls (splits not covered by a range read stale values).
- * At most 65535 splits.  Argument errors return WN_ERR_INVALID_ARG before any launch.
+ *   ws:    wn_workspace_size(WN_OP_BACKWARD, nV, nF, nQ) bytes, holding the running sums.
+ * A range of at least S tiles keeps every split busy (about nF / 256 x S workgroups).
+ * Argument errors return WN_ERR_INVALID_ARG before any launch.
  */
 #define WN_BWD_BEGIN 1
 #define WN_BWD_END 2
+#define WN_BWD_TILE 256
 WN_API wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF,
                                    const wn_grid *grid, const float *Q, int64_t nQ,
-                                   const float *dLdW, int64_t chunk, int64_t p0, int64_t n,
+                                   const float *dLdW, int64_t p0, int64_t n,
                                    int32_t flags, float *dLdV, float *dLdT,
                                    void *ws, size_t ws_bytes, void *stream);
 
-/* The split size in points for (nF, nQ) and a requested chunk (chunk > 0 is returned
- * as is; 0 gives the default); -1 on negative arguments. */
-WN_API int64_t wn_backward_chunk(int64_t nF, int64_t nQ, int64_t chunk);
-
-/* Workspace bytes of wn_backward_range with this chunk (0 on invalid sizes or more than
- * 65535 splits). */
-WN_API size_t wn_workspace_size_backward(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk);
+/* The number of splits S of the adjoint of nF faces over nQ points (a pure function of the
+ * sizes: about 32 768 waves of (face block, split) work, at most one split per tile, at
+ * most 4096, and at most 256 MiB of running sums, 72 bytes per face per split); -1 on
+ * invalid sizes. */
+WN_API int64_t wn_backward_splits(int64_t nF, int64_t nQ);
 
 /*
  * The naive discretisation of the flux integral (Section 2.1, Eq. 4): one sample per
@@ -387,15 +389,21 @@ WN_API wn_status wn_marching_cubes(const float *f, const wn_grid *grid, float is
                                    void *stream);
 
 /*
- * Laplacian smoothing with the umbrella operator, `iters` Jacobi steps
- *   v <- v + lam (mean of the vertices joined to v by a face edge - v);
- * vertices without neighbours stay.  Each vertex adds its neighbours in increasing id
- * order, so the result is deterministic.  V (float [nV][3]) is read, Vout (float
- * [nV][3], not aliasing V) written.  Out-of-range face indices are replaced by 0 and
- * recorded.  Workspace: wn_workspace_size(WN_OP_SMOOTH, nV, nF, 0).
+ * The Laplacian filter of the evaluation (Section 3): `iters` Jacobi steps of the
+ * umbrella operator
+ *   v <- v + lam (mean of the vertices joined to v by a face edge - v),
+ * vertices without neighbours staying; with keep_volume = 1 (the filter's default in the
+ * tool the paper names) each step is followed by a uniform scaling about the origin by
+ * (V0 / V)^(1/3), V0 the volume the surface enclosed before the first step and V the one
+ * after this step (sum over faces of v0 . (v1 x v2) / 6, FP64, fixed order), skipped when
+ * V0 / V is not positive; keep_volume = 0 leaves the steps alone.  Each vertex adds its
+ * neighbours in increasing id order, so the result is deterministic.  V (float [nV][3])
+ * is read, Vout (float [nV][3], not aliasing V) written.  Out-of-range face indices are
+ * replaced by 0 and recorded.  Workspace: wn_workspace_size(WN_OP_SMOOTH, nV, nF, 0).
  */
 WN_API wn_status wn_laplacian_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam,
-                                     int32_t iters, float *Vout, void *ws, size_t ws_bytes, void *stream);
+                                     int32_t iters, int32_t keep_volume, float *Vout, void *ws, size_t ws_bytes,
+                                     void *stream);
 
 /*
  * Area-uniform surface samples from caller-supplied uniform numbers u (device double

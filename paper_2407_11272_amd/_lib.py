@@ -43,6 +43,7 @@ WN_NOALLOC_SCRATCH_BYTES = 96 << 20
 
 WN_BWD_BEGIN = 1
 WN_BWD_END = 2
+WN_BWD_TILE = 256
 
 #: every symbol include/wn.h declares
 EXPORTED = (
@@ -54,8 +55,7 @@ EXPORTED = (
     "wn_sigmoid_mse",
     "wn_backward",
     "wn_backward_range",
-    "wn_backward_chunk",
-    "wn_workspace_size_backward",
+    "wn_backward_splits",
     "wn_voxelize_naive",
     "wn_backward_naive",
     "wn_voxelize_batched",
@@ -137,11 +137,9 @@ def load():
     lib.wn_backward.restype = i32
     lib.wn_backward.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, vp, vp, vp, sz, vp]
     lib.wn_backward_range.restype = i32
-    lib.wn_backward_range.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i64, i64, i64, i32, vp, vp, vp, sz, vp]
-    lib.wn_backward_chunk.restype = i64
-    lib.wn_backward_chunk.argtypes = [i64, i64, i64]
-    lib.wn_workspace_size_backward.restype = sz
-    lib.wn_workspace_size_backward.argtypes = [i64, i64, i64, i64]
+    lib.wn_backward_range.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i64, i64, i32, vp, vp, vp, sz, vp]
+    lib.wn_backward_splits.restype = i64
+    lib.wn_backward_splits.argtypes = [i64, i64]
     lib.wn_voxelize_naive.restype = i32
     lib.wn_voxelize_naive.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i32, f32, f32, vp, vp, sz, vp]
     lib.wn_backward_naive.restype = i32
@@ -168,7 +166,7 @@ def load():
     lib.wn_marching_cubes.restype = i32
     lib.wn_marching_cubes.argtypes = [vp, gp, f32, vp, i64, vp, i64, vp, vp, sz, vp]
     lib.wn_laplacian_smooth.restype = i32
-    lib.wn_laplacian_smooth.argtypes = [vp, i64, vp, i64, f32, i32, vp, vp, sz, vp]
+    lib.wn_laplacian_smooth.argtypes = [vp, i64, vp, i64, f32, i32, i32, vp, vp, sz, vp]
     lib.wn_sample_surface.restype = i32
     lib.wn_sample_surface.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, vp, sz, vp]
     lib.wn_nn_distance.restype = i32

@@ -191,14 +191,14 @@ def wn_voxelize_naive(V, F, grid: Grid | None = None, Q: torch.Tensor | None = N
 
 
 class SlicedBackward:
-    """The adjoint of one (mesh, grid or point list) computed over point ranges in
-    separate calls (``wn_backward_range``): :meth:`begin`, then :meth:`points` for ranges
-    that together cover every split of ``chunk`` points once, then :meth:`end`.  The
-    result has the same bits as one call over all points with the same chunk; with
-    chunk 0 that is :func:`wn_backward`.  The object owns its workspace, which holds the
-    per-split sums between calls; all calls go to the current stream of V's device."""
+    """The adjoint of one (mesh, grid or point list) computed over consecutive point
+    ranges in separate calls (``wn_backward_range``): :meth:`begin`, then :meth:`points`
+    for ranges of whole 256-point tiles in increasing order that together cover every
+    point once, then :meth:`end`.  The result has the same bits as :func:`wn_backward`.
+    The object owns its workspace, which holds the splits' running sums between calls;
+    all calls go to the current stream of V's device."""
 
-    def __init__(self, V, F, grid: Grid | None = None, Q: torch.Tensor | None = None, chunk: int = 0):
+    def __init__(self, V, F, grid: Grid | None = None, Q: torch.Tensor | None = None):
         _check_mesh(V, F)
         if (grid is None) == (Q is None):
             raise ValueError("pass exactly one of grid or Q")
@@ -213,17 +213,17 @@ class SlicedBackward:
             self.P = self._nQ = Q.shape[0]
             self._Q = Q
             self._qptr = _ptr(Q)
-        self.chunk = int(self.lib.wn_backward_chunk(F.shape[0], self.P, int(chunk)))
-        if self.chunk < 1:
-            raise ValueError("invalid chunk")
-        self.splits = -(-self.P // self.chunk) if self.P else 0
-        need = self.lib.wn_workspace_size_backward(V.shape[0], F.shape[0], self.P, int(chunk))
+        self.tile = L.WN_BWD_TILE
+        self.splits = int(self.lib.wn_backward_splits(F.shape[0], self.P))
+        if self.splits < 1:
+            raise ValueError("sizes out of range for the adjoint")
+        need = wn_workspace_size(L.WN_OP_BACKWARD, V.shape[0], F.shape[0], self.P)
         if need == 0:
-            raise ValueError("sizes out of range for the adjoint (at most 65535 splits)")
+            raise ValueError("sizes out of range for the adjoint")
         self._buf = torch.empty(need + 256, dtype=torch.uint8, device=self.dev)
         base = self._buf.data_ptr()
         self._ws, self._wsb = ctypes.c_void_p(base + (-base) % 256), need
-        self._req_chunk = int(chunk)
+        self._next = 0
 
     @property
     def workspace_bytes(self) -> int:
@@ -232,20 +232,28 @@ class SlicedBackward:
     def _call(self, dLdW, p0, n, flags, dLdV=None, dLdT=None):
         g = ctypes.byref(self._gc) if self._gc is not None else None
         st = self.lib.wn_backward_range(_ptr(self.V), self.V.shape[0], _ptr(self.F), self.F.shape[0], g, self._qptr,
-                                        self._nQ, _ptr(dLdW), self._req_chunk, int(p0), int(n), flags, _ptr(dLdV),
-                                        _ptr(dLdT), self._ws, self._wsb, _stream_handle(self.dev))
+                                        self._nQ, _ptr(dLdW), int(p0), int(n), flags, _ptr(dLdV), _ptr(dLdT),
+                                        self._ws, self._wsb, _stream_handle(self.dev))
         L.check("wn_backward_range", st)
 
     def begin(self):
+        self._next = 0
         self._call(None, 0, 0, L.WN_BWD_BEGIN)
 
     def points(self, p0: int, n: int, dLdW: torch.Tensor):
-        """Add points [p0, p0 + n); dLdW is indexed by the global point number."""
+        """Add points [p0, p0 + n): the next range after the previous one (p0 and n whole
+        tiles, or the range reaching the last point); dLdW is indexed by the global point
+        number."""
         if dLdW.dtype != torch.float32 or not dLdW.is_contiguous() or dLdW.numel() != self.P or not dLdW.is_cuda:
             raise ValueError("dLdW must be a contiguous float32 device tensor with one entry per point")
+        if int(p0) != self._next:
+            raise ValueError(f"ranges must be consecutive: expected p0 = {self._next}, got {p0}")
         self._call(dLdW, p0, n, 0)
+        self._next = int(p0) + int(n)
 
     def end(self, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None) -> torch.Tensor:
+        if self._next != self.P:
+            raise ValueError(f"the ranges covered {self._next} of {self.P} points")
         if dLdV is None:
             dLdV = torch.empty_like(self.V)
         self._call(None, 0, 0, L.WN_BWD_END, dLdV, dLdT)
@@ -475,13 +483,16 @@ def wn_marching_cubes(f: torch.Tensor, grid: Grid, iso: float = 0.5):
     return V, F
 
 
-def wn_laplacian_smooth(V: torch.Tensor, F: torch.Tensor, lam: float = 0.15, iters: int = 10) -> torch.Tensor:
-    """Umbrella-operator Laplacian smoothing (Jacobi steps); returns new vertices."""
+def wn_laplacian_smooth(V: torch.Tensor, F: torch.Tensor, lam: float = 0.15, iters: int = 10,
+                        keep_volume: bool = True) -> torch.Tensor:
+    """Umbrella-operator Laplacian smoothing (Jacobi steps), each step followed by a
+    scaling about the origin back to the starting enclosed volume unless ``keep_volume``
+    is False; returns new vertices."""
     _check_mesh(V, F)
     out = torch.empty_like(V)
     ws, wsb = Workspace.get(wn_workspace_size(L.WN_OP_SMOOTH, V.shape[0], F.shape[0], 0), V.device)
-    st = L.load().wn_laplacian_smooth(_ptr(V), V.shape[0], _ptr(F), F.shape[0], lam, int(iters), _ptr(out), ws, wsb,
-                                      _stream_handle(V.device))
+    st = L.load().wn_laplacian_smooth(_ptr(V), V.shape[0], _ptr(F), F.shape[0], lam, int(iters),
+                                      1 if keep_volume else 0, _ptr(out), ws, wsb, _stream_handle(V.device))
     L.check("wn_laplacian_smooth", st)
     return out
 

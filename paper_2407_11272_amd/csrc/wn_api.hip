@@ -16,7 +16,6 @@ using namespace wn;
 namespace {
 
 constexpr int64_t kMaxCount = 2147483647LL;  // 2^31 - 1
-constexpr int64_t kMaxBwdSplits = 65535;     // point splits of one adjoint (grid y)
 
 bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
@@ -213,24 +212,22 @@ wn_status wn_sigmoid_mse(const float *W, const float *target, int64_t n, float t
 }
 
 wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
-                            const float *Q, int64_t nQ, const float *dLdW, int64_t chunk, int64_t p0, int64_t n,
-                            int32_t flags, float *dLdV, float *dLdT, void *ws, size_t ws_bytes, void *stream) {
+                            const float *Q, int64_t nQ, const float *dLdW, int64_t p0, int64_t n, int32_t flags,
+                            float *dLdV, float *dLdT, void *ws, size_t ws_bytes, void *stream) {
     if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
     const int64_t P = query_count(grid, Q, nQ);
     if (P < 0) return WN_ERR_INVALID_ARG;
     if (flags & ~(WN_BWD_BEGIN | WN_BWD_END)) return WN_ERR_INVALID_ARG;
-    if (chunk < 0 || p0 < 0 || n < 0 || p0 > P || n > P - p0) return WN_ERR_INVALID_ARG;
-    const int64_t c = bwd_chunk(nF, P, chunk);
-    if (P > 0 && (P + c - 1) / c > kMaxBwdSplits) return WN_ERR_INVALID_ARG;
-    if (n > 0 && (p0 % c != 0 || (p0 + n != P && n % c != 0))) return WN_ERR_INVALID_ARG;
+    if (p0 < 0 || n < 0 || p0 > P || n > P - p0) return WN_ERR_INVALID_ARG;
+    if (n > 0 && (p0 % WN_BWD_TILE != 0 || (p0 + n != P && n % WN_BWD_TILE != 0))) return WN_ERR_INVALID_ARG;
     if ((flags & WN_BWD_END) && nV > 0 && dLdV == nullptr) return WN_ERR_INVALID_ARG;
     if (n > 0 && nF > 0 && dLdW == nullptr) return WN_ERR_INVALID_ARG;
     if (grid)
         for (int d = 0; d < 3; ++d)
             if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
-    const size_t need = bwd_workspace(nV, nF, P, chunk);
+    const size_t need = bwd_workspace(nV, nF, P);
     if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
-    return run_backward(V, nV, F, nF, make_point_src(grid, Q), P, dLdW, chunk, p0, n, flags, dLdV, dLdT,
+    return run_backward(V, nV, F, nF, make_point_src(grid, Q), P, dLdW, p0, n, flags, dLdV, dLdT,
                         static_cast<char *>(ws), ws_bytes, static_cast<hipStream_t>(stream));
 }
 
@@ -238,20 +235,13 @@ wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, 
                       const float *Q, int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, void *ws,
                       size_t ws_bytes, void *stream) {
     const int64_t P = query_count(grid, Q, nQ);
-    return wn_backward_range(V, nV, F, nF, grid, Q, nQ, dLdW, 0, 0, P < 0 ? 0 : P, WN_BWD_BEGIN | WN_BWD_END, dLdV,
+    return wn_backward_range(V, nV, F, nF, grid, Q, nQ, dLdW, 0, P < 0 ? 0 : P, WN_BWD_BEGIN | WN_BWD_END, dLdV,
                              dLdT, ws, ws_bytes, stream);
 }
 
-int64_t wn_backward_chunk(int64_t nF, int64_t nQ, int64_t chunk) {
-    if (nF < 0 || nQ < 0 || chunk < 0) return -1;
-    return bwd_chunk(nF, nQ, chunk);
-}
-
-size_t wn_workspace_size_backward(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk) {
-    if (nV < 0 || nF < 0 || nQ < 0 || chunk < 0 || nV > kMaxCount || nF > kMaxCount || nQ > kMaxCount) return 0;
-    const int64_t c = bwd_chunk(nF, nQ, chunk);
-    if (nQ > 0 && (nQ + c - 1) / c > kMaxBwdSplits) return 0;
-    return bwd_workspace(nV, nF, nQ, chunk);
+int64_t wn_backward_splits(int64_t nF, int64_t nQ) {
+    if (nF < 0 || nQ < 0 || nF > kMaxCount || nQ > kMaxCount) return -1;
+    return bwd_splits(nF, nQ);
 }
 
 }  // extern "C"
@@ -524,11 +514,13 @@ wn_status wn_cubify(const uint8_t *occ, const wn_grid *grid, float *V, int64_t c
 }
 
 wn_status wn_laplacian_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam, int32_t iters,
-                              float *Vout, void *ws, size_t ws_bytes, void *stream) {
+                              int32_t keep_volume, float *Vout, void *ws, size_t ws_bytes, void *stream) {
     if (!mesh_ok(V, nV, F, nF) || nF > kMaxCount / 6 || iters < 0 || !std::isfinite(lam)) return WN_ERR_INVALID_ARG;
+    if (keep_volume != 0 && keep_volume != 1) return WN_ERR_INVALID_ARG;
     if (nV > 0 && (Vout == nullptr || Vout == V)) return WN_ERR_INVALID_ARG;
     if (ws == nullptr || !aligned256(ws) || ws_bytes < smooth_workspace(nV, nF)) return WN_ERR_WORKSPACE;
-    return run_smooth(V, nV, F, nF, lam, iters, Vout, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
+    return run_smooth(V, nV, F, nF, lam, iters, keep_volume, Vout, static_cast<char *>(ws),
+                      static_cast<hipStream_t>(stream));
 }
 
 wn_status wn_sample_surface(const float *V, int64_t nV, const int32_t *F, int64_t nF, const double *u, int64_t n,

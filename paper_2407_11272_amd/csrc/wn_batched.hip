@@ -114,6 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_pack(char *ws) {
         if (mh.R) {
             vid = mh.R[2 * r];
             fid = mh.R[2 * r + 1];
+            check_strip_record(mh.R, r, mh.F, mh.nF, fid, hdr);
         } else {
             const int64_t f = r / 3;
             const int j = (int)(r - 3 * f);

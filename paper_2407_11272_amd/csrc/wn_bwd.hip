@@ -15,9 +15,13 @@
 //   * query points (with their dL/dW) stream through LDS and are read by every
 //     lane (broadcast), solid angles are recomputed per pair, nothing of size
 //     points x faces is stored;
-//   * the points are split over workgroups; the per-split partial sums are added
-//     in a fixed order, then corners are grouped per vertex by a stable radix sort
-//     of their vertex ids and summed in face order -- deterministic throughout.
+//   * the points are split over workgroups: the 256-point tiles are dealt to S
+//     splits in turn (tile t to split t mod S), each split keeping its own
+//     compensated sums per corner; the splits are added in a fixed order at the end,
+//     then corners are grouped per vertex by a stable radix sort of their vertex ids
+//     and summed in face order -- deterministic throughout.  A split's running sums
+//     live in the workspace between calls, so the adjoint can also be computed over
+//     consecutive point ranges (the served loop's units) with the same bits.
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -26,10 +30,13 @@
 
 namespace wn {
 
-constexpr int kPointTile = kBlock;  // points staged per tile (one per thread)
+constexpr int kPointTile = kBwdTile;  // points staged per tile (one per thread)
+static_assert(kBwdTile == kBlock && kBwdTile == WN_BWD_TILE, "one point per thread per tile");
 
-// dL/dv partial sums of one face over a range of points.  Grid: x = face blocks,
-// y = point splits.  partials layout: [split][9][nF].
+// dL/dv running sums of one face over the tiles [t0, t1) of its split.  Grid: x = face
+// blocks, y = the splits that own a tile of the range (split (t0 + y) mod S).  state
+// layout: float2 (sum, compensation) [S][9][nF]; a split whose first tile (tile s) is
+// in the range starts from zero, any other resumes its stored sums.
 //
 // Per pair the corner vector is gk r_j^-1 (beta u_j - alpha E - alpha (e_k . e_l) e_j)
 // with E = e_0 + e_1 + e_2 and gk = dL/dW / (alpha^2 + beta^2) (the projection folded
@@ -39,11 +46,12 @@ constexpr int kPointTile = kBlock;  // points staged per tile (one per thread)
 // and C_1 = C_2 = 0, so over a tile of points it is C_j sum(w) + D_j x sum(w R_0): four
 // sums per pair instead of nine products.  alpha = (R_0 . N) / (r_0 r_1 r_2) (Eq. 7).
 __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ soup, int32_t nF, PointSrc ps,
-                                                   int64_t nQ, int64_t chunkP, int32_t split0,
-                                                   const float *__restrict__ dLdW, float *__restrict__ partials) {
+                                                   int64_t nQ, int32_t S, int64_t t0, int64_t t1,
+                                                   const float *__restrict__ dLdW, float2 *__restrict__ state) {
     __shared__ float4 pts[kPointTile];
     const int tid = threadIdx.x;
-    const int64_t sy = (int64_t)split0 + blockIdx.y;  // this block's point split
+    const int64_t tfirst = t0 + blockIdx.y;       // this block's first tile
+    const int64_t sy = tfirst % S;                // its split
     int32_t f = (int32_t)blockIdx.x * kBlock + tid;
     const bool live = f < nF;
     f = live ? f : nF - 1;
@@ -52,18 +60,16 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
     const float N[3] = {r.c.y, r.c.z, r.c.w};
 
     float s[9], c[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] = c[i] = 0.0f;
+    load_state(state, sy, nF, f, tfirst < S, s, c);
 
-    const int64_t p0 = sy * chunkP;
-    const int64_t p1 = min(nQ, p0 + chunkP);
-    for (int64_t t0 = p0; t0 < p1; t0 += kPointTile) {
-        const int nt = (int)min((int64_t)kPointTile, p1 - t0);
+    for (int64_t t = tfirst; t < t1; t += S) {
+        const int64_t q0 = t * kPointTile;
+        const int nt = (int)min((int64_t)kPointTile, nQ - q0);
         __syncthreads();
         if (tid < nt) {
             float x, y, z;
-            ps.get(t0 + tid, x, y, z);
-            pts[tid] = make_float4(x, y, z, dLdW[t0 + tid]);
+            ps.get(q0 + tid, x, y, z);
+            pts[tid] = make_float4(x, y, z, dLdW[q0 + tid]);
         }
         __syncthreads();
         float ts[9], sw = 0.0f, sq[3] = {0.0f, 0.0f, 0.0f};
@@ -124,32 +130,33 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd(const FaceRec *__restrict__ s
 #pragma unroll
         for (int i = 0; i < 9; ++i) neumaier_add(s[i], c[i], ts[i]);
     }
-    if (live) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) partials[(sy * 9 + i) * nF + f] = s[i] + c[i];
-    }
+    if (live) store_state(state, sy, nF, f, s, c);
 }
 
-// T[f][i] = sum over splits (fixed order) * scale (1/(2 pi) for the exact field).
-__global__ __launch_bounds__(kBlock) void k_bwd_reduce(const float *__restrict__ partials, int32_t split, int32_t nF,
+// T[f][i] = sum over splits (fixed order) of each split's total, * scale (1/(2 pi) for
+// the exact field, 1/(8 pi) for Eq. 4).
+__global__ __launch_bounds__(kBlock) void k_bwd_reduce(const float2 *__restrict__ state, int32_t split, int32_t nF,
                                                        float scale, float *__restrict__ T) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)nF * 9) return;
     const int32_t i = (int32_t)(t / nF);
     const int32_t f = (int32_t)(t - (int64_t)i * nF);
-    const float *p = partials + (int64_t)i * nF + f;
+    const float2 *p = state + (int64_t)i * nF + f;
     const int64_t stride = (int64_t)9 * nF;  // from one split to the next
     float s = 0.0f, c = 0.0f;
     int32_t k = 0;
     // eight loads in flight, then added in split order (the same order as one at a time)
     for (; k + 8 <= split; k += 8) {
-        float x[8];
+        float2 x[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) x[u] = p[(int64_t)(k + u) * stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) neumaier_add(s, c, x[u]);
+        for (int u = 0; u < 8; ++u) neumaier_add(s, c, x[u].x + x[u].y);
     }
-    for (; k < split; ++k) neumaier_add(s, c, p[(int64_t)k * stride]);
+    for (; k < split; ++k) {
+        const float2 x = p[(int64_t)k * stride];
+        neumaier_add(s, c, x.x + x.y);
+    }
     T[(int64_t)f * 9 + i] = (s + c) * scale;
 }
 
@@ -271,8 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_flip_faces(const int32_t *__restrict
 namespace {
 
 struct BwdPlan {
-    int split;
-    int64_t chunkP;
+    int split;      // S: tile t of the points belongs to split t mod S
+    int64_t tiles;  // 256-point tiles of the points
     unsigned bits;
     size_t sort_tmp;
     size_t off_soup, off_part, off_T, off_keys, off_vals, off_keys2, off_vals2, off_tmp, off_vs, off_ve, total;
@@ -280,31 +287,30 @@ struct BwdPlan {
 
 }  // namespace
 
-// Points per split: the caller's chunk, or by default about 32768 waves over the face
-// waves and splits (at most 4096 splits), rounded up to whole point tiles.  Several
-// rounds of resident workgroups keep the last, partly filled round short; more splits
-// than that cost more in the per-split sums than they save.
-int64_t bwd_chunk(int64_t nF, int64_t nQ, int64_t chunk) {
-    if (chunk > 0) return chunk;
+// Splits of the points: about 32768 waves of (face block, split) work, so that several
+// rounds of resident workgroups keep the last, partly filled round short (more splits
+// cost more in the per-split sums than they save); at most one split per tile, at most
+// 4096, and the running sums (8 B per corner per split) within kBwdStateBytes.  A pure
+// function of (nF, nQ), so results never depend on how the points are cut into ranges.
+constexpr int64_t kBwdStateBytes = int64_t(256) << 20;
+
+int bwd_splits(int64_t nF, int64_t nQ) {
     const int64_t face_waves = (nF + 63) / 64;
     int64_t sp = (32768 + face_waves - 1) / (face_waves > 0 ? face_waves : 1);
     if (sp > 4096) sp = 4096;
-    const int64_t max_by_points = (nQ + kPointTile - 1) / kPointTile;
-    if (sp > max_by_points) sp = max_by_points;
-    if (sp < 1) sp = 1;
-    int64_t c = (nQ + sp - 1) / sp;
-    c = (c + kPointTile - 1) / kPointTile * kPointTile;
-    return c < kPointTile ? kPointTile : c;
+    const int64_t tiles = (nQ + kPointTile - 1) / kPointTile;
+    if (sp > tiles) sp = tiles;
+    const int64_t by_mem = kBwdStateBytes / (72 * (nF > 0 ? nF : 1));
+    if (sp > by_mem) sp = by_mem;
+    return (int)(sp < 1 ? 1 : sp);
 }
 
 namespace {
 
-BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk_arg = 0) {
+BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ) {
     BwdPlan p{};
-    const int64_t chunk = bwd_chunk(nF, nQ, chunk_arg);
-    p.chunkP = chunk;
-    p.split = (int)((nQ + chunk - 1) / chunk);
-    if (p.split < 1) p.split = 1;
+    p.split = bwd_splits(nF, nQ);
+    p.tiles = (nQ + kPointTile - 1) / kPointTile;
     unsigned bits = 1;
     while (bits < 31 && ((int64_t)1 << bits) < nV) ++bits;
     p.bits = bits;
@@ -318,7 +324,7 @@ BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk_arg = 0)
     p.off_soup = o;
     o += align_up((size_t)nF * sizeof(FaceRec));
     p.off_part = o;
-    o += align_up((size_t)p.split * 9 * (size_t)nF * sizeof(float));
+    o += align_up((size_t)p.split * 9 * (size_t)nF * sizeof(float2));
     p.off_T = o;
     o += align_up((size_t)nF * 9 * sizeof(float));
     p.off_keys = o;
@@ -343,9 +349,7 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk) {
-    return plan_backward(nV, nF, nQ, chunk).total;
-}
+size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ) { return plan_backward(nV, nF, nQ).total; }
 
 // The flip reuses the adjoint's layout with no points: the corner sort buffers, vertex
 // bounds, and the face-normal table in place of the per-split partials.
@@ -388,13 +392,13 @@ wn_status run_flip(const float *V, int64_t nV, const int32_t *F, int64_t nF, flo
 }
 
 wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps, int64_t nQ,
-                       const float *dLdW, int64_t chunk, int64_t p0, int64_t n, int flags, float *dLdV, float *dLdT,
-                       char *ws, size_t ws_bytes, hipStream_t s, bool naive) {
-    const BwdPlan p = plan_backward(nV, nF, nQ, chunk);
+                       const float *dLdW, int64_t p0, int64_t n, int flags, float *dLdV, float *dLdT, char *ws,
+                       size_t ws_bytes, hipStream_t s, bool naive) {
+    const BwdPlan p = plan_backward(nV, nF, nQ);
     if (ws_bytes < p.total) return WN_ERR_WORKSPACE;
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
     FaceRec *soup = reinterpret_cast<FaceRec *>(ws + p.off_soup);
-    float *partials = reinterpret_cast<float *>(ws + p.off_part);
+    float2 *state = reinterpret_cast<float2 *>(ws + p.off_part);
     hipError_t e = hipSuccess;
 
     // begin: face records (and the index check) for the whole call sequence
@@ -402,15 +406,15 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
         if ((e = launch_ws_reset(hdr, s)) != hipSuccess) return WN_ERR_HIP;
         if (nV > 0 && nF > 0 && (e = launch_pack(V, nV, F, nF, soup, hdr, s)) != hipSuccess) return WN_ERR_HIP;
     }
-    // points [p0, p0 + n): the splits they cover (whole splits, or the ragged last one)
+    // points [p0, p0 + n): its tiles [t0, t1), one workgroup row per split that owns one
     if (n > 0 && nV > 0 && nF > 0) {
-        const int64_t s0 = p0 / p.chunkP, s1 = (p0 + n + p.chunkP - 1) / p.chunkP;
+        const int64_t t0 = p0 / kPointTile, t1 = (p0 + n + kPointTile - 1) / kPointTile;
+        const int64_t rows = min((int64_t)p.split, t1 - t0);
         if (naive) {
-            e = launch_naive_bwd(soup, (int32_t)nF, ps, nQ, p.chunkP, (int32_t)s0, (int32_t)(s1 - s0), dLdW, partials,
-                                 s);
+            e = launch_naive_bwd(soup, (int32_t)nF, ps, nQ, p.split, t0, t1, (int32_t)rows, dLdW, state, s);
         } else {
-            k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)(s1 - s0)), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.chunkP,
-                                                                                  (int32_t)s0, dLdW, partials);
+            k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)rows), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.split, t0,
+                                                                              t1, dLdW, state);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return WN_ERR_HIP;
@@ -430,8 +434,7 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
     int32_t *vs = reinterpret_cast<int32_t *>(ws + p.off_vs);
     int32_t *ve = reinterpret_cast<int32_t *>(ws + p.off_ve);
     if (nQ > 0) {
-        k_bwd_reduce<<<blocks_for(9 * nF), kBlock, 0, s>>>(partials, p.split, (int32_t)nF, naive ? kInv8Pi : kInv2Pi,
-                                                            T);
+        k_bwd_reduce<<<blocks_for(9 * nF), kBlock, 0, s>>>(state, p.split, (int32_t)nF, naive ? kInv8Pi : kInv2Pi, T);
     } else {
         k_fill_i32<<<blocks_for(9 * nF), kBlock, 0, s>>>(reinterpret_cast<int32_t *>(T), 9 * nF, 0);
     }

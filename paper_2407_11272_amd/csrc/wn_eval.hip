@@ -9,7 +9,9 @@
 //   * cube surface: counts per voxel and used lattice corners, two exclusive scans,
 //     then each voxel writes its own faces at its scanned offset;
 //   * smoothing: neighbour lists from a radix sort of the directed edges, then Jacobi
-//     steps that add each vertex's neighbours in increasing id order;
+//     steps that add each vertex's neighbours in increasing id order, each optionally
+//     followed by a scaling about the origin back to the starting enclosed volume (FP64
+//     volume summed in a fixed order);
 //   * sampling: integer area weights and an integer prefix sum, so the face choice is
 //     exact; the areas are formed in FP64 without contraction;
 //   * nearest neighbours: squared distances are non-negative floats, whose bit patterns
@@ -254,10 +256,67 @@ __global__ __launch_bounds__(kBlock) void k_smooth_step(const float *__restrict_
     Y[3 * v + 2] = z + lam * (sz * inv - z);
 }
 
+// Enclosed volume of the surface (v0 . (v1 x v2) / 6 summed over faces, the divergence
+// theorem), in FP64 and in a fixed order: kVolBlocks workgroups each sum a fixed strided
+// set of faces per thread, then a fixed-shape tree; one workgroup adds the partials.
+constexpr int kVolBlocks = 256;
+
+__device__ __forceinline__ double block_sum_f64(double x) {
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_volume_partial(const float *__restrict__ X, int64_t nV,
+                                                           const int32_t *__restrict__ F, int64_t nF,
+                                                           double *__restrict__ part) {
+    double acc = 0.0;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nF; f += (int64_t)gridDim.x * blockDim.x) {
+        double v[3][3];
+        for (int j = 0; j < 3; ++j) {
+            int64_t id = F[3 * f + j];
+            id = (id < 0 || id >= nV) ? 0 : id;  // recorded by the edge pass
+            for (int c = 0; c < 3; ++c) v[j][c] = X[3 * id + c];
+        }
+        const double cx = v[1][1] * v[2][2] - v[1][2] * v[2][1];
+        const double cy = v[1][2] * v[2][0] - v[1][0] * v[2][2];
+        const double cz = v[1][0] * v[2][1] - v[1][1] * v[2][0];
+        acc += v[0][0] * cx + v[0][1] * cy + v[0][2] * cz;
+    }
+    const double t = block_sum_f64(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// vol[0] = the volume (first call), or scale[0] = cbrt(vol0 / vol) when that ratio is
+// positive and finite, else 1 (a surface that encloses no volume is not rescaled).
+__global__ __launch_bounds__(kBlock) void k_volume_final(const double *__restrict__ part, double *__restrict__ vol0,
+                                                         double *__restrict__ scale, int first) {
+    const double t = block_sum_f64(threadIdx.x < kVolBlocks ? part[threadIdx.x] : 0.0) / 6.0;
+    if (threadIdx.x != 0) return;
+    if (first) {
+        vol0[0] = t;
+    } else {
+        const double r = t != 0.0 ? vol0[0] / t : 0.0;
+        scale[0] = (r > 0.0 && r <= 1.79e308) ? cbrt(r) : 1.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_f32(float *__restrict__ X, int64_t n,
+                                                      const double *__restrict__ scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) X[i] = (float)((double)X[i] * scale[0]);
+}
+static_assert(kVolBlocks <= kBlock, "one thread per volume partial in the final sum");
+
 struct SmoothPlan {
     unsigned bits;
     size_t sort_tmp, scan_tmp, scan2_tmp;
-    size_t off_keys, off_keys2, off_flag, off_pos, off_nbr, off_deg, off_off, off_tmp, off_T, total;
+    size_t off_keys, off_keys2, off_flag, off_pos, off_nbr, off_deg, off_off, off_tmp, off_T, off_vol, total;
 };
 
 SmoothPlan plan_smooth(int64_t nV, int64_t nF) {
@@ -296,6 +355,8 @@ SmoothPlan plan_smooth(int64_t nV, int64_t nF) {
     o += align_up(tmp > 0 ? tmp : 1);
     p.off_T = o;
     o += align_up((size_t)nV * 12);
+    p.off_vol = o;  // kVolBlocks partials, then vol0 and the scale
+    o += align_up((size_t)(kVolBlocks + 2) * 8);
     p.total = o;
     return p;
 }
@@ -574,8 +635,8 @@ wn_status run_cubify(const uint8_t *occ, const int32_t n[3], const float lo[3], 
     return hipGetLastError() == hipSuccess ? WN_OK : WN_ERR_HIP;
 }
 
-wn_status run_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam, int32_t iters, float *Vout,
-                     char *ws, hipStream_t s) {
+wn_status run_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam, int32_t iters,
+                     int32_t keep_volume, float *Vout, char *ws, hipStream_t s) {
     const SmoothPlan p = plan_smooth(nV, nF);
     const int64_t nE = 6 * nF;
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
@@ -587,9 +648,16 @@ wn_status run_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, f
     int32_t *deg = reinterpret_cast<int32_t *>(ws + p.off_deg);
     int64_t *off = reinterpret_cast<int64_t *>(ws + p.off_off);
     float *T = reinterpret_cast<float *>(ws + p.off_T);
+    double *vpart = reinterpret_cast<double *>(ws + p.off_vol);
+    double *vol0 = vpart + kVolBlocks, *vscale = vol0 + 1;
     hipError_t e = launch_ws_reset(hdr, s);
     if (e != hipSuccess) return WN_ERR_HIP;
     if (nV == 0) return WN_OK;
+    const bool rescale = keep_volume && nF > 0 && iters > 0;
+    if (rescale) {
+        k_volume_partial<<<kVolBlocks, kBlock, 0, s>>>(V, nV, F, nF, vpart);
+        k_volume_final<<<1, kBlock, 0, s>>>(vpart, vol0, vscale, 1);
+    }
     k_fill_u32<<<nblocks(nV + 1), kBlock, 0, s>>>(reinterpret_cast<uint32_t *>(deg), nV + 1, 0u);
     if (nE > 0) {
         k_edge_keys<<<nblocks(nF), kBlock, 0, s>>>(F, nF, nV, keys, hdr);
@@ -616,6 +684,11 @@ wn_status run_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, f
         for (int32_t it = 0; it < iters; ++it) {
             float *dst = ((iters - 1 - it) % 2 == 0) ? Vout : T;
             k_smooth_step<<<nblocks(nV), kBlock, 0, s>>>(src, dst, nV, off, nbr, lam);
+            if (rescale) {  // back to the starting volume, scaling about the origin
+                k_volume_partial<<<kVolBlocks, kBlock, 0, s>>>(dst, nV, F, nF, vpart);
+                k_volume_final<<<1, kBlock, 0, s>>>(vpart, vol0, vscale, 0);
+                k_scale_f32<<<nblocks(3 * nV), kBlock, 0, s>>>(dst, 3 * nV, vscale);
+            }
             src = dst;
         }
     }

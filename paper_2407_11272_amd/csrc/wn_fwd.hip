@@ -66,6 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_records(const float *__restrict
     if (R) {
         vid = R[2 * r];
         fid = R[2 * r + 1];
+        check_strip_record(R, r, F, nF, fid, hdr);
     } else {
         const int64_t f = r / 3;
         const int j = (int)(r - 3 * f);

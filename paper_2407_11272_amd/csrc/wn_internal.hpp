@@ -363,6 +363,40 @@ __device__ __forceinline__ VRec make_record(const float *__restrict__ V, int64_t
     return r;
 }
 
+// A strip record r whose face id fid is in range must complete F[fid]: the vertex ids of
+// records r - 2, r - 1 and r are those of F[fid] in some order (a stale strip order or a
+// hand-built stream that breaks this would give a silently wrong W).  Records 0 and 1
+// have no such window.
+__device__ __forceinline__ void sort3(int32_t &a, int32_t &b, int32_t &c) {
+    int32_t t;
+    if (a > b) t = a, a = b, b = t;
+    if (b > c) t = b, b = c, c = t;
+    if (a > b) t = a, a = b, b = t;
+}
+
+__device__ __forceinline__ bool strip_window_ok(const int32_t *__restrict__ R, int64_t r,
+                                                const int32_t *__restrict__ F, int32_t fid) {
+    if (r < 2) return false;
+    int32_t a = R[2 * (r - 2)], b = R[2 * (r - 1)], c = R[2 * r];
+    int32_t x = F[3 * (int64_t)fid], y = F[3 * (int64_t)fid + 1], z = F[3 * (int64_t)fid + 2];
+    sort3(a, b, c);
+    sort3(x, y, z);
+    return a == x && b == y && c == z;
+}
+
+// Strip record r (vertex vid, face fid) checked against F before it is packed: a face
+// whose window is not F[fid] is recorded as a bad index, and a face flag on record 0 or
+// 1 is also dropped (its window would reach before the stream).
+__device__ __forceinline__ void check_strip_record(const int32_t *__restrict__ R, int64_t r,
+                                                   const int32_t *__restrict__ F, int64_t nF, int32_t &fid,
+                                                   WsHeader *hdr) {
+    if (fid < 0 || (int64_t)fid >= nF) return;  // no face, or out of range (make_record records it)
+    if (!strip_window_ok(R, r, F, fid)) {
+        atomicOr(&hdr->bad_index, 1);
+        if (r < 2) fid = -1;
+    }
+}
+
 struct OccParams {
     void *occ;
     int32_t mode;
@@ -414,21 +448,41 @@ hipError_t launch_sigmoid_mse(const float *W, const float *target, int64_t n, fl
 int loss_blocks(int64_t n);
 
 // Backward pieces (wn_bwd.hip).  `naive` selects the adjoint of the Eq. 4 sum instead of
-// the exact solid-angle field.  The points are cut into splits of `chunk` points (0: the
-// default size, bwd_chunk) whose partial sums are kept apart and added in split order at
-// the end, so a call sequence BEGIN, any ranges of whole splits, END gives the same bits
-// as one call over all points with the same chunk.
+// the exact solid-angle field.  The points' 256-point tiles are dealt to S = bwd_splits
+// splits in turn (tile t to split t mod S); each split keeps compensated running sums
+// per corner in the workspace, and the splits are added in split order at the end.  A
+// call sequence BEGIN, consecutive point ranges of whole tiles in increasing order, END
+// therefore gives the same bits as one call over all points.
 constexpr int kBwdBegin = 1, kBwdEnd = 2;
-int64_t bwd_chunk(int64_t nF, int64_t nQ, int64_t chunk);
-size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ, int64_t chunk = 0);
+constexpr int kBwdTile = 256;
+int bwd_splits(int64_t nF, int64_t nQ);
+size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ);
 wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
-                       int64_t nQ, const float *dLdW, int64_t chunk, int64_t p0, int64_t n, int flags, float *dLdV,
-                       float *dLdT, char *ws, size_t ws_bytes, hipStream_t s, bool naive = false);
+                       int64_t nQ, const float *dLdW, int64_t p0, int64_t n, int flags, float *dLdV, float *dLdT,
+                       char *ws, size_t ws_bytes, hipStream_t s, bool naive = false);
 inline wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
                               int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes,
                               hipStream_t s, bool naive = false) {
-    return run_backward(V, nV, F, nF, ps, nQ, dLdW, 0, 0, nQ, kBwdBegin | kBwdEnd, dLdV, dLdT, ws, ws_bytes, s,
-                        naive);
+    return run_backward(V, nV, F, nF, ps, nQ, dLdW, 0, nQ, kBwdBegin | kBwdEnd, dLdV, dLdT, ws, ws_bytes, s, naive);
+}
+
+// A split's running sums of face f: (sum, compensation) of its 9 corner components at
+// state[(split * 9 + i) * nF + f] (coalesced over faces).  A split that starts here
+// begins at zero.
+__device__ __forceinline__ void load_state(const float2 *__restrict__ state, int64_t split, int32_t nF, int32_t f,
+                                           bool fresh, float (&s)[9], float (&c)[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float2 x = fresh ? make_float2(0.0f, 0.0f) : state[(split * 9 + i) * nF + f];
+        s[i] = x.x;
+        c[i] = x.y;
+    }
+}
+
+__device__ __forceinline__ void store_state(float2 *__restrict__ state, int64_t split, int32_t nF, int32_t f,
+                                            const float (&s)[9], const float (&c)[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) state[(split * 9 + i) * nF + f] = make_float2(s[i], c[i]);
 }
 
 // Naive flux integral of Eq. 4 (wn_naive.hip).
@@ -444,8 +498,8 @@ size_t sample_workspace(int64_t nF);
 size_t nn_workspace(int64_t nA, int64_t nB);
 wn_status run_cubify(const uint8_t *occ, const int32_t n[3], const float lo[3], const float hi[3], float *V,
                      int64_t capV, int32_t *F, int64_t capF, int64_t *counts, char *ws, hipStream_t s);
-wn_status run_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam, int32_t iters, float *Vout,
-                     char *ws, hipStream_t s);
+wn_status run_smooth(const float *V, int64_t nV, const int32_t *F, int64_t nF, float lam, int32_t iters,
+                     int32_t keep_volume, float *Vout, char *ws, hipStream_t s);
 wn_status run_sample(const float *V, int64_t nV, const int32_t *F, int64_t nF, const double *u, int64_t n, float *P,
                      int32_t *face, char *ws, hipStream_t s);
 wn_status run_nn(const float *A, int64_t nA, const float *B, int64_t nB, float *d, char *ws, hipStream_t s);
@@ -454,9 +508,10 @@ wn_status run_chamfer(const float *A, int64_t nA, const float *B, int64_t nB, do
 // Adam over a flat parameter array (wn_morph.hip); t >= 1 is the step number.
 hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float b1,
                        float b2, float eps, hipStream_t s);
-// The adjoint pair kernel of Eq. 4 (defined in wn_naive.hip, launched by run_backward).
-hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int64_t chunkP,
-                            int32_t split0, int32_t nsplit, const float *dLdW, float *partials, hipStream_t s);
+// The adjoint pair kernel of Eq. 4 (defined in wn_naive.hip, launched by run_backward)
+// over the tiles [t0, t1) with S splits, `rows` = min(S, t1 - t0).
+hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int32_t S, int64_t t0,
+                            int64_t t1, int32_t rows, const float *dLdW, float2 *state, hipStream_t s);
 
 // Flipping duplication (wn_bwd.hip).
 size_t flip_workspace(int64_t nV, int64_t nF);

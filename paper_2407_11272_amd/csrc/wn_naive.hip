@@ -104,13 +104,16 @@ __global__ __launch_bounds__(kBlock) void k_naive_fwd(const NaiveRec *__restrict
     }
 }
 
-// Adjoint pair kernel: grid x = face blocks, y = point splits; partials [split][9][nF].
+// Adjoint pair kernel: grid x = face blocks, y = the splits owning a tile of [t0, t1)
+// (split (t0 + y) mod S, tiles of kBwdTile points dealt to the splits in turn); running
+// sums in state, float2 [S][9][nF] (the layout of the exact adjoint).
 __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict__ soup, int32_t nF, PointSrc ps,
-                                                      int64_t nQ, int64_t chunkP, int32_t split0,
-                                                      const float *__restrict__ dLdW, float *__restrict__ partials) {
+                                                      int64_t nQ, int32_t S, int64_t t0, int64_t t1,
+                                                      const float *__restrict__ dLdW, float2 *__restrict__ state) {
     __shared__ float4 pts[kBlock];
     const int tid = threadIdx.x;
-    const int64_t sy = (int64_t)split0 + blockIdx.y;  // this block's point split
+    const int64_t tfirst = t0 + blockIdx.y;  // this block's first tile
+    const int64_t sy = tfirst % S;           // its split
     int32_t f = (int32_t)blockIdx.x * kBlock + tid;
     const bool live = f < nF;
     f = live ? f : nF - 1;
@@ -126,17 +129,15 @@ __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict_
 #pragma unroll
         for (int d = 0; d < 3; ++d) e[j][d] = v[(j + 1) % 3][d] - v[(j + 2) % 3][d];
     float s[9], c[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] = c[i] = 0.0f;
-    const int64_t p0 = sy * chunkP;
-    const int64_t p1 = min(nQ, p0 + chunkP);
-    for (int64_t t0 = p0; t0 < p1; t0 += kBlock) {
-        const int nt = (int)min((int64_t)kBlock, p1 - t0);
+    load_state(state, sy, nF, f, tfirst < S, s, c);
+    for (int64_t t = tfirst; t < t1; t += S) {
+        const int64_t q0 = t * kBwdTile;
+        const int nt = (int)min((int64_t)kBwdTile, nQ - q0);
         __syncthreads();
         if (tid < nt) {
             float x, y, z;
-            ps.get(t0 + tid, x, y, z);
-            pts[tid] = make_float4(x, y, z, dLdW[t0 + tid]);
+            ps.get(q0 + tid, x, y, z);
+            pts[tid] = make_float4(x, y, z, dLdW[q0 + tid]);
         }
         __syncthreads();
         // Per corner j the pair adds u + e_j x a, where u (the centroid part, shared by the
@@ -170,10 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_naive_bwd(const FaceRec *__restrict_
 #pragma unroll
         for (int i = 0; i < 9; ++i) neumaier_add(s[i], c[i], ts[i]);
     }
-    if (live) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) partials[(sy * 9 + i) * nF + f] = s[i] + c[i];
-    }
+    if (live) store_state(state, sy, nF, f, s, c);
 }
 
 // ------------------------------------------------------------------ host
@@ -219,10 +217,10 @@ hipError_t launch_naive_fwd(const float *V, int64_t nV, const int32_t *F, int64_
     return launch_split_reduce(partials, split, nQ, kInv8Pi, W, occ, s);
 }
 
-hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int64_t chunkP,
-                            int32_t split0, int32_t nsplit, const float *dLdW, float *partials, hipStream_t s) {
-    k_naive_bwd<<<dim3((unsigned)((nF + kBlock - 1) / kBlock), (unsigned)nsplit), kBlock, 0, s>>>(
-        soup, nF, ps, nQ, chunkP, split0, dLdW, partials);
+hipError_t launch_naive_bwd(const FaceRec *soup, int32_t nF, const PointSrc &ps, int64_t nQ, int32_t S, int64_t t0,
+                            int64_t t1, int32_t rows, const float *dLdW, float2 *state, hipStream_t s) {
+    k_naive_bwd<<<dim3((unsigned)((nF + kBlock - 1) / kBlock), (unsigned)rows), kBlock, 0, s>>>(soup, nF, ps, nQ, S,
+                                                                                               t0, t1, dLdW, state);
     return hipGetLastError();
 }
 

@@ -9,8 +9,9 @@ caller wants d(loss)/d(vertices)).  The loop
   * keeps each admitted request's mesh, grid outputs and gradient buffers resident
     on the device until it completes;
   * cuts every request into units of work: slices of its voxels for the forward pass
-    and, for gradient requests, whole point splits of the adjoint (its per-split sums
-    are kept apart and added in split order at the end);
+    and, for gradient requests, consecutive point ranges of the adjoint (each a whole
+    number of rounds over the adjoint's splits, whose running sums stay in the request's
+    workspace and are added in split order at the end);
   * every scheduler step spends a bounded amount of work.  Under the default
     earliest-deadline policy each request gets a deadline at admission (its arrival
     plus a slack proportional to its estimated service time) and the step's budget goes
@@ -24,8 +25,8 @@ caller wants d(loss)/d(vertices)).  The loop
     not delayed by host polling.
 
 A voxel's winding number does not depend on which slice or batch computed it, and a
-request's adjoint split size depends only on its own size, so each result is
-bit-identical alone and in any mix.  The scheduling logic talks to the GPU only through
+request's adjoint splits depend only on its own size and its ranges run in order, so
+each result is bit-identical alone and in any mix.  The scheduling logic talks to the GPU only through
 an executor object; tests drive it with a simulated executor on the CPU.
 """
 from __future__ import annotations
@@ -45,7 +46,6 @@ ADJOINT_COST = 2.8        # cost of one adjoint (point, face) pair in forward pa
 RATE_PAIRS = 1.4e12       # forward pairs per second, for the deadline estimate
 DEADLINE_SLACK = 1.0      # deadline = arrival + DEADLINE_SLACK * estimated service + DEADLINE_BASE
 DEADLINE_BASE = 0.05      # seconds
-ADJOINT_MAX_CHUNK = 8192   # points per adjoint split (at most; small requests use smaller splits)
 
 
 @dataclass
@@ -85,6 +85,7 @@ class ServeResult:
     occ: object = None
     loss: object = None
     dLdV: object = None
+    dLdT: object = None
 
     @property
     def latency(self) -> float:
@@ -96,7 +97,7 @@ class _Active:
     req: ServeRequest
     res: ServeResult
     footprint: int
-    adj_chunk: int = 0
+    adj_unit: int = 0           # adjoint: points per unit granule (one round over its splits)
     deadline: float = 0.0
     state: object = None        # executor-owned per-request state
     next_point: int = 0         # forward: next voxel to launch
@@ -114,14 +115,15 @@ def _lib():
     return L.load()
 
 
-def adjoint_chunk(nF: int, P: int) -> int:
-    """Points per adjoint split of a served gradient request: the library's default for
-    (nF, P), at most ADJOINT_MAX_CHUNK, so that a step's worth of splits fills the GPU
-    whatever the face count, and large enough for at most 65535 splits.  Depends only on
-    the request."""
-    c = int(min(ADJOINT_MAX_CHUNK, _lib().wn_backward_chunk(max(0, nF), max(0, P), 0)))
-    least = -(-max(0, P) // 65535)
-    return max(c, -(-least // 256) * 256)
+def adjoint_unit(nF: int, P: int) -> int:
+    """Points per adjoint unit granule of a served gradient request: one round of 256-point
+    tiles over the adjoint's splits, so that every unit keeps all of its splits busy.
+    Depends only on the request."""
+    from . import _lib as L
+    S = int(_lib().wn_backward_splits(max(0, nF), max(0, P)))
+    if S < 1:
+        raise ValueError("sizes out of range for the adjoint")
+    return S * L.WN_BWD_TILE
 
 
 def footprint_bytes(req: ServeRequest, slice_points: int) -> int:
@@ -132,9 +134,10 @@ def footprint_bytes(req: ServeRequest, slice_points: int) -> int:
     chunks = max(1, -(-nF // 4096))
     b += 48 * nF + (4 * chunks * min(P, slice_points) if chunks > 1 else 0)
     if req.wants_grad:
-        # target, dL/dW, dL/dV, and the adjoint's own workspace (face records, per-split
-        # corner sums, corner sort buffers, vertex bounds)
-        ws = _lib().wn_workspace_size_backward(nV, nF, P, adjoint_chunk(nF, P))
+        # target, dL/dW, dL/dV, and the adjoint's own workspace (face records, the splits'
+        # running corner sums, corner sort buffers, vertex bounds)
+        from . import _lib as L
+        ws = _lib().wn_workspace_size(L.WN_OP_BACKWARD, nV, nF, P)
         if ws == 0:
             raise ValueError("sizes out of range for the adjoint")
         b += 8 * P + 12 * nV + int(ws) + 512
@@ -196,7 +199,7 @@ class Server:
         nF, P = len(req.F), req.points
         work = P * nF
         if req.wants_grad:
-            a.adj_chunk = adjoint_chunk(nF, P)
+            a.adj_unit = adjoint_unit(nF, P)
             work += self.adj_cost * P * nF
         a.deadline = req.arrival + self.slack * work / self.rate + self.base
         prep = getattr(self.ex, "prepare", None)
@@ -229,7 +232,7 @@ class Server:
             self.pending.popleft()
             admitted += 1
             a.res.admitted = now
-            a.state = self.ex.admit(a.req, a.adj_chunk)
+            a.state = self.ex.admit(a.req)
             self.active.append(a)
             self.in_use += a.footprint
             self.peak_in_use = max(self.peak_in_use, self.in_use)
@@ -276,12 +279,12 @@ class Server:
                     a.launched_all = True
                     fdone.append(a)
             if a.launched_all and a.req.wants_grad and not a.adj_ended:
-                unit = a.adj_chunk * nF * self.adj_cost
+                unit = a.adj_unit * nF * self.adj_cost
                 k = int((b - spent) // unit)
                 if k < 1 and must and spent == 0:
                     k = 1
                 if k > 0 or P == 0:
-                    n = min(k * a.adj_chunk, P - a.adj_next)
+                    n = min(k * a.adj_unit, P - a.adj_next)
                     last = a.adj_next + n >= P
                     adj.append((a, a.adj_next, n, last))
                     a.adj_next += n
@@ -367,11 +370,12 @@ class GpuExecutor:
     the forward stream, and the loss of requests whose forward completed and adjoint
     units on a second stream after that forward; completion times from timing events."""
 
-    def __init__(self, device="cuda", graph: bool = True, strips: bool = True):
+    def __init__(self, device="cuda", graph: bool = True, strips: bool = True, keep_dLdT: bool = False):
         import concurrent.futures
         import torch
         self.torch = torch
         self.strips = strips
+        self.keep_dLdT = keep_dLdT   # also return per-corner dL/dT of gradient requests
         self.dev = torch.device(device)
         self.fwd = torch.cuda.Stream(self.dev)
         self.aux = torch.cuda.Stream(self.dev)   # losses and adjoint units (default priority)
@@ -397,7 +401,7 @@ class GpuExecutor:
         self.ref.synchronize()
         self.t_ref = time.perf_counter() - t0
 
-    def admit(self, req: ServeRequest, adj_chunk: int = 0):
+    def admit(self, req: ServeRequest):
         import paper_2407_11272_amd as wn
         torch = self.torch
         st = {}
@@ -422,7 +426,9 @@ class GpuExecutor:
                 st["target"] = T.to(self.dev, non_blocking=True)
                 st["hold"] = (V, F, T)
                 st["dLdW"] = torch.empty(req.points, dtype=torch.float32, device=self.dev)
-                st["adj"] = wn.SlicedBackward(st["V"], st["F"], grid=job.grid, chunk=adj_chunk)
+                st["adj"] = wn.SlicedBackward(st["V"], st["F"], grid=job.grid)
+                if self.keep_dLdT:
+                    st["dLdT"] = torch.empty((len(req.F), 3, 3), dtype=torch.float32, device=self.dev)
         return st
 
     def wait_inflight(self, keep: int):
@@ -468,7 +474,7 @@ class GpuExecutor:
                 if n > 0:
                     st["adj"].points(p0, n, st["dLdW"])
                 if last:
-                    st["dLdV"] = st["adj"].end()
+                    st["dLdV"] = st["adj"].end(dLdT=st.get("dLdT"))
                     self._done_event(st, self.aux)
             ev = torch.cuda.Event()
             ev.record(self.aux)
@@ -483,7 +489,7 @@ class GpuExecutor:
     def collect(self, st, res: ServeResult):
         job = st["job"]
         res.W, res.occ = job.W, job.occ
-        res.loss, res.dLdV = st.get("loss"), st.get("dLdV")
+        res.loss, res.dLdV, res.dLdT = st.get("loss"), st.get("dLdV"), st.get("dLdT")
         st.clear()
 
     def idle(self, seconds: float):

@@ -57,18 +57,16 @@ def test_no_cpu_fallback_on_host_tensors():
         wn.wn_voxelize(torch.zeros((3, 3)), torch.zeros((1, 3), dtype=torch.int32), grid=wn.Grid.cube(2))
 
 
-def test_backward_split_size_and_sliced_workspace_are_host_only():
+def test_backward_splits_are_host_only():
     lib = L.load()
-    # the default split size: whole 256-point tiles; a requested size is returned as is
-    d = lib.wn_backward_chunk(5120, 64 ** 3, 0)
-    assert d >= 256 and d % 256 == 0
-    assert lib.wn_backward_chunk(5120, 64 ** 3, 1000) == 1000
-    assert lib.wn_backward_chunk(-1, 10, 0) == -1 and lib.wn_backward_chunk(1, 10, -5) == -1
-    # the default sliced workspace is wn_backward's; smaller splits need more partial sums
-    assert lib.wn_workspace_size_backward(2562, 5120, 64 ** 3, 0) == wn.wn_workspace_size(L.WN_OP_BACKWARD, 2562,
-                                                                                          5120, 64 ** 3)
-    small = lib.wn_workspace_size_backward(2562, 5120, 64 ** 3, 256)
-    assert small >= 36 * 5120 * (64 ** 3 // 256)
-    # at most 65535 splits
-    assert lib.wn_workspace_size_backward(10, 10, 65536, 1) == 0
-    assert lib.wn_workspace_size_backward(10, 10, 65535, 1) > 0
+    # a pure function of the sizes: at most one split per 256-point tile, at most 4096,
+    # and at most 256 MiB of running sums (72 bytes per face per split)
+    assert lib.wn_backward_splits(5120, 64 ** 3) == lib.wn_backward_splits(5120, 64 ** 3)
+    assert 1 <= lib.wn_backward_splits(5120, 64 ** 3) <= 1024
+    assert lib.wn_backward_splits(10, 300) == 2
+    assert lib.wn_backward_splits(10, 0) == 1
+    assert lib.wn_backward_splits(100000, 256 ** 3) * 72 * 100000 <= 256 << 20
+    assert lib.wn_backward_splits(-1, 10) == -1 and lib.wn_backward_splits(1, -5) == -1
+    # the adjoint workspace grows with the split count's running sums
+    b = wn.wn_workspace_size(L.WN_OP_BACKWARD, 2562, 5120, 64 ** 3)
+    assert b >= 256 + 48 * 5120 + 72 * 5120 * lib.wn_backward_splits(5120, 64 ** 3)

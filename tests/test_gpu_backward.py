@@ -32,22 +32,29 @@ def _to_dev(c):
     return wn.as_mesh(torch.as_tensor(np.asarray(c.V, np.float32)), torch.as_tensor(c.F))
 
 
-def _gpu_loss_grad(c):
-    """Forward, sigmoid-MSE loss and its gradient, adjoint: all in the HIP library."""
+def _f32(V):
+    return np.asarray(V, np.float32).astype(np.float64)
+
+
+def _oracle_dLdW(orc, c, Q=None):
+    """The oracle's W, loss and dL/dW of the sigmoid-MSE loss (FP64); the GPU adjoint is
+    then given the same dL/dW (rounded to FP32), so both sides differentiate the same
+    loss at the same point and no input of the oracle comes from the GPU."""
+    V64 = _f32(c.V)
+    Q = orc.grid_points(c.grid) if Q is None else Q
+    W = orc.winding(V64, c.F, Q)
+    L, g = orc.sigmoid_mse(W, c.target, c.tau, c.k)
+    g32 = np.asarray(g, np.float32)
+    return W, L, g32, Q
+
+
+def _gpu_adjoint(c, g32):
     import torch
     import paper_2407_11272_amd as wn
     Vt, Ft = _to_dev(c)
-    W = wn.wn_voxelize(Vt, Ft, grid=c.grid).reshape(-1)
-    T = torch.as_tensor(c.target).cuda()
-    loss, dLdW = wn.wn_sigmoid_mse(W, T, c.tau, c.k)
-    dLdV, dLdT = wn.wn_backward(Vt, Ft, dLdW, grid=c.grid, want_dLdT=True)
+    dLdV, dLdT = wn.wn_backward(Vt, Ft, torch.as_tensor(g32).cuda(), grid=c.grid, want_dLdT=True)
     torch.cuda.synchronize()
-    return (W.cpu().numpy().astype(np.float64), float(loss.item()), dLdW.cpu().numpy().astype(np.float64),
-            dLdV.cpu().numpy().astype(np.float64), dLdT.cpu().numpy().astype(np.float64))
-
-
-def _f32(V):
-    return np.asarray(V, np.float32).astype(np.float64)
+    return dLdV.cpu().numpy().astype(np.float64), dLdT.cpu().numpy().astype(np.float64)
 
 
 def _check_T(Tg, Tr, label):
@@ -55,69 +62,96 @@ def _check_T(Tg, Tr, label):
     d = np.abs(Tg - Tr)
     big = np.abs(Tr) > 1e-2 * scale
     rel = d[big] / np.abs(Tr[big])
-    print(f"[{label}] |dL/dT|inf={scale:.3e} max abs err={d.max():.3e} max rel (big)={rel.max():.3e}", flush=True)
+    print(f"[{label}] |dL/dT|inf={scale:.3e} max abs err={d.max():.3e} max rel (big)={rel.max():.3e} "
+          f"({int(big.sum())} of {big.size} entries big)", flush=True)
     assert d.max() <= 1e-3 * scale
     assert rel.max() <= 1e-3
 
 
-def test_corner_and_vertex_gradients_32(dev, orc):
-    """(i) + (ii) on the differentiable workload's mesh at 32^3, every face."""
-    c = wi.config3_differentiable(res=32)
-    Wg, Lg, gg, Dg, Tg = _gpu_loss_grad(c)
-    V64 = _f32(c.V)
-    Q = orc.grid_points(c.grid)
-    # the gradient is taken at the GPU's dL/dW so only the adjoint is compared here
-    Tr, Dr = orc.grad(V64, c.F, Q, gg)
-    _check_T(Tg.reshape(-1), Tr.reshape(-1), "C3@32 dL/dT")
+def _check_V(Dg, Dr, Tr, F, label):
+    """dL/dV is a sum of corner gradients that cancel (exactly, for a closed mesh): each
+    vertex is held to 1e-3 of the sum of the magnitudes of its corners' terms."""
     corner_abs = np.zeros_like(Dr)
-    np.add.at(corner_abs, c.F.reshape(-1), np.abs(Tr.reshape(-1, 3)))
-    assert np.all(np.abs(Dg - Dr) <= 1e-3 * corner_abs + 1e-12)
-    # the loss itself against the oracle's forward
-    Lr, gr = orc.sigmoid_mse(orc.winding(V64, c.F, Q), c.target, c.tau, c.k)
-    assert Lg == pytest.approx(Lr, rel=1e-4)
+    np.add.at(corner_abs, np.asarray(F).reshape(-1), np.abs(Tr.reshape(-1, 3)))
+    err = np.abs(Dg - Dr)
+    print(f"[{label}] max |d dL/dV| / corner scale = {(err / (corner_abs + 1e-300)).max():.3e}", flush=True)
+    assert np.all(err <= 1e-3 * corner_abs + 1e-12)
 
 
-def test_corner_gradients_full_size_sampled_faces(dev, orc):
-    """(i) at the full 64^3 grid for 96 seeded faces (the oracle's cost is per face)."""
+def test_corner_and_vertex_gradients_32(dev, orc):
+    """(i) + (ii) on the differentiable workload's mesh at 32^3, every face and vertex;
+    the loss of the GPU's own forward against the oracle's."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable(res=32)
+    Wr, Lr, g32, Q = _oracle_dLdW(orc, c)
+    Dg, Tg = _gpu_adjoint(c, g32)
+    Tr, Dr = orc.grad(_f32(c.V), c.F, Q, g32.astype(np.float64))
+    _check_T(Tg.reshape(-1), Tr.reshape(-1), "C3@32 dL/dT")
+    _check_V(Dg, Dr, Tr, c.F, "C3@32 dL/dV")
+    Vt, Ft = _to_dev(c)
+    W = wn.wn_voxelize(Vt, Ft, grid=c.grid).reshape(-1)
+    loss, _ = wn.wn_sigmoid_mse(W, torch.as_tensor(c.target).cuda(), c.tau, c.k)
+    assert float(loss.item()) == pytest.approx(Lr, rel=1e-4)
+
+
+def test_corner_and_vertex_gradients_full_size(dev, orc):
+    """(i) + (ii) on the differentiable workload at its full size (5120 faces, 64^3):
+    all 46 080 corner components and all 2562 vertices against the oracle."""
     c = wi.config3_differentiable(res=64)
-    Wg, Lg, gg, Dg, Tg = _gpu_loss_grad(c)
-    rng = np.random.default_rng(200)
-    fs = np.sort(rng.choice(len(c.F), 96, replace=False))
-    Tr, _ = orc.grad(_f32(c.V), c.F[fs], orc.grid_points(c.grid), gg)
-    _check_T(Tg[fs].reshape(-1), Tr.reshape(-1), "C3@64 dL/dT sampled")
+    Wr, Lr, g32, Q = _oracle_dLdW(orc, c)
+    Dg, Tg = _gpu_adjoint(c, g32)
+    Tr, Dr = orc.grad(_f32(c.V), c.F, Q, g32.astype(np.float64))
+    _check_T(Tg.reshape(-1), Tr.reshape(-1), "C3@64 dL/dT all faces")
+    _check_V(Dg, Dr, Tr, c.F, "C3@64 dL/dV all vertices")
 
 
-def test_open_mesh_vertex_gradient_vs_finite_differences(dev, orc):
-    """(iii) Open variant at 24^3: the full sigmoid-MSE loss differentiated by FP64
-    central differences of the oracle (h = 1e-6) on the rim vertices with the largest
-    gradient; interior vertices carry no gradient."""
-    c = wi.config3_differentiable(res=24, open_variant=True)
-    Wg, Lg, gg, Dg, Tg = _gpu_loss_grad(c)
+def _rim_vertices(F):
+    from collections import Counter
+    cnt = Counter()
+    for f in F:
+        for j in range(3):
+            a, b = sorted((int(f[j]), int(f[(j + 1) % 3])))
+            cnt[(a, b)] += 1
+    return {x for (a, b), n in cnt.items() if n == 1 for x in (a, b)}
+
+
+def test_open_mesh_vertex_gradient_vs_finite_differences_full_size(dev, orc):
+    """(iii) The open variant of the differentiable workload at its full 64^3 grid: dL/dV
+    of the sigmoid-MSE loss against FP64 central differences (h = 1e-6) of the oracle's
+    loss, on the 8 rim vertices with the largest gradient (1e-3 relative).
+    Moving vertex v changes only the faces that use it, so the perturbed field is
+    W - W_adj(V) + W_adj(V +- h e_d), with W_adj the oracle's sum over v's faces: the
+    same FP64 loss as a full re-evaluation, at a few faces' cost per difference.
+    Interior vertices carry no gradient (W depends only on the boundary)."""
+    c = wi.config3_differentiable(res=64, open_variant=True)
+    Wr, Lr, g32, Q = _oracle_dLdW(orc, c)
+    Dg, Tg = _gpu_adjoint(c, g32)
     V64 = _f32(c.V)
-    Q = orc.grid_points(c.grid)
-    _, Dr = orc.grad(V64, c.F, Q, orc.sigmoid_mse(orc.winding(V64, c.F, Q), c.target, c.tau, c.k)[1])
+    _, Dr = orc.grad(V64, c.F, Q, g32.astype(np.float64))
+    rim = _rim_vertices(c.F)
     mag = np.linalg.norm(Dr, axis=1)
-    picks = np.argsort(-mag)[:4]
+    picks = [v for v in np.argsort(-mag) if v in rim][:8]
+    assert len(picks) == 8
     h = 1e-6
+    compared = 0
     for v in picks:
+        adj = np.nonzero((c.F == v).any(axis=1))[0]
+        Fa = c.F[adj]
+        W_rest = Wr - orc.winding(V64, Fa, Q)
         for d in range(3):
             Vp, Vm = V64.copy(), V64.copy()
             Vp[v, d] += h
             Vm[v, d] -= h
-            Lp = orc.sigmoid_mse(orc.winding(Vp, c.F, Q), c.target, c.tau, c.k)[0]
-            Lm = orc.sigmoid_mse(orc.winding(Vm, c.F, Q), c.target, c.tau, c.k)[0]
+            Lp = orc.sigmoid_mse(W_rest + orc.winding(Vp, Fa, Q), c.target, c.tau, c.k)[0]
+            Lm = orc.sigmoid_mse(W_rest + orc.winding(Vm, Fa, Q), c.target, c.tau, c.k)[0]
             fd = (Lp - Lm) / (2 * h)
             if abs(fd) > 1e-2 * mag[picks[0]]:
-                print(f"v={v} d={d} gpu={Dg[v, d]:.6e} fd={fd:.6e}", flush=True)
+                print(f"v={v} d={d} gpu={Dg[v, d]:.6e} fd={fd:.6e} rel={abs(Dg[v, d] - fd) / abs(fd):.2e}",
+                      flush=True)
                 assert Dg[v, d] == pytest.approx(fd, rel=1e-3)
-    # interior (not on a hole rim) vertices: zero up to FP32 cancellation
-    from collections import Counter
-    cnt = Counter()
-    for f in c.F:
-        for j in range(3):
-            a, b = sorted((f[j], f[(j + 1) % 3]))
-            cnt[(a, b)] += 1
-    rim = {x for (a, b), n in cnt.items() if n == 1 for x in (a, b)}
+                compared += 1
+    assert compared >= 12
     interior = np.array(sorted(set(range(len(c.V))) - rim))
     assert np.abs(Dg[interior]).max() <= 1e-3 * np.abs(Dg).max()
 
@@ -177,50 +211,49 @@ def test_backward_edge_cases(dev, orc):
 
 
 def test_sliced_adjoint_equals_one_call_and_the_oracle(dev, orc):
-    """wn_backward_range: ranges of whole splits in any order and grouping give the same
-    bits as one call with the same split size; split size 0 is wn_backward bit for bit;
-    and the sliced result holds the oracle's bar (i)."""
+    """wn_backward_range: consecutive ranges of whole 256-point tiles in increasing order
+    (shorter and longer than one round over the splits, the last reaching the final
+    point) give the same bits as wn_backward, and hold the oracle's bar (i)."""
     import torch
     import paper_2407_11272_amd as wn
-    c = wi.config3_differentiable(res=32, open_variant=True)
+    c = wi.config3_differentiable(res=64, open_variant=True)
     Vt, Ft = _to_dev(c)
     P = c.grid.size
     g = torch.randn(P, device="cuda", generator=torch.Generator("cuda").manual_seed(11))
-    # chunk 0: the same as wn_backward
-    sb0 = wn.SlicedBackward(Vt, Ft, grid=c.grid)
-    sb0.begin()
-    sb0.points(0, P, g)
-    T0 = torch.empty((len(c.F), 3, 3), device="cuda")
-    D0 = sb0.end(dLdT=T0)
     Dw, Tw = wn.wn_backward(Vt, Ft, g, grid=c.grid, want_dLdT=True)
-    torch.cuda.synchronize()
-    assert torch.equal(D0, Dw) and torch.equal(T0, Tw)
-    # chunk 1280 (not a multiple of the 256-point tile): 26 splits, the last ragged
-    chunk = 1280
-    one = wn.SlicedBackward(Vt, Ft, grid=c.grid, chunk=chunk)
-    assert one.chunk == chunk and one.splits == -(-P // chunk)
+    one = wn.SlicedBackward(Vt, Ft, grid=c.grid)
+    tiles = -(-P // one.tile)
+    print(f"[sliced] {P} points, {tiles} tiles, {one.splits} splits", flush=True)
+    assert 1 < one.splits < tiles   # so that ranges can be shorter and longer than a round
     one.begin()
     one.points(0, P, g)
-    T1 = torch.empty_like(T0)
-    D1 = one.end(dLdT=T1)
+    T0 = torch.empty((len(c.F), 3, 3), device="cuda")
+    D0 = one.end(dLdT=T0)
+    torch.cuda.synchronize()
+    assert torch.equal(D0, Dw) and torch.equal(T0, Tw)
     rng = np.random.default_rng(5)
-    for trial in range(3):
-        cuts = np.sort(rng.choice(np.arange(1, one.splits), size=6, replace=False))
-        bounds = [0] + [int(x) * chunk for x in cuts] + [P]
-        ranges = [(bounds[i], bounds[i + 1] - bounds[i]) for i in range(len(bounds) - 1)]
-        rng.shuffle(ranges)
-        sb = wn.SlicedBackward(Vt, Ft, grid=c.grid, chunk=chunk)
+    for trial in range(4):
+        cuts = np.sort(rng.choice(np.arange(1, tiles), size=7 if trial < 3 else tiles - 1, replace=False))
+        bounds = [0] + [int(x) * one.tile for x in cuts] + [P]
+        sb = wn.SlicedBackward(Vt, Ft, grid=c.grid)
         sb.begin()
-        for p0, n in ranges:
-            sb.points(p0, n, g)
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            sb.points(a, b - a, g)
         T2 = torch.empty_like(T0)
         D2 = sb.end(dLdT=T2)
         torch.cuda.synchronize()
-        print(f"[sliced] trial {trial}: {len(ranges)} ranges, order {[p0 // chunk for p0, _ in ranges]}", flush=True)
-        assert torch.equal(D1, D2) and torch.equal(T1, T2)
-    # the split size changes only the summation order: the oracle's bar (i)
+        print(f"[sliced] trial {trial}: {len(bounds) - 1} ranges, tiles per range "
+              f"{sorted(set(np.diff(bounds) // one.tile))[:8]}", flush=True)
+        assert torch.equal(D2, Dw) and torch.equal(T2, Tw)
     Tr, _ = orc.grad(_f32(c.V), c.F, orc.grid_points(c.grid), g.cpu().numpy().astype(np.float64))
-    _check_T(T1.cpu().numpy().astype(np.float64).reshape(-1), Tr.reshape(-1), "sliced chunk 1280")
+    _check_T(T0.cpu().numpy().astype(np.float64).reshape(-1), Tr.reshape(-1), "sliced")
+    # ranges out of order are refused by the binding before anything is launched
+    sb = wn.SlicedBackward(Vt, Ft, grid=c.grid)
+    sb.begin()
+    with pytest.raises(ValueError):
+        sb.points(one.tile, P - one.tile, g)
+    with pytest.raises(ValueError):
+        sb.end()
 
 
 def test_sliced_adjoint_point_list_and_argument_errors(dev, orc):
@@ -235,40 +268,37 @@ def test_sliced_adjoint_point_list_and_argument_errors(dev, orc):
     gq = rng.normal(size=1000).astype(np.float32)
     Vt, Ft = wn.as_mesh(torch.as_tensor(Vs), torch.as_tensor(Fs))
     Qt, gt = torch.as_tensor(Q).cuda(), torch.as_tensor(gq).cuda()
-    sb = wn.SlicedBackward(Vt, Ft, Q=Qt, chunk=256)
+    sb = wn.SlicedBackward(Vt, Ft, Q=Qt)
     sb.begin()
-    sb.points(768, 232, gt)   # the ragged last split first
-    sb.points(0, 768, gt)
+    sb.points(0, 256, gt)
+    sb.points(256, 512, gt)
+    sb.points(768, 232, gt)   # the ragged last tile
     D = sb.end()
     Dw = wn.wn_backward(Vt, Ft, gt, Q=Qt)
     torch.cuda.synchronize()
+    assert torch.equal(D, Dw)
     _, Dr = orc.grad(_f32(Vs), Fs, Q.astype(np.float64), gq.astype(np.float64))
     np.testing.assert_allclose(D.cpu().numpy(), Dr, rtol=1e-3, atol=1e-4 * np.abs(Dr).max())
-    np.testing.assert_allclose(D.cpu().numpy(), Dw.cpu().numpy(), rtol=1e-4, atol=1e-5 * np.abs(Dr).max())
     # argument errors, before any launch
     lib = L.load()
     p = ctypes.c_void_p
     s = p(torch.cuda.current_stream().cuda_stream)
-    need = lib.wn_workspace_size_backward(9, 4, 1000, 256)
+    need = wn.wn_workspace_size(L.WN_OP_BACKWARD, 9, 4, 1000)
     ws = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
     base = p(ws.data_ptr() + (-ws.data_ptr()) % 256)
     dV = torch.empty_like(Vt)
 
-    def call(p0, n, flags=0, chunk=256, wsb=need, dLdV=dV):
+    def call(p0, n, flags=0, wsb=need, dLdV=dV):
         return lib.wn_backward_range(p(Vt.data_ptr()), 9, p(Ft.data_ptr()), 4, None, p(Qt.data_ptr()), 1000,
-                                     p(gt.data_ptr()), chunk, p0, n, flags, p(dLdV.data_ptr()) if dLdV is not None
+                                     p(gt.data_ptr()), p0, n, flags, p(dLdV.data_ptr()) if dLdV is not None
                                      else None, None, base, wsb, s)
 
     assert call(0, 0, L.WN_BWD_BEGIN) == L.WN_OK
-    assert call(100, 256) == L.WN_ERR_INVALID_ARG          # p0 not on a split boundary
-    assert call(0, 300) == L.WN_ERR_INVALID_ARG            # n not whole splits and not the end
+    assert call(100, 256) == L.WN_ERR_INVALID_ARG          # p0 not on a tile boundary
+    assert call(0, 300) == L.WN_ERR_INVALID_ARG            # n not whole tiles and not the end
     assert call(768, 233) == L.WN_ERR_INVALID_ARG          # past the last point
+    assert call(-256, 256) == L.WN_ERR_INVALID_ARG
     assert call(0, 256, 4) == L.WN_ERR_INVALID_ARG         # unknown flag
     assert call(0, 0, L.WN_BWD_END, dLdV=None) == L.WN_ERR_INVALID_ARG
-    assert call(0, 256, chunk=-1) == L.WN_ERR_INVALID_ARG
     assert call(0, 256, wsb=need - 1) == L.WN_ERR_WORKSPACE
-    Q2 = torch.zeros((70000, 3), device="cuda")
-    g2 = torch.zeros(70000, device="cuda")
-    assert lib.wn_backward_range(p(Vt.data_ptr()), 9, p(Ft.data_ptr()), 4, None, p(Q2.data_ptr()), 70000,
-                                 p(g2.data_ptr()), 1, 0, 1, 0, None, None, base, need, s) == L.WN_ERR_INVALID_ARG
     torch.cuda.synchronize()

@@ -69,14 +69,20 @@ def test_smoothing_matches_oracle(dev, orc):
     g = wi.Grid((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0), (11, 9, 10))
     Vc, Fc = orc.cubify((rng.random(g.size) < 0.4).astype(np.uint8), g)
     c1 = wi.config1_icosphere()
-    for name, V, F, iters in (("cubified", Vc, Fc, 10), ("icosphere", c1.V, c1.F, 10), ("one step", Vc, Fc, 1),
-                              ("no steps", Vc, Fc, 0)):
-        V32 = np.asarray(V, np.float32)
-        S = wn.wn_laplacian_smooth(_cuda(V32), _cuda(np.asarray(F, np.int32)), 0.15, iters).cpu().numpy()
-        Sr = orc.laplacian_smooth(V32.astype(np.float64), F, 0.15, iters)
-        err = np.abs(S - Sr).max() / np.abs(Sr).max()
-        print(f"[smooth {name}] max err / max |v| = {err:.2e}", flush=True)
-        assert err <= 4e-7 * max(iters, 1)
+    for keep in (True, False):
+        for name, V, F, iters in (("cubified", Vc, Fc, 10), ("icosphere", c1.V, c1.F, 10), ("one step", Vc, Fc, 1),
+                                  ("no steps", Vc, Fc, 0)):
+            V32 = np.asarray(V, np.float32)
+            S = wn.wn_laplacian_smooth(_cuda(V32), _cuda(np.asarray(F, np.int32)), 0.15, iters,
+                                       keep_volume=keep).cpu().numpy()
+            Sr = orc.laplacian_smooth(V32.astype(np.float64), F, 0.15, iters, keep_volume=keep)
+            err = np.abs(S - Sr).max() / np.abs(Sr).max()
+            print(f"[smooth {name} keep_volume={keep}] max err / max |v| = {err:.2e}", flush=True)
+            # each step rounds the FP32 positions (and, with the rescale, the scaled ones)
+            assert err <= 4e-7 * max(iters, 1)
+            if keep and iters:
+                v0 = orc.enclosed_volume(V32.astype(np.float64), F)
+                assert orc.enclosed_volume(S.astype(np.float64), F) == pytest.approx(v0, rel=1e-5)
     # no faces: vertices unchanged; isolated vertex among faces stays
     S = wn.wn_laplacian_smooth(_cuda(V32), _cuda(np.zeros((0, 3), np.int32)), 0.15, 10)
     np.testing.assert_array_equal(S.cpu().numpy(), V32)
@@ -185,7 +191,10 @@ def test_eval_argument_errors(dev):
                                     s) == L.WN_ERR_INVALID_ARG
     assert lib.wn_sample_surface(p(A.data_ptr()), 4, None, 0, p(A.data_ptr()), 3, p(A.data_ptr()), p(d.data_ptr()),
                                  base, 1 << 20, s) == L.WN_ERR_INVALID_ARG
-    assert lib.wn_laplacian_smooth(p(A.data_ptr()), 4, None, 0, 0.15, 10, p(A.data_ptr()), base, 1 << 20,
+    assert lib.wn_laplacian_smooth(p(A.data_ptr()), 4, None, 0, 0.15, 10, 1, p(A.data_ptr()), base, 1 << 20,
+                                   s) == L.WN_ERR_INVALID_ARG
+    B = torch.zeros((4, 3), device="cuda")
+    assert lib.wn_laplacian_smooth(p(A.data_ptr()), 4, None, 0, 0.15, 10, 2, p(B.data_ptr()), base, 1 << 20,
                                    s) == L.WN_ERR_INVALID_ARG
     torch.cuda.synchronize()
 

@@ -72,17 +72,29 @@ def test_config1_full_grid(dev, orc):
     assert 0.05 < (Wr > 0.5).mean() < 0.5
 
 
-def test_config2_full_size_sampled(dev, orc):
-    """Non-watertight union (19 000 faces) at 128^3 in the benchmark's launch
-    configuration; the oracle checks 3000 seeded voxels plus the first and last."""
+def test_config2_full_size_strided(dev, orc):
+    """Non-watertight union (19 000 faces) at 128^3 on the path the benchmark times: the
+    triangle-strip order, after the autotuner has picked the launch configuration.  Every
+    16th voxel (131 072 of 2 097 152, a deterministic stride through every slab of the
+    grid) plus the last is held to the oracle: W within 1e-4 outside the guard band, the
+    guard band at most 1e-4 of the points, occupancy bit-identical off the band."""
+    import torch
+    import paper_2407_11272_amd as wn
     c = wi.config2_ellipsoid_union()
-    Wg, occ = _gpu_w(c.V, c.F, grid=c.grid, occupancy="threshold")
-    assert Wg.shape == (128 ** 3,)
-    rng = np.random.default_rng(100)
-    idx = np.unique(np.concatenate([rng.integers(0, len(Wg), 3000), [0, len(Wg) - 1]]))
-    Qall = orc.grid_points(c.grid)
-    _compare(orc, c.V, c.F, Qall[idx], Wg[idx], "C2-sampled", occ_g=occ[idx])
-    assert np.isfinite(Wg).all()
+    V, F = wn.as_mesh(torch.as_tensor(np.asarray(c.V, np.float32)), torch.as_tensor(c.F))
+    R = _strips_dev(c.F, len(c.V))
+    grid = wn.Grid.of(c.grid)
+    W = torch.empty(tuple(grid.n), dtype=torch.float32, device="cuda")
+    occ = torch.empty(tuple(grid.n), dtype=torch.uint8, device="cuda")
+    wn.wn_autotune("voxelize", [wn.MeshJob(V, F, grid, "threshold", W=W, occ=occ, strips=R)])
+    W, occ = wn.wn_voxelize_strips(V, F, R, grid=grid, occupancy="threshold")
+    Wg, og = W.cpu().numpy().reshape(-1), occ.cpu().numpy().reshape(-1)
+    assert Wg.shape == (128 ** 3,) and np.isfinite(Wg).all()
+    idx = np.unique(np.concatenate([np.arange(0, len(Wg), 16), [len(Wg) - 1]]))
+    assert len(idx) >= 131072
+    Q = orc.grid_points(c.grid)[idx]
+    Wr, guard = _compare(orc, c.V, c.F, Q, Wg[idx], "C2 every 16th voxel, strips", occ_g=og[idx])
+    assert guard.sum() <= 1e-4 * len(idx)
 
 
 def test_largest_served_request_sampled(dev, orc):
@@ -363,6 +375,36 @@ def test_bad_strip_records_are_reported(dev):
     W = wn.wn_voxelize_strips(Vt, Ft, torch.as_tensor(R).cuda(), grid=c.grid)
     assert wn.wn_get_device_error() == wn._lib.WN_ERR_BAD_INDEX
     assert torch.isfinite(W).all()
+
+
+def test_forged_strip_windows_are_reported(dev):
+    """A strip record that claims face f must complete F[f]: its vertex id and those of
+    the two records before it are F[f]'s ids in some order.  A window with an in-range
+    but wrong vertex id (a stale strip order, a hand-built stream) and a face flag on
+    record 0 are reported as bad indices, by the single-mesh and the batched packs; the
+    valid stream is not."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere(res=16)
+    Vt, Ft = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    R = wn.wn_build_strips(c.F, len(c.V))
+    face_rows = np.nonzero(R[:, 1] >= 0)[0]
+    i = int(face_rows[len(face_rows) // 2])
+    wrong = next(v for v in range(len(c.V)) if v not in set(c.F[R[i, 1]].tolist()))
+    bad_window = R.copy()
+    bad_window[i, 0] = wrong            # in range, but not a vertex of face R[i, 1]
+    bad_first = R.copy()
+    bad_first[0, 1] = R[i, 1]           # a face flag on record 0 (no window)
+    for name, stream, expect in (("valid", R, 0), ("wrong vertex", bad_window, wn._lib.WN_ERR_BAD_INDEX),
+                                 ("flag on record 0", bad_first, wn._lib.WN_ERR_BAD_INDEX)):
+        Rt = torch.as_tensor(stream).cuda()
+        W = wn.wn_voxelize_strips(Vt, Ft, Rt, grid=c.grid)
+        assert wn.wn_get_device_error() == expect, name
+        assert torch.isfinite(W).all()
+        job = wn.MeshJob(Vt, Ft, c.grid, strips=Rt).prepare()
+        wn.wn_voxelize_batched([job], graph=False)
+        assert wn.wn_get_device_error() == expect, name + " (batched)"
+        assert torch.isfinite(job.W).all()
 
 
 def test_adversarial_points_on_vertices_and_edges(dev, orc):

@@ -2,8 +2,13 @@
 
 Each request's W (and dL/dV for gradient requests) must be bit-identical to the same
 request served alone, and within 2e-6 of the plain one-mesh-per-launch path (whose
-face partition differs); one request is also held to the FP64 oracle (1e-4).
+face partition differs); one request is also held to the FP64 oracle (1e-4), and one
+gradient request of the served workload's large end (57 529 faces at 128^3) is held to
+values the oracle alone computed (tests/golden/served_grad_57529f_128.json).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -111,10 +116,10 @@ def test_budget_rejection_on_device(dev):
 
 def test_degenerate_requests_on_device(dev):
     """No faces, an empty grid, a one-voxel grid: every request completes; gradients
-    equal the sliced adjoint run directly with the request's split size."""
+    equal wn_backward run directly on the request's own dL/dW."""
     import torch
     import paper_2407_11272_amd as wn
-    from paper_2407_11272_amd.serve import ServeRequest, adjoint_chunk
+    from paper_2407_11272_amd.serve import ServeRequest
     c1 = wi.config1_icosphere()
     V = np.asarray(c1.V, np.float32)
     F = np.delete(np.asarray(c1.F, np.int32), np.arange(0, len(c1.F), 20), axis=0)  # open: rims carry gradient
@@ -134,10 +139,50 @@ def test_degenerate_requests_on_device(dev):
     for r, o in zip(reqs[3:], out[3:]):
         Vd, Fd = wn.as_mesh(torch.as_tensor(r.V), torch.as_tensor(r.F))
         loss, dLdW = wn.wn_sigmoid_mse(o.W.reshape(-1), torch.as_tensor(r.target).cuda(), r.tau, r.k)
-        sb = wn.SlicedBackward(Vd, Fd, grid=wn.Grid.of(r.grid), chunk=adjoint_chunk(len(r.F), r.points))
-        sb.begin()
-        sb.points(0, r.points, dLdW)
-        D = sb.end()
+        D = wn.wn_backward(Vd, Fd, dLdW, grid=wn.Grid.of(r.grid))
         torch.cuda.synchronize()
         assert torch.equal(D, o.dLdV) and torch.equal(loss, o.loss)
     assert float(out[4].dLdV.abs().max()) > 0.0
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "served_grad_57529f_128.json")
+
+
+def test_large_served_gradient_request_against_the_oracle(dev):
+    """A gradient request of the served workload's large end (57 529 faces at 128^3,
+    sigmoid k = 50 MSE), served among smaller requests in units of the sliced adjoint,
+    against values written by the oracle alone (tests/golden/make_served_grad.py): W at
+    512 seeded voxels (1e-4 off the guard band), the loss (1e-4 relative), and dL/dT of 64
+    seeded faces (bar (i) of the adjoint: |d|_inf <= 1e-3 |ref|_inf, and 1e-3 relative
+    where |ref| > 1e-2 |ref|_inf).  The served loss and dL/dW come from the GPU's own W."""
+    import torch
+    from paper_2407_11272_amd.serve import GpuExecutor, ServeRequest, Server
+    g = json.load(open(GOLDEN))
+    rq = g["request"]
+    w = wi.configs.Request(0, 0.0, rq["faces_requested"], rq["res"], True, rq["mesh_seed"]).build()
+    assert len(w.F) == g["n_faces"] and len(w.V) == g["n_vertices"]
+    big = ServeRequest(100, w.V.astype(np.float32), w.F.astype(np.int32), w.grid, 0.0, w.occ_mode, w.target)
+    others = _trace(6, 200.0)
+    srv = Server(GpuExecutor(keep_dLdT=True), slots=4, quantum_pairs=1e10)
+    out = srv.run_trace([big] + others)
+    torch.cuda.synchronize()
+    res = {o.rid: o for o in out}[100]
+    assert np.isfinite(res.done) and not res.rejected
+    adjoint_units = sum(1 for *_, a in srv.step_log if a)
+    print(f"[served golden] steps={srv.steps} adjoint units={adjoint_units} loss={float(res.loss.item()):.7f} "
+          f"oracle {g['loss']:.7f}", flush=True)
+    assert adjoint_units > 1   # the adjoint really was served in slices
+    vox = np.asarray(g["voxels"])
+    Wg = res.W.reshape(-1).cpu().numpy()[vox].astype(np.float64)
+    ok = ~np.asarray(g["guard"])
+    assert np.abs(Wg - np.asarray(g["W"]))[ok].max() <= 1e-4
+    assert float(res.loss.item()) == pytest.approx(g["loss"], rel=1e-4)
+    Tg = res.dLdT.reshape(len(w.F), 9).cpu().numpy()[np.asarray(g["faces"])].astype(np.float64).reshape(-1)
+    Tr = np.asarray(g["dLdT"], np.float64).reshape(-1)
+    scale = np.abs(Tr).max()
+    d = np.abs(Tg - Tr)
+    big_ = np.abs(Tr) > 1e-2 * scale
+    print(f"[served golden] |dL/dT|inf={scale:.3e} max abs err={d.max():.3e} "
+          f"max rel (big)={(d[big_] / np.abs(Tr[big_])).max():.3e}", flush=True)
+    assert d.max() <= 1e-3 * scale
+    assert np.all(d[big_] <= 1e-3 * np.abs(Tr[big_]))

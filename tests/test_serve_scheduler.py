@@ -11,8 +11,8 @@ under every policy, and that a long request is not starved by a stream of short 
 import numpy as np
 import pytest
 
-from paper_2407_11272_amd.serve import (ADJOINT_COST, ADJOINT_MAX_CHUNK, Server, ServeRequest, adjoint_chunk,
-                                        footprint_bytes, latency_stats)
+from paper_2407_11272_amd.serve import (ADJOINT_COST, Server, ServeRequest, adjoint_unit, footprint_bytes,
+                                        latency_stats)
 from wn_inputs import Grid
 
 
@@ -42,11 +42,11 @@ class FakeExecutor:
     def start(self, t0):
         pass
 
-    def admit(self, req, adj_chunk=0):
+    def admit(self, req):
         self.clock.t += self.upload_s   # host time of the upload
         self.slices[req.rid] = []
         self.adj[req.rid] = []
-        return {"rid": req.rid, "chunk": adj_chunk}
+        return {"rid": req.rid}
 
     def wait_inflight(self, keep):
         while len(self.inflight) > max(0, keep):
@@ -125,13 +125,14 @@ def test_every_request_completes_and_units_partition_the_grid(policy):
         if not r.wants_grad:
             assert units == []
             continue
-        # adjoint units: whole splits in order, after the forward, the last one flagged
-        chunk = adjoint_chunk(len(r.F), r.points)
+        # adjoint units: consecutive whole rounds over the adjoint's splits, in order,
+        # after the forward, the last one flagged
+        unit = adjoint_unit(len(r.F), r.points)
         pos = 0
         for i, (p0, n, last, k) in enumerate(units):
             assert p0 == pos and n > 0 and k >= last_fwd_step
             assert last == (i == len(units) - 1)
-            assert n % chunk == 0 or p0 + n == r.points
+            assert n % unit == 0 or p0 + n == r.points
             pos += n
         assert pos == r.points
     for r in out:
@@ -140,12 +141,18 @@ def test_every_request_completes_and_units_partition_the_grid(policy):
     assert st["count"] == 40 and st["p99_ms"] >= st["p50_ms"] > 0
 
 
-def test_adjoint_chunk_depends_only_on_the_request():
-    # small requests use the library's split size (many splits, to fill the GPU alone);
-    # large ones at most ADJOINT_MAX_CHUNK points per split
-    assert adjoint_chunk(1000, 64 ** 3) < ADJOINT_MAX_CHUNK
-    assert adjoint_chunk(100000, 256 ** 3) == ADJOINT_MAX_CHUNK
-    assert adjoint_chunk(5000, 64 ** 3) == adjoint_chunk(5000, 64 ** 3)
+def test_adjoint_unit_depends_only_on_the_request():
+    # one round of 256-point tiles over the adjoint's splits: many splits for few faces
+    # (to fill the GPU alone), few for many faces (their running sums stay within 256 MiB)
+    from paper_2407_11272_amd import _lib as L
+    lib = L.load()
+    assert adjoint_unit(5000, 64 ** 3) == adjoint_unit(5000, 64 ** 3)
+    assert adjoint_unit(1000, 64 ** 3) == 256 * lib.wn_backward_splits(1000, 64 ** 3)
+    big = lib.wn_backward_splits(100000, 256 ** 3)
+    assert 1 <= big and big * 72 * 100000 <= 256 << 20
+    assert lib.wn_backward_splits(1000, 64 ** 3) > big
+    # the largest served gradient request's adjoint workspace stays well under 1 GB
+    assert lib.wn_workspace_size(L.WN_OP_BACKWARD, 60000, 100000, 256 ** 3) < 400 << 20
 
 
 def test_footprint_admission_and_rejection():
@@ -161,9 +168,10 @@ def test_footprint_admission_and_rejection():
 
 
 def test_gradient_footprint_counts_the_adjoint_splits():
+    from paper_2407_11272_amd import _lib as L
     r = _req(0, 100000, 256, 0.0, grad=True)
-    splits = -(-r.points // adjoint_chunk(len(r.F), r.points))
-    assert footprint_bytes(r, 10 ** 9) > 36 * len(r.F) * splits
+    splits = L.load().wn_backward_splits(len(r.F), r.points)
+    assert footprint_bytes(r, 10 ** 9) > 72 * len(r.F) * splits
     assert footprint_bytes(r, 10 ** 9) > footprint_bytes(_req(0, 100000, 256, 0.0), 10 ** 9)
 
 
@@ -266,8 +274,9 @@ def test_degenerate_requests_complete(policy):
             assert units and units[-1][2] and sum(n for _, n, _, _ in units) == r.points
 
 
-def test_adjoint_split_count_stays_within_the_library_limit():
-    # a huge grid: the split size grows so that there are at most 65535 splits
+def test_adjoint_unit_of_a_huge_grid():
+    # a huge grid: the split count is bounded (at most 4096, at most 256 MiB of running
+    # sums), so a unit granule stays a few thousand tiles at most
     P = 1024 ** 3
-    c = adjoint_chunk(100000, P)
-    assert c % 256 == 0 and -(-P // c) <= 65535
+    u = adjoint_unit(100000, P)
+    assert u % 256 == 0 and 256 <= u <= 4096 * 256
