@@ -1,19 +1,24 @@
 """Benchmark of the winding-number voxelization path on one MI355X.
 
-Headline step (one pass of the forward path over one batch of input): pack the
-19 000-face non-watertight ellipsoid union, evaluate the winding number at every
-centre of the 128^3 grid, reduce, and map to hard occupancy -- all in the HIP
-library, inputs already resident in HBM.  ``value`` = point-triangle evaluations
-per second over the timed steps.
+Headline step (one pass of the hot path over one batch of input): the batched workload
+-- 64 seeded ellipsoid-union meshes of 500 to 50 000 faces, each with its own 32^3,
+64^3 or 128^3 grid -- voxelized in ONE persistent, graph-captured launch (pack the
+meshes' strip-order vertex records, evaluate the winding number at every voxel centre
+of every grid, reduce, map to hard occupancy), all in the HIP library, inputs resident
+in HBM.  ``value`` = point-triangle evaluations per second over the timed steps; the
+same meshes launched one per call (the plain kernel) are timed beside it.
 
-Extra rows measured in the same run (reported under "rows"):
+Rows measured in the same run (``rows``; a compact ``summary`` closes the line):
+  * forward_c2: the 19 000-face non-watertight union at 128^3, one mesh per launch;
   * adjoint: forward + sigmoid-MSE loss + wn_backward on the 5120-face icosphere at 64^3;
-  * batched: 64 meshes of uneven size in one persistent launch;
   * served: continuous batching of a seeded Poisson trace, p50/p99 latency vs the
-    plain one-mesh-per-launch loop (see ``--served``).
+    plain one-mesh-per-launch loop at several offered loads;
+  * naive (Eq. 4), eval (Section 3's evaluation chain), morph (Section 2.4), flip
+    (Algorithm 2).
 
 The CPU baseline is the FP64 oracle timed on the host's cores over a bounded,
-deterministic subsample of the same workload.
+deterministic per-mesh subsample of the same batch (and, for context, the other
+workloads and a one-thread run).
 """
 from __future__ import annotations
 
@@ -36,7 +41,9 @@ PEAK_HBM = 8.0e12
 
 
 # Sources that define each profiled kernel (its code and everything it inlines).
-KERNEL_SOURCES = {"k_wn_fwd": ("wn_internal.hpp", "wn_fwd.hip")}
+KERNEL_SOURCES = {"k_wn_fwd": ("wn_internal.hpp", "wn_fwd.hip"),
+                  "k_batched_persistent": ("wn_internal.hpp", "wn_batched.hip"),
+                  "k_wn_bwd": ("wn_internal.hpp", "wn_bwd.hip")}
 
 
 def source_hash(kernel: str = "k_wn_fwd") -> str:
@@ -47,20 +54,37 @@ def source_hash(kernel: str = "k_wn_fwd") -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
-    on the current kernel sources (else None)."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+def load_counters(kernel: str, workload: str):
+    """Figures from committed rocprofv3 counter runs of a kernel on a workload (HBM bytes
+    per launch, FP32 FLOPs and VALU instructions per pair), if they were taken on the
+    current kernel sources (else {})."""
+    p = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(p):
-        return None
+        return {}
     try:
-        d = json.load(open(p))
-        e = d[kernel][workload]
+        e = json.load(open(p))[kernel][workload]
         if e.get("source_hash") != source_hash(kernel):
-            return None
-        return float(e["bytes_per_launch"])
+            return {}
+        return e
     except Exception:
-        return None
+        return {}
+
+
+def roofline(kernel: str, workload: str, pairs: float, launch_s: float, flop_per_pair: int) -> dict:
+    """The FP32-ALU roofline of one launch: algorithmic FLOPs (a fixed count per pair) over
+    the measured launch time; with committed counters also the hardware fraction
+    (counted FP32 FLOPs over the same time) and the HBM bytes per launch."""
+    achieved = pairs * flop_per_pair / launch_s
+    c = load_counters(kernel, workload)
+    out = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+           "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+           "traffic": c.get("bytes_per_launch"), "flop_per_pair": flop_per_pair, "launch_ms": launch_s * 1e3}
+    if c.get("hw_flop_per_pair"):
+        out["hw_flop_per_pair"] = c["hw_flop_per_pair"]
+        out["hw_frac"] = pairs * c["hw_flop_per_pair"] / launch_s / PEAK_FP32
+    if c.get("valu_per_pair"):
+        out["valu_per_pair"] = c["valu_per_pair"]
+    return out
 
 
 def time_steps(fn, steps, warmup, stream):
@@ -81,9 +105,10 @@ def time_steps(fn, steps, warmup, stream):
 
 
 def bench_forward(steps, warmup, autotune=True, compare=True):
-    """Headline: the forward step with the mesh's triangle-strip record stream (built on
-    the host from F before timing, like the mesh itself); also the same step with the
-    default three records per face."""
+    """The plain forward on the 19 000-face non-watertight union at 128^3 (one mesh per
+    launch) with the mesh's triangle-strip record stream (built on the host from F
+    before timing, like the mesh itself); also the same step with the default three
+    records per face."""
     import torch
     import paper_2407_11272_amd as wn
     import wn_inputs as wi
@@ -107,17 +132,25 @@ def bench_forward(steps, warmup, autotune=True, compare=True):
     def step_plain():
         wn.wn_voxelize(V, F, grid=grid, W=W, occupancy="threshold", occ=occ)
 
-    dev_s, wall_s = time_steps(step, steps, warmup, stream)
+    dev_s, _ = time_steps(step, steps, warmup, stream)
     pairs = grid.size * len(c.F)
-    extra = {
+    out = {
+        "workload": c.name,
+        "faces": int(len(c.F)),
+        "points": int(grid.size),
+        "pairs_per_launch": int(pairs),
+        "ms": dev_s / steps * 1e3,
+        "pairs_per_s": pairs * steps / dev_s,
         "strip_records_per_face": len(Rh) / len(c.F),
         "strip_build_ms_host": strip_ms,
         "autotune": tune["chosen"] if tune else None,
+        "roofline": roofline("k_wn_fwd", "c2", pairs, dev_s / steps, FLOP_FWD),
     }
     if compare:
-        plain_s, _ = time_steps(step_plain, max(2, steps // 2), 1, stream)
-        extra["three_records_per_face_pairs_per_s"] = pairs * max(2, steps // 2) / plain_s
-    return c, pairs, dev_s, wall_s, extra
+        n = max(2, steps // 2)
+        plain_s, _ = time_steps(step_plain, n, 1, stream)
+        out["three_records_per_face_pairs_per_s"] = pairs * n / plain_s
+    return c, out
 
 
 def bench_adjoint(steps, warmup):
@@ -159,8 +192,8 @@ def bench_adjoint(steps, warmup):
     }
 
 
-def bench_batched(reps: int, autotune: bool):
-    """64 meshes of uneven size in one persistent launch vs one mesh per launch."""
+def batch_jobs():
+    """The 64 meshes of the batched workload on the device, each with its strip order."""
     import torch
     import paper_2407_11272_amd as wn
     import wn_inputs as wi
@@ -170,32 +203,46 @@ def bench_batched(reps: int, autotune: bool):
         V, F = wn.as_mesh(torch.as_tensor(w.V), torch.as_tensor(w.F))
         R = torch.as_tensor(wn.wn_build_strips(w.F, len(w.V))).cuda()
         jobs.append(wn.MeshJob(V, F, wn.Grid.of(w.grid), "threshold", strips=R).prepare())
+    return ws, jobs
+
+
+def bench_batched(steps: int, warmup: int, autotune: bool, compare: bool = True):
+    """The headline: 64 meshes of uneven size in one persistent, graph-captured launch;
+    beside it the same meshes launched one per call (the plain kernel, same strip order)."""
+    import torch
+    import paper_2407_11272_amd as wn
+    ws, jobs = batch_jobs()
     pairs = sum(int(j.grid.size) * int(j.F.shape[0]) for j in jobs)
     report = wn.wn_autotune("batched", jobs) if autotune else None
     stream = torch.cuda.current_stream()
-    b_s, _ = time_steps(lambda: wn.wn_voxelize_batched(jobs), reps, 1, stream)
-
-    def plain():
-        for j in jobs:
-            wn.wn_voxelize_strips(j.V, j.F, j.strips, grid=j.grid, W=j.W, occupancy="threshold", occ=j.occ)
-
-    p_s, _ = time_steps(plain, 1, 1, stream)
-    rate = pairs * reps / b_s
-    return {
-        "workload": "64 ellipsoid-union meshes, 500-50k faces log-uniform, grids 32^3/64^3/128^3, strip order",
-        "pairs_per_launch": pairs,
-        "batched_ms": b_s / reps * 1e3,
-        "batched_pairs_per_s": rate,
-        "batched_frac_fp32_peak": rate * FLOP_FWD / PEAK_FP32,
-        "plain_one_mesh_per_launch_ms": p_s * 1e3,
-        "plain_pairs_per_s": pairs / p_s,
-        "batched_over_plain": (pairs * reps / b_s) / (pairs / p_s),
+    b_s, wall_s = time_steps(lambda: wn.wn_voxelize_batched(jobs), steps, warmup, stream)
+    out = {
+        "workload": "ellipsoid-union-batch-64meshes-500-50000f-32-128cube",
+        "meshes": len(jobs),
+        "faces_total": int(sum(int(j.F.shape[0]) for j in jobs)),
+        "points_total": int(sum(int(j.grid.size) for j in jobs)),
+        "pairs_per_launch": int(pairs),
+        "grids": {str(r): sum(1 for j in jobs if j.grid.n[0] == r) for r in (32, 64, 128)},
+        "ms": b_s / steps * 1e3,
+        "wall_ms": wall_s / steps * 1e3,
+        "pairs_per_s": pairs * steps / b_s,
         "autotune": report["chosen"] if report else None,
+        "autotune_identical": report["identical"] if report else None,
     }
+    if compare:
+        def plain():
+            for j in jobs:
+                wn.wn_voxelize_strips(j.V, j.F, j.strips, grid=j.grid, W=j.W, occupancy="threshold", occ=j.occ)
+
+        p_s, _ = time_steps(plain, 2, 1, stream)
+        out["plain_one_mesh_per_launch_ms"] = p_s / 2 * 1e3
+        out["plain_pairs_per_s"] = pairs * 2 / p_s
+        out["batched_over_plain"] = out["pairs_per_s"] / out["plain_pairs_per_s"]
+    return ws, pairs, b_s, wall_s, out
 
 
 def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s: float, warmup_frac: float = 0.0,
-                 policy: str = "edf", step_pairs: float | None = None):
+                 policy: str = "edf", step_pairs: float | None = None, burst_requests: int | None = None):
     """Poisson trace through the continuous-batching server and through the plain FIFO
     one-mesh-per-launch loop, at each offered load in ``loads``; p50/p99 latency and
     throughput of both.  A load puts the offered GPU time at that fraction of the wall
@@ -261,11 +308,13 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
         print(f"# served load {load}: p50 {s_stats['p50_ms']:.0f} / {p_stats['p50_ms']:.0f} ms, "
               f"p99 {s_stats['p99_ms']:.0f} / {p_stats['p99_ms']:.0f} ms (served / plain)", file=sys.stderr,
               flush=True)
-    # saturation: every request at t = 0, so the makespan measures throughput alone
+    # saturation: every request (the first burst_requests of the trace) at t = 0, so the
+    # makespan measures throughput alone
+    bb = built[:burst_requests] if burst_requests else built
     reqs = [ServeRequest(r.rid, w.V.astype(np.float32), w.F.astype(np.int32), w.grid, 0.0, w.occ_mode, w.target)
-            for r, w in built]
-    fwd_pairs = sum(int(np.prod(w.grid.n)) * len(w.F) for r, w in built)
-    adj_pairs = sum(int(np.prod(w.grid.n)) * len(w.F) for r, w in built if r.wants_grad)
+            for r, w in bb]
+    fwd_pairs = sum(int(np.prod(w.grid.n)) * len(w.F) for r, w in bb)
+    adj_pairs = sum(int(np.prod(w.grid.n)) * len(w.F) for r, w in bb if r.wants_grad)
     flops = fwd_pairs * FLOP_FWD + adj_pairs * FLOP_BWD
 
     def burst(out):
@@ -284,8 +333,8 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
     print(f"# served burst: {b_served['throughput_pairs_per_s']:.3g} / {b_plain['throughput_pairs_per_s']:.3g} "
           f"pairs/s (served / plain)", file=sys.stderr, flush=True)
     return {
-        "burst": {"what": "every request at t = 0; pairs count forward and adjoint pairs, the fraction weights "
-                          f"them by {FLOP_FWD} and {FLOP_BWD} FLOP",
+        "burst": {"what": f"the first {len(bb)} requests at t = 0; pairs count forward and adjoint pairs, the "
+                          f"fraction weights them by {FLOP_FWD} and {FLOP_BWD} FLOP",
                   "served": b_served, "plain_fifo": b_plain},
         "workload": f"{n_requests} Poisson requests, 1k-100k faces log-uniform, grids 64^3/128^3/256^3, "
                     f"30% with dL/dV (sigmoid-MSE), offered load swept, first {warmup_frac:.0%} not counted",
@@ -377,10 +426,14 @@ def bench_morph(iters: int):
     return out
 
 
-def bench_eval(reps: int):
+def bench_eval(reps: int, repeats: int = 3):
     """The evaluation chain of Section 3 on the 19 000-face union at 128^3: strip-order
-    forward with threshold occupancy, cube surface, 10 smoothing steps (lambda 0.15),
-    20 000 samples of the result and of the mesh, Chamfer and Hausdorff."""
+    forward with threshold occupancy, cube surface, 10 smoothing steps (lambda 0.15, the
+    enclosed volume kept), 20 000 samples of the result and of the mesh, Chamfer and
+    Hausdorff; and marching cubes of W in place of the cube surface.  The metrics are
+    the mean and standard deviation over ``repeats`` independent sample streams (the
+    paper reports three repeats); stage times are means over ``reps`` passes."""
+    import numpy as np
     import torch
     import paper_2407_11272_amd as wn
     import wn_inputs as wi
@@ -388,7 +441,6 @@ def bench_eval(reps: int):
     V, F = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
     R = torch.as_tensor(wn.wn_build_strips(c.F, len(c.V))).cuda()
     grid = wn.Grid.of(c.grid)
-    ua, ub = (torch.as_tensor(u).cuda() for u in wi.evaluation_samples())
     stages = {}
 
     def timed(name, fn):
@@ -400,7 +452,10 @@ def bench_eval(reps: int):
         stages.setdefault(name, []).append(ev0.elapsed_time(ev1))
         return out
 
-    for _ in range(reps + 1):
+    cube, march = [], []
+    for it in range(max(reps, repeats) + 1):
+        rep = max(0, it - 1) % repeats
+        ua, ub = (torch.as_tensor(u).cuda() for u in wi.evaluation_samples(repeat=rep))
         W, occ = timed("voxelize", lambda: wn.wn_voxelize_strips(V, F, R, grid=grid, occupancy="threshold"))
         Vc, Fc = timed("cubify", lambda: wn.wn_cubify(occ, grid))
         Vs = timed("smooth", lambda: wn.wn_laplacian_smooth(Vc, Fc, 0.15, 10))
@@ -413,17 +468,21 @@ def bench_eval(reps: int):
         Vms = timed("smooth_marching", lambda: wn.wn_laplacian_smooth(Vm, Fm, 0.15, 10))
         Pm, _ = timed("sample_marching", lambda: wn.wn_sample_surface(Vms, Fm, ua))
         mm = timed("metrics_marching", lambda: wn.wn_chamfer_hausdorff(Pm, Pb))
-    ms = {k: sum(v[1:]) / reps for k, v in stages.items()}  # first pass is a warm-up
-    m, mm = m.cpu().numpy(), mm.cpu().numpy()
-    cube = ("voxelize", "cubify", "smooth", "sample", "sample_ref", "metrics")
-    return {"workload": "ellipsoid-union-19000f-128cube: occupancy -> cube surface -> 10 x Laplacian(0.15) "
-                        "-> 2 x 20000 samples -> Chamfer/Hausdorff; and marching cubes of W in place of the "
+        if 1 <= it <= repeats:   # the first pass is a warm-up
+            cube.append(m.cpu().numpy())
+            march.append(mm.cpu().numpy())
+    ms = {k: sum(v[1:]) / (len(v) - 1) for k, v in stages.items()}
+    cube, march = np.array(cube), np.array(march)
+    stat = lambda a: {"mean": float(a.mean()), "std": float(a.std(ddof=1)) if len(a) > 1 else 0.0}  # noqa: E731
+    cube_keys = ("voxelize", "cubify", "smooth", "sample", "sample_ref", "metrics")
+    march_keys = ("voxelize", "marching", "smooth_marching", "sample_marching", "sample_ref", "metrics_marching")
+    return {"workload": "ellipsoid-union-19000f-128cube: occupancy -> cube surface -> 10 x Laplacian(0.15, volume "
+                        "kept) -> 2 x 20000 samples -> Chamfer/Hausdorff; and marching cubes of W in place of the "
                         "cube surface",
-            "stage_ms": ms, "total_ms": sum(ms[k] for k in cube), "cube_faces": int(Fc.shape[0]),
-            "chamfer": float(m[0]), "hausdorff": float(m[1]),
-            "marching_faces": int(Fm.shape[0]), "marching_total_ms": sum(ms[k] for k in ("voxelize", "marching", "smooth_marching", "sample_marching",
-                                                       "sample_ref", "metrics_marching")),
-            "chamfer_marching": float(mm[0]), "hausdorff_marching": float(mm[1])}
+            "repeats": repeats, "stage_ms": ms, "total_ms": sum(ms[k] for k in cube_keys),
+            "cube_faces": int(Fc.shape[0]), "chamfer": stat(cube[:, 0]), "hausdorff": stat(cube[:, 1]),
+            "marching_faces": int(Fm.shape[0]), "marching_total_ms": sum(ms[k] for k in march_keys),
+            "chamfer_marching": stat(march[:, 0]), "hausdorff_marching": stat(march[:, 1])}
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
@@ -439,38 +498,69 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}
 
 
-def cpu_baseline(c, budget_s: float = 15.0):
-    """FP64 oracle on a deterministic stride subsample of the workload's voxels."""
-    import numpy as np
-    import oracle
-    Q = oracle.grid_points(c.grid)
-    threads = oracle.max_threads()
-    # calibrate on a small slice, then size the sample to the time budget
-    probe = Q[:: max(1, len(Q) // 512)]
-    t0 = time.perf_counter()
-    oracle.winding(c.V, c.F, probe)
-    rate = len(probe) * len(c.F) / max(time.perf_counter() - t0, 1e-6)
-    n_pts = int(min(len(Q), max(1024, budget_s * rate / len(c.F))))
-    stride = max(1, len(Q) // n_pts)
-    sample = Q[::stride]
-    t0 = time.perf_counter()
-    oracle.winding(c.V, c.F, sample)
-    dt = time.perf_counter() - t0
-    cpu = "unknown"
+def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return "unknown"
+
+
+def cpu_baseline(batch, budget_s: float = 15.0):
+    """The FP64 oracle (as it stands) on a bounded, deterministic subsample of the
+    headline batch: the same number of seeded voxels of every mesh (pairs counted with
+    each mesh's own face count), sized to about ``budget_s`` on all host threads; then a
+    smaller sample on one thread, and the other workloads' rates for context (the small
+    plain forward and the differentiable mesh in full, the 128^3 union on a stride)."""
+    import numpy as np
+    import oracle
+    import wn_inputs as wi
+    threads = oracle.max_threads()
+
+    def run(per_mesh, nthreads):
+        rng = np.random.default_rng(17)
+        pairs, t = 0, 0.0
+        for w in batch:
+            Q = oracle.grid_points(w.grid)
+            idx = np.sort(rng.choice(len(Q), min(per_mesh, len(Q)), replace=False))
+            t0 = time.perf_counter()
+            oracle.winding(w.V, w.F, Q[idx], threads=nthreads)
+            t += time.perf_counter() - t0
+            pairs += len(idx) * len(w.F)
+        return pairs, t
+
+    # calibrate on a small sample, then size the sample to the time budget
+    p0, t0 = run(64, threads)
+    per_mesh = int(max(256, min(65536, 64 * budget_s / max(t0, 1e-3))))
+    pairs, dt = run(per_mesh, threads)
+    p1, t1 = run(max(32, per_mesh // (4 * max(1, threads))), 1)
+    # (the thread count is passed explicitly: the one-thread run set the runtime's default)
+    context = {}
+    c1 = wi.config1_icosphere()
+    tt = time.perf_counter()
+    oracle.winding(c1.V, c1.F, oracle.grid_points(c1.grid), threads=threads)
+    context["plain_32cube_full"] = c1.pairs / (time.perf_counter() - tt)
+    c3 = wi.config3_differentiable()
+    tt = time.perf_counter()
+    oracle.winding(c3.V, c3.F, oracle.grid_points(c3.grid), threads=threads)
+    context["differentiable_64cube_full"] = c3.pairs / (time.perf_counter() - tt)
+    c2 = wi.config2_ellipsoid_union()
+    Q2 = oracle.grid_points(c2.grid)[::64]
+    tt = time.perf_counter()
+    oracle.winding(c2.V, c2.F, Q2, threads=threads)
+    context["union_128cube_every_64th_voxel"] = len(Q2) * len(c2.F) / (time.perf_counter() - tt)
     return {
-        "value": len(sample) * len(c.F) / dt,
+        "value": pairs / dt,
         "unit": UNIT,
         "cores": threads,
         "kind": "oracle",
-        "sample": f"every {stride}th voxel of the 128^3 grid ({len(sample)} points x {len(c.F)} faces, "
-                  f"{dt:.1f} s, FP64, {cpu})",
+        "sample": f"{per_mesh} seeded voxels of each of the {len(batch)} meshes of the batch ({pairs:.3g} pairs, "
+                  f"{dt:.1f} s, FP64, {_cpu_model()})",
+        "value_1thread": p1 / t1,
+        "sample_1thread": f"{max(32, per_mesh // (4 * max(1, threads)))} voxels per mesh, {t1:.1f} s on one thread",
+        "other_workloads_pairs_per_s": context,
     }
 
 
@@ -483,9 +573,9 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="headline step only")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=64)
-    ap.add_argument("--rows", default="adjoint,batched,served,naive,flip,morph,eval",
-                    help="comma list of extra rows to measure (adjoint, batched, served, naive, flip, morph, eval)")
+    ap.add_argument("--served-requests", type=int, default=150)
+    ap.add_argument("--rows", default="forward,adjoint,served,naive,flip,morph,eval",
+                    help="comma list of extra rows (forward, adjoint, served, naive, flip, morph, eval)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration for profiling runs)")
     ap.add_argument("--served-loads", default="0.5,0.8,0.95",
@@ -494,10 +584,12 @@ def main():
                     help="scheduler policy of the served row (earliest deadline first, or shares)")
     ap.add_argument("--served-step-pairs", type=float, default=None,
                     help="pairs of work per scheduler step (default: the server's)")
-    ap.add_argument("--served-warmup", type=float, default=0.0,
+    ap.add_argument("--served-warmup", type=float, default=0.2,
                     help="fraction of the served requests (earliest arrivals) left out of the statistics")
+    ap.add_argument("--served-burst-requests", type=int, default=64,
+                    help="requests of the saturated (all at t = 0) served run")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the three-records-per-face comparison launches (profiling runs)")
+                    help="skip the one-mesh-per-launch and three-records-per-face comparison launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported (the path would shard by voxel "
@@ -511,22 +603,18 @@ def main():
     import paper_2407_11272_amd as wn
     wn.wn_version()
     calib = copy_calibration() if args.copy_calibration else None
-    print(f"# bench: forward, {args.steps} steps after {args.warmup} warm-up", file=sys.stderr, flush=True)
-    c, pairs, dev_s, wall_s, fwd_extra = bench_forward(args.steps, args.warmup, not args.no_autotune,
-                                                       not args.no_compare)
-    ms = dev_s / args.steps * 1e3
-    value = pairs * args.steps / dev_s
+    print(f"# bench: batched headline, {args.steps} steps after {args.warmup} warm-up", file=sys.stderr, flush=True)
+    batch, pairs, dev_s, wall_s, head = bench_batched(args.steps, args.warmup, not args.no_autotune,
+                                                      not args.no_compare)
     launch_s = dev_s / args.steps
-    achieved = pairs * FLOP_FWD / launch_s
-    traffic = load_traffic("k_wn_fwd", "c2")
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": pairs * args.steps / dev_s,
         "unit": UNIT,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": launch_s * 1e3,
         "wall_ms_per_step": wall_s / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -534,15 +622,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": c.name,
-            "faces": int(len(c.F)),
-            "vertices": int(len(c.V)),
-            "grid": list(c.grid.n),
-            "points": int(c.grid.size),
-            "pairs_per_step": int(pairs),
+            **head,
             "occupancy": "threshold 0.5",
             "face_order": "triangle strips (host-built from F, resident in HBM)",
-            **fwd_extra,
+            "launch": "one persistent, graph-captured launch for all meshes",
         },
         "paper_context": {
             "kind": "context, not a target: other hardware and precision",
@@ -551,32 +634,21 @@ def main():
             "derived_as": "res^3 x faces / time of the paper's own method at 128^3 (appendix table), "
                           "over its meshes",
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_wn_fwd",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP32 / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32,
-            "traffic": traffic,
-            "flop_per_pair": FLOP_FWD,
-            "launch_ms": launch_s * 1e3,
-        },
+        "roofline": roofline("k_batched_persistent", "c4", pairs, launch_s, FLOP_FWD),
     }
     want = set() if args.no_rows else {r.strip() for r in args.rows.split(",") if r.strip()}
     rows = {}
+    if "forward" in want:
+        print("# bench: forward row (one mesh per launch)", file=sys.stderr, flush=True)
+        _, rows["forward_c2"] = bench_forward(max(2, args.steps // 2), 1, not args.no_autotune, not args.no_compare)
     if "adjoint" in want or "served" in want:
         print("# bench: adjoint row", file=sys.stderr, flush=True)
         rows["adjoint"] = bench_adjoint(max(2, args.steps // 2), 1)
-    if "batched" in want or "served" in want:
-        print("# bench: batched row", file=sys.stderr, flush=True)
-        rows["batched"] = bench_batched(3, not args.no_autotune)
     if "served" in want and args.served_requests > 0:
         print("# bench: served row", file=sys.stderr, flush=True)
         rows["served"] = bench_served(args.served_requests, [float(x) for x in args.served_loads.split(",")],
-                                      rows["batched"]["batched_pairs_per_s"],
-                                      rows["adjoint"]["adjoint_pairs_per_s"], args.served_warmup,
-                                      args.served_policy, args.served_step_pairs)
+                                      head["pairs_per_s"], rows["adjoint"]["adjoint_pairs_per_s"], args.served_warmup,
+                                      args.served_policy, args.served_step_pairs, args.served_burst_requests)
     if "naive" in want:
         print("# bench: naive row", file=sys.stderr, flush=True)
         rows["naive"] = bench_naive(3, not args.no_autotune)
@@ -595,8 +667,39 @@ def main():
         out["copy_calibration"] = calib
     if not args.no_cpu_baseline:
         print("# bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)
+    out["summary"] = summary(out)
     print(json.dumps(out), flush=True)
+
+
+def summary(out) -> dict:
+    """The line's key figures in a few hundred bytes (its last field)."""
+    r = out.get("rows", {})
+    s = {"batched_c4": {"pairs_per_s": out["value"], "frac": round(out["roofline"]["frac"], 4),
+                        "ms": round(out["ms_per_step"], 2),
+                        "over_plain": round(out["config"].get("batched_over_plain", 0.0), 4)}}
+    if "hw_frac" in out["roofline"]:
+        s["batched_c4"]["hw_frac"] = round(out["roofline"]["hw_frac"], 4)
+    if "forward_c2" in r:
+        f = r["forward_c2"]
+        s["forward_c2"] = {"pairs_per_s": f["pairs_per_s"], "frac": round(f["roofline"]["frac"], 4),
+                           "ms": round(f["ms"], 3)}
+        if "hw_frac" in f["roofline"]:
+            s["forward_c2"]["hw_frac"] = round(f["roofline"]["hw_frac"], 4)
+    if "adjoint" in r:
+        a = r["adjoint"]
+        s["adjoint_c3"] = {"pairs_per_s": a["adjoint_pairs_per_s"], "frac": round(a["adjoint_frac_fp32_peak"], 4),
+                           "ms": round(a["bwd_ms"], 3)}
+    if "served" in r:
+        s["served_c5"] = [{"load": x["load"], "p50_ms": [round(x["served"]["p50_ms"]), round(x["plain_fifo"]["p50_ms"])],
+                           "p99_ms": [round(x["served"]["p99_ms"]), round(x["plain_fifo"]["p99_ms"])]}
+                          for x in r["served"]["sweep"]]
+        b = r["served"]["burst"]
+        s["served_c5_burst_frac"] = [round(b["served"]["frac_fp32_peak"], 4), round(b["plain_fifo"]["frac_fp32_peak"], 4)]
+    if "cpu_baseline" in out:
+        s["cpu_oracle"] = {"pairs_per_s": out["cpu_baseline"]["value"], "threads": out["cpu_baseline"]["cores"],
+                           "pairs_per_s_1thread": out["cpu_baseline"]["value_1thread"]}
+    return s
 
 
 if __name__ == "__main__":

@@ -150,6 +150,15 @@ WN_API wn_status wn_occupancy(const float *W, int64_t n, int32_t mode, float tau
                        void *stream);
 
 /*
+ * Adjoint of the soft occupancy map (WN_OCC_SIGMOID): for g = dL/d(occ) (float [n]),
+ * dLdW[i] = g[i] k s (1 - s) with s = sigmoid(k (W[i] - tau)) recomputed from W as
+ * wn_occupancy computes it; dLdW may alias g.  The chain rule from a soft-occupancy loss
+ * to the winding numbers (Section 2.4 supervises the mesh by voxel occupancy).
+ */
+WN_API wn_status wn_occupancy_backward(const float *W, const float *g, int64_t n, float tau, float k, float *dLdW,
+                                       void *stream);
+
+/*
  * Soft-occupancy MSE loss L = (1/n) sum_i (sigmoid(k (W_i - tau)) - target_i)^2 and its
  * gradient dLdW[i] (both outputs optional: pass NULL to skip).  `loss` is one float
  * in device memory.  Needs a workspace of wn_workspace_size(WN_OP_LOSS, 0, 0, n).
@@ -265,8 +274,10 @@ typedef struct {
  * workspace and replayed.  Each mesh's result is bit-identical to the same mesh
  * alone in a batched call (its chunking depends only on its own size).
  * Workspace: wn_workspace_size_batched(desc, n).  The table describing the batch is
- * copied from library-owned pinned host memory on `stream`; a later call on the same
- * workspace waits (on the host) until that copy has finished.
+ * copied on `stream` from a ring of library-owned pinned host buffers: a call takes a
+ * buffer whose earlier copy has finished or adds one, so it does not wait on the host
+ * (unless 64 copies for this workspace are still queued).  wn_release_workspace frees
+ * the graphs and buffers.
  * flags: 0, or WN_BATCH_NO_GRAPH to launch without graph capture.
  * Every mesh needs W non-NULL and a grid with n[d] >= 1 and hi > lo.
  */
@@ -277,6 +288,14 @@ WN_API wn_status wn_voxelize_batched(const wn_mesh_desc *desc, int32_t n, int32_
 /* Exact workspace bytes for wn_voxelize_batched of these meshes (0 if a descriptor
  * is invalid). */
 WN_API size_t wn_workspace_size_batched(const wn_mesh_desc *desc, int32_t n);
+
+/*
+ * Frees what the library keeps on the host for a workspace that batched launches used:
+ * its captured graphs and pinned staging buffers.  Call it before the workspace memory
+ * is freed or reused for something else, once no launch using it is still running
+ * (synchronise its stream first).  A workspace the library holds nothing for is a no-op.
+ */
+WN_API wn_status wn_release_workspace(void *ws);
 
 /*
  * Launch autotuner.  Times each candidate launch configuration -- the point tile

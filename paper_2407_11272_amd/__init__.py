@@ -33,6 +33,8 @@ from .api import (  # noqa: F401
     wn_voxelize_strips,
     wn_get_device_error,
     wn_occupancy,
+    wn_occupancy_backward,
+    wn_release_workspace,
     wn_sigmoid_mse,
     wn_version,
     wn_voxelize,

@@ -52,6 +52,7 @@ EXPORTED = (
     "wn_build_strips",
     "wn_voxelize_strips",
     "wn_occupancy",
+    "wn_occupancy_backward",
     "wn_sigmoid_mse",
     "wn_backward",
     "wn_backward_range",
@@ -60,6 +61,7 @@ EXPORTED = (
     "wn_backward_naive",
     "wn_voxelize_batched",
     "wn_workspace_size_batched",
+    "wn_release_workspace",
     "wn_autotune",
     "wn_flip_duplicate",
     "wn_adam",
@@ -132,6 +134,10 @@ def load():
     lib.wn_voxelize_strips.argtypes = [vp, i64, vp, i64, vp, i64, gp, vp, i64, vp, i32, f32, f32, vp, vp, sz, vp]
     lib.wn_occupancy.restype = i32
     lib.wn_occupancy.argtypes = [vp, i64, i32, f32, f32, vp, vp]
+    lib.wn_occupancy_backward.restype = i32
+    lib.wn_occupancy_backward.argtypes = [vp, vp, i64, f32, f32, vp, vp]
+    lib.wn_release_workspace.restype = i32
+    lib.wn_release_workspace.argtypes = [vp]
     lib.wn_sigmoid_mse.restype = i32
     lib.wn_sigmoid_mse.argtypes = [vp, vp, i64, f32, f32, vp, vp, vp, sz, vp]
     lib.wn_backward.restype = i32

@@ -67,6 +67,10 @@ class Workspace:
         key = (device.index, torch.cuda.current_stream(device).cuda_stream)
         buf = cls._cache.get(key)
         if buf is None or buf.numel() < nbytes + 256:
+            if buf is not None:   # the old buffer goes: release what the library keeps for it
+                torch.cuda.current_stream(device).synchronize()
+                old = buf.data_ptr()
+                L.check("wn_release_workspace", L.load().wn_release_workspace(ctypes.c_void_p(old + (-old) % 256)))
             cap = max(nbytes + 256, 1 << 20, 0 if buf is None else int(buf.numel() * 1.5))
             buf = torch.zeros(cap, dtype=torch.uint8, device=device)
             cls._cache[key] = buf
@@ -76,6 +80,11 @@ class Workspace:
 
     @classmethod
     def clear(cls):
+        lib = L.load()
+        for (dev, _), buf in cls._cache.items():
+            torch.cuda.synchronize(dev)
+            base = buf.data_ptr()
+            L.check("wn_release_workspace", lib.wn_release_workspace(ctypes.c_void_p(base + (-base) % 256)))
         cls._cache.clear()
 
 
@@ -277,6 +286,27 @@ def wn_occupancy(W: torch.Tensor, mode: str = "threshold", tau: float = 0.5, k: 
     st = L.load().wn_occupancy(_ptr(W), W.numel(), m, tau, k, _ptr(occ), _stream_handle(W.device))
     L.check("wn_occupancy", st)
     return occ
+
+
+def wn_occupancy_backward(W: torch.Tensor, g: torch.Tensor, tau: float = 0.5, k: float = 50.0,
+                          dLdW: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dW from g = dL/d(occ) of the soft occupancy sigmoid(k (W - tau))."""
+    for name, t in (("W", W), ("g", g)):
+        if not t.is_contiguous() or t.dtype != torch.float32 or not t.is_cuda:
+            raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if g.numel() != W.numel():
+        raise ValueError("g must have one entry per entry of W")
+    if dLdW is None:
+        dLdW = torch.empty_like(W)
+    st = L.load().wn_occupancy_backward(_ptr(W), _ptr(g), W.numel(), tau, k, _ptr(dLdW), _stream_handle(W.device))
+    L.check("wn_occupancy_backward", st)
+    return dLdW
+
+
+def wn_release_workspace(ws) -> None:
+    """Free what the library keeps for a workspace (graphs, pinned staging); the caller
+    synchronises the workspace's stream first."""
+    L.check("wn_release_workspace", L.load().wn_release_workspace(ws))
 
 
 def wn_sigmoid_mse(W: torch.Tensor, target: torch.Tensor, tau: float = 0.5, k: float = 50.0,

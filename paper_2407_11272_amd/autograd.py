@@ -45,19 +45,22 @@ class NaiveWindingNumber(torch.autograd.Function):
 
 
 class SigmoidOccupancy(torch.autograd.Function):
-    """occ = sigmoid(k (W - tau)) on the device; backward k occ (1 - occ) g."""
+    """occ = sigmoid(k (W - tau)); forward and backward (g k occ (1 - occ)) both in the
+    HIP library (wn_occupancy, wn_occupancy_backward)."""
 
     @staticmethod
     def forward(ctx, W, tau: float = 0.5, k: float = 50.0):
-        occ = api.wn_occupancy(W.contiguous(), "sigmoid", tau, k)
-        ctx.save_for_backward(occ)
-        ctx.k = k
+        W = W.contiguous()
+        occ = api.wn_occupancy(W, "sigmoid", tau, k)
+        ctx.save_for_backward(W)
+        ctx.tau, ctx.k = tau, k
         return occ
 
     @staticmethod
     def backward(ctx, g):
-        (occ,) = ctx.saved_tensors
-        return g * ctx.k * occ * (1.0 - occ), None, None
+        (W,) = ctx.saved_tensors
+        g = g.contiguous().to(torch.float32)
+        return api.wn_occupancy_backward(W, g, ctx.tau, ctx.k), None, None
 
 
 def winding_number(V, F, grid=None, Q=None):

@@ -200,6 +200,19 @@ wn_status wn_occupancy(const float *W, int64_t n, int32_t mode, float tau, float
     return hip_status(launch_occ(W, n, op, static_cast<hipStream_t>(stream)));
 }
 
+wn_status wn_occupancy_backward(const float *W, const float *g, int64_t n, float tau, float k, float *dLdW,
+                                void *stream) {
+    if (n < 0 || !std::isfinite(tau) || !std::isfinite(k)) return WN_ERR_INVALID_ARG;
+    if (n == 0) return WN_OK;
+    if (W == nullptr || g == nullptr || dLdW == nullptr) return WN_ERR_INVALID_ARG;
+    return hip_status(launch_occ_bwd(W, g, n, tau, k, dLdW, static_cast<hipStream_t>(stream)));
+}
+
+wn_status wn_release_workspace(void *ws) {
+    if (ws == nullptr) return WN_ERR_INVALID_ARG;
+    return release_batched(ws);
+}
+
 wn_status wn_sigmoid_mse(const float *W, const float *target, int64_t n, float tau, float k, float *loss,
                          float *dLdW, void *ws, size_t ws_bytes, void *stream) {
     if (n < 0 || n > kMaxCount) return WN_ERR_INVALID_ARG;

@@ -338,14 +338,22 @@ bool make_plan(const wn_mesh_desc *d, int32_t n, int32_t ppl, Plan &plan) {
     return true;
 }
 
-// Per-workspace host state: pinned staging for the tables and the captured graphs.
-struct WsState {
-    void *staging = nullptr;
+// Per-workspace host state: a ring of pinned staging buffers for the tables, each with
+// the event recorded after its copy, and the captured graphs.  A call takes a buffer
+// whose copy has finished (hipEventQuery), or adds one to the ring, so it never waits on
+// the host for an earlier call's copy.
+struct Staging {
+    void *buf = nullptr;
     size_t cap = 0;
     hipEvent_t copied = nullptr;
-    bool pending = false;
+};
+
+struct WsState {
+    std::vector<Staging> ring;
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (ppl, depth, persistent grid, device)
 };
+
+constexpr size_t kMaxStaging = 64;  // buffers per workspace ring
 
 std::mutex g_mu;
 std::map<const void *, WsState> g_state;
@@ -408,22 +416,41 @@ wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws,
 
     std::lock_guard<std::mutex> lk(g_mu);
     WsState &st = g_state[ws];
-    if (st.pending && hipEventSynchronize(st.copied) != hipSuccess) return WN_ERR_HIP;
-    st.pending = false;
     const size_t tb = plan.tables.size();
-    if (st.cap < tb) {
-        if (st.staging) (void)hipHostFree(st.staging);
-        st.staging = nullptr;
-        st.cap = 0;
-        const size_t cap = std::max<size_t>(tb, 64 * 1024);
-        if (hipHostMalloc(&st.staging, cap, hipHostMallocDefault) != hipSuccess) return WN_ERR_HIP;
-        st.cap = cap;
+    // a staging buffer whose previous copy has finished, else a new one in the ring
+    Staging *sb = nullptr;
+    for (Staging &x : st.ring) {
+        const hipError_t q = hipEventQuery(x.copied);
+        if (q == hipSuccess) {
+            sb = &x;
+            break;
+        }
+        if (q != hipErrorNotReady) return WN_ERR_HIP;
     }
-    if (!st.copied && hipEventCreateWithFlags(&st.copied, hipEventDisableTiming) != hipSuccess) return WN_ERR_HIP;
-    memcpy(st.staging, plan.tables.data(), tb);
-    if (hipMemcpyAsync(ws + kWsHeader, st.staging, tb, hipMemcpyHostToDevice, s) != hipSuccess) return WN_ERR_HIP;
-    if (hipEventRecord(st.copied, s) != hipSuccess) return WN_ERR_HIP;
-    st.pending = true;
+    if (sb == nullptr) {
+        if (st.ring.size() >= kMaxStaging) {  // a deep backlog of copies: wait for the oldest
+            if (hipEventSynchronize(st.ring.front().copied) != hipSuccess) return WN_ERR_HIP;
+            sb = &st.ring.front();
+        } else {
+            st.ring.emplace_back();
+            sb = &st.ring.back();
+            if (hipEventCreateWithFlags(&sb->copied, hipEventDisableTiming) != hipSuccess) {
+                st.ring.pop_back();
+                return WN_ERR_HIP;
+            }
+        }
+    }
+    if (sb->cap < tb) {
+        if (sb->buf) (void)hipHostFree(sb->buf);
+        sb->buf = nullptr;
+        sb->cap = 0;
+        const size_t cap = std::max<size_t>(tb, 64 * 1024);
+        if (hipHostMalloc(&sb->buf, cap, hipHostMallocDefault) != hipSuccess) return WN_ERR_HIP;
+        sb->cap = cap;
+    }
+    memcpy(sb->buf, plan.tables.data(), tb);
+    if (hipMemcpyAsync(ws + kWsHeader, sb->buf, tb, hipMemcpyHostToDevice, s) != hipSuccess) return WN_ERR_HIP;
+    if (hipEventRecord(sb->copied, s) != hipSuccess) return WN_ERR_HIP;
 
     if (flags & WN_BATCH_NO_GRAPH) return enqueue_kernels(ws, ppl, depth, grid, s) == hipSuccess ? WN_OK : WN_ERR_HIP;
 
@@ -446,6 +473,23 @@ wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws,
         it = st.graphs.emplace(key, exec).first;
     }
     return hipGraphLaunch(it->second, s) == hipSuccess ? WN_OK : WN_ERR_HIP;
+}
+
+wn_status release_batched(const void *ws) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_state.find(ws);
+    if (it == g_state.end()) return WN_OK;
+    wn_status st = WN_OK;
+    for (Staging &x : it->second.ring) {
+        if (x.copied) {
+            if (hipEventSynchronize(x.copied) != hipSuccess) st = WN_ERR_HIP;
+            (void)hipEventDestroy(x.copied);
+        }
+        if (x.buf) (void)hipHostFree(x.buf);
+    }
+    for (auto &g : it->second.graphs) (void)hipGraphExecDestroy(g.second);
+    g_state.erase(it);
+    return st;
 }
 
 }  // namespace wn

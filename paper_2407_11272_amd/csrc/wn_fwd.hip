@@ -132,6 +132,16 @@ __global__ __launch_bounds__(kBlock) void k_occ(const float *__restrict__ W, int
     write_occ(occ, idx, W[idx]);
 }
 
+// Chain rule through the soft occupancy s = sigmoid(k (W - tau)): dL/dW = g k s (1 - s),
+// with s recomputed from W as the forward map computes it.
+__global__ __launch_bounds__(kBlock) void k_occ_bwd(const float *__restrict__ W, const float *__restrict__ g,
+                                                    int64_t n, float tau, float k, float *__restrict__ dLdW) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const float sg = sigmoidf(k * (W[idx] - tau));
+    dLdW[idx] = g[idx] * k * sg * (1.0f - sg);
+}
+
 // Sigmoid-MSE: per block, a fixed-shape tree sum of (s - t)^2; per element dL/dW.
 constexpr int kLossBlocks = 1024;
 
@@ -273,6 +283,13 @@ hipError_t launch_split_reduce(const float *partials, int split, int64_t nQ, flo
 hipError_t launch_occ(const float *W, int64_t n, const OccParams &occ, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_occ<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), kBlock, 0, s>>>(W, n, occ);
+    return hipGetLastError();
+}
+
+hipError_t launch_occ_bwd(const float *W, const float *g, int64_t n, float tau, float k, float *dLdW,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_occ_bwd<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), kBlock, 0, s>>>(W, g, n, tau, k, dLdW);
     return hipGetLastError();
 }
 

@@ -440,6 +440,8 @@ hipError_t launch_fwd(const VRec *recs, int64_t nR, const PointSrc &ps, int64_t 
 // Order-free checksum (sum of the bit patterns) of n floats into hdr->checksum.
 hipError_t launch_checksum(const float *x, int64_t n, WsHeader *hdr, bool reset, hipStream_t s);
 hipError_t launch_occ(const float *W, int64_t n, const OccParams &occ, hipStream_t s);
+hipError_t launch_occ_bwd(const float *W, const float *g, int64_t n, float tau, float k, float *dLdW,
+                          hipStream_t s);
 // Fixed-order sum of [split][nQ] partials times `scale` into W, plus occupancy.
 hipError_t launch_split_reduce(const float *partials, int split, int64_t nQ, float scale, float *W,
                                const OccParams &occ, hipStream_t s);
@@ -532,6 +534,8 @@ wn_status noalloc_header(void **out);
 
 // Batched pieces (wn_batched.hip).
 size_t batched_workspace(const wn_mesh_desc *d, int32_t n);
+// Frees what the library holds for a workspace (captured graphs, pinned staging).
+wn_status release_batched(const void *ws);
 wn_status run_batched(const wn_mesh_desc *d, int32_t n, int32_t flags, char *ws, size_t ws_bytes,
                       hipStream_t s, const struct TuneConfig *force);
 

@@ -220,3 +220,36 @@ def test_batched_strips_alone_mix_and_plain(dev):
     b = _run([j])[0]
     p = wn.wn_voxelize_strips(j.V, j.F, j.strips, grid=j.grid).cpu().numpy().reshape(-1)
     np.testing.assert_array_equal(b, p)
+
+
+def test_back_to_back_batches_without_host_waits_and_release(dev):
+    """Several different batches enqueued on one workspace with no synchronisation in
+    between (each call stages its table in its own pinned buffer of the workspace's ring
+    instead of waiting for the previous copy), each into its own outputs: every mesh
+    equals its eager result.  wn_release_workspace then frees the graphs and buffers, and
+    the next call rebuilds them."""
+    import ctypes
+    import torch
+    import paper_2407_11272_amd as wn
+    from paper_2407_11272_amd import _lib as L
+    base = _small_batch(3)
+    batches = [base, base[::-1], base[1:4], base[:2], base]
+    ref = [_run([_job(V, F, gr) for V, F, gr in b], graph=False) for b in batches]
+    lib = L.load()
+    jobs_all = [[_job(V, F, gr).prepare() for V, F, gr in b] for b in batches]
+    need = max(int(lib.wn_workspace_size_batched(wn.api._descs(js), len(js))) for js in jobs_all)
+    buf = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    ws = ctypes.c_void_p(buf.data_ptr() + (-buf.data_ptr()) % 256)
+    for rnd in range(2):
+        for js in jobs_all:   # no synchronisation between the calls
+            wn.wn_voxelize_batched(js, graph=True, workspace=(ws, need))
+        torch.cuda.synchronize()
+        for js, r in zip(jobs_all, ref):
+            for j, x in zip(js, r):
+                np.testing.assert_array_equal(j.W.cpu().numpy().reshape(-1), x)
+        for js in jobs_all:
+            for j in js:
+                j.W.fill_(float("nan"))
+        assert lib.wn_release_workspace(ws) == L.WN_OK
+    assert lib.wn_release_workspace(ws) == L.WN_OK    # nothing held: a no-op
+    assert lib.wn_release_workspace(None) == L.WN_ERR_INVALID_ARG

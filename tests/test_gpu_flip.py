@@ -50,12 +50,16 @@ def test_flip_duplicate_matches_oracle(dev, orc, case):
     V2r, F2r = orc.flip_duplicate(V32.astype(np.float64), F, eps)
     np.testing.assert_array_equal(F2.cpu().numpy(), F2r)
     assert np.abs(V2.cpu().numpy() - V2r).max() <= 1e-6
+    # the duplicate voxelizes like a closed mesh: the oracle's duplicate (rounded to FP32)
+    # is the input of both sides
     grid = wi.Grid.cube(40)
-    R = torch.as_tensor(wn.wn_build_strips(F2.cpu().numpy(), V2.shape[0])).cuda()
-    W = wn.wn_voxelize_strips(V2, F2, R, grid=grid).cpu().numpy().reshape(-1)
+    V2in = np.asarray(V2r, np.float32)
+    V2d, F2d = wn.as_mesh(torch.as_tensor(V2in), torch.as_tensor(F2r))
+    R = torch.as_tensor(wn.wn_build_strips(F2r, len(V2in))).cuda()
+    W = wn.wn_voxelize_strips(V2d, F2d, R, grid=grid).cpu().numpy().reshape(-1)
     Q = orc.grid_points(grid)
     idx = np.random.default_rng(3).choice(len(Q), 4000, replace=False)
-    V2g = V2.cpu().numpy().astype(np.float64)
+    V2g = V2in.astype(np.float64)
     Wr = orc.winding(V2g, F2r, Q[idx])
     guard = orc.guard_mask(V2g, F2r, Q[idx])
     err = np.abs(W[idx] - Wr)[~guard]

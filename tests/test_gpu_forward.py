@@ -286,23 +286,33 @@ def test_argument_errors(dev):
 
 
 def test_occupancy_maps_and_loss(dev, orc):
+    """Occupancy maps, the sigmoid-MSE loss and its gradient, and the soft occupancy's
+    adjoint, all applied on the GPU to the oracle's W (rounded to FP32): the same input
+    on both sides.  The fused occupancy of the forward equals the separate map."""
     import torch
     import paper_2407_11272_amd as wn
     c = wi.config3_differentiable(res=32)
-    c_t = torch.as_tensor(c.target).cuda()
     Vt, Ft = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
-    W, occ = wn.wn_voxelize(Vt, Ft, grid=c.grid, occupancy="sigmoid", k=50.0)
-    occ2 = wn.wn_occupancy(W, "sigmoid", 0.5, 50.0)
+    Wf, occf = wn.wn_voxelize(Vt, Ft, grid=c.grid, occupancy="sigmoid", k=50.0)
+    torch.testing.assert_close(occf, wn.wn_occupancy(Wf, "sigmoid", 0.5, 50.0), rtol=0, atol=0)
+    W32 = orc.winding(np.asarray(c.V, np.float32).astype(np.float64), c.F, orc.grid_points(c.grid)).astype(np.float32)
+    Wn = W32.astype(np.float64)
+    W = torch.as_tensor(W32).cuda()
+    occ = wn.wn_occupancy(W, "sigmoid", 0.5, 50.0)
     thr = wn.wn_occupancy(W, "threshold", 0.5)
-    loss, g = wn.wn_sigmoid_mse(W.reshape(-1), c_t)
+    c_t = torch.as_tensor(c.target).cuda()
+    loss, g = wn.wn_sigmoid_mse(W, c_t)
+    # soft-occupancy adjoint: with g_occ = 2 (occ - target) / P it is the loss gradient
+    s_ref = orc.occupancy_sigmoid(Wn, 0.5, 50.0)
+    g_occ = torch.as_tensor((2.0 * (s_ref - c.target) / len(Wn)).astype(np.float32)).cuda()
+    dW = wn.wn_occupancy_backward(W, g_occ, 0.5, 50.0)
     torch.cuda.synchronize()
-    Wn = W.cpu().numpy().reshape(-1).astype(np.float64)
-    torch.testing.assert_close(occ, occ2, rtol=0, atol=0)
-    np.testing.assert_allclose(occ.cpu().numpy().reshape(-1), orc.occupancy_sigmoid(Wn, 0.5, 50.0), atol=1e-6)
-    np.testing.assert_array_equal(thr.cpu().numpy().reshape(-1), orc.occupancy_threshold(Wn))
+    np.testing.assert_allclose(occ.cpu().numpy(), s_ref, atol=1e-6)
+    np.testing.assert_array_equal(thr.cpu().numpy(), orc.occupancy_threshold(Wn))
     Lr, gr = orc.sigmoid_mse(Wn, c.target, 0.5, 50.0)
     assert float(loss.item()) == pytest.approx(Lr, rel=1e-5)
-    np.testing.assert_allclose(g.cpu().numpy().reshape(-1), gr, rtol=1e-4, atol=1e-12)
+    np.testing.assert_allclose(g.cpu().numpy(), gr, rtol=1e-4, atol=1e-12)
+    np.testing.assert_allclose(dW.cpu().numpy(), gr, rtol=1e-4, atol=1e-12)
 
 
 def _strips_dev(F, nV):
