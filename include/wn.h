@@ -198,6 +198,12 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
  * split's first tile restarts that split); the library does not detect it.
  *   p0:    a multiple of WN_BWD_TILE;  n: a multiple of WN_BWD_TILE, or p0 + n = nQ;
  *   dLdW:  indexed by the global point number (only [p0, p0 + n) is read);
+ *   pairs: NULL (one face per lane), or a device copy of wn_build_face_pairs' output
+ *          (n_pairs of them) for two faces per lane; the same in every call of a
+ *          sequence.  Pairs give the same gradient up to rounding (the per-face
+ *          arithmetic is the same, the compiler's contractions may differ).  A face
+ *          missing or repeated, or a pair without a shared edge, is recorded as a bad
+ *          index (wn_get_device_error);
  *   V, F, grid / Q, nQ: the same in every call of a sequence;
  *   dLdV:  needed with WN_BWD_END; dLdT optional, as in wn_backward;
  *   ws:    wn_workspace_size(WN_OP_BACKWARD, nV, nF, nQ) bytes, holding the running sums.
@@ -208,10 +214,26 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
 #define WN_BWD_END 2
 #define WN_BWD_TILE 256
 WN_API wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF,
+                                   const int32_t *pairs, int64_t n_pairs,
                                    const wn_grid *grid, const float *Q, int64_t nQ,
                                    const float *dLdW, int64_t p0, int64_t n,
                                    int32_t flags, float *dLdV, float *dLdT,
                                    void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Pairs of faces that share an edge, built on the host from HOST face indices F (int32
+ * [nF][3], every index in [0, nV)), for the adjoint: with them wn_backward_range gives
+ * each lane two faces and evaluates the shared edge's two vertices once for both (4
+ * instead of 6 vertices per point).  Output int32 [n_pairs][2] = (f, g), pairs of faces
+ * with three distinct vertex ids sharing exactly two (consecutive faces of the strips of
+ * wn_build_strips, then left-over faces matched across an edge), followed by the
+ * unpaired faces as (f, -1); every face appears exactly once, so ceil(nF / 2) <= n_pairs
+ * <= nF.  A pure function of F.  With pairs == NULL only *n_pairs is set; otherwise
+ * capacity (in pairs) must be >= *n_pairs, else WN_ERR_WORKSPACE.  Invalid indices
+ * return WN_ERR_INVALID_ARG.
+ */
+WN_API wn_status wn_build_face_pairs(const int32_t *F, int64_t nF, int64_t nV, int32_t *pairs, int64_t capacity,
+                                     int64_t *n_pairs);
 
 /* The number of splits S of the adjoint of nF faces over nQ points (a pure function of the
  * sizes: about 32 768 waves of (face block, split) work, at most one split per tile, at

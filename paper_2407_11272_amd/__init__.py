@@ -29,6 +29,7 @@ from .api import (  # noqa: F401
     wn_backward_naive,
     wn_voxelize_naive,
     wn_build_strips,
+    wn_build_face_pairs,
     wn_flip_duplicate,
     wn_voxelize_strips,
     wn_get_device_error,

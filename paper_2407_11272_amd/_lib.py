@@ -57,6 +57,7 @@ EXPORTED = (
     "wn_backward",
     "wn_backward_range",
     "wn_backward_splits",
+    "wn_build_face_pairs",
     "wn_voxelize_naive",
     "wn_backward_naive",
     "wn_voxelize_batched",
@@ -143,7 +144,10 @@ def load():
     lib.wn_backward.restype = i32
     lib.wn_backward.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, vp, vp, vp, sz, vp]
     lib.wn_backward_range.restype = i32
-    lib.wn_backward_range.argtypes = [vp, i64, vp, i64, gp, vp, i64, vp, i64, i64, i32, vp, vp, vp, sz, vp]
+    lib.wn_backward_range.argtypes = [vp, i64, vp, i64, vp, i64, gp, vp, i64, vp, i64, i64, i32, vp, vp, vp, sz,
+                                      vp]
+    lib.wn_build_face_pairs.restype = i32
+    lib.wn_build_face_pairs.argtypes = [vp, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_int64)]
     lib.wn_backward_splits.restype = i64
     lib.wn_backward_splits.argtypes = [i64, i64]
     lib.wn_voxelize_naive.restype = i32

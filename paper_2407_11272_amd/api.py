@@ -160,6 +160,30 @@ def wn_build_strips(F, nV: int | None = None):
     return out[:n.value].copy()
 
 
+def wn_build_face_pairs(F, nV: int | None = None):
+    """Pairs of host faces F ([nF, 3]) that share an edge, for the adjoint's two-faces-per-
+    lane kernel: an int32 numpy array [n, 2] of (f, g or -1), every face once.  Depends
+    only on F."""
+    import numpy as np
+    lib = L.load()
+    Fh = np.ascontiguousarray(torch.as_tensor(F).cpu().numpy(), dtype=np.int32).reshape(-1, 3)
+    nV = int(Fh.max()) + 1 if nV is None and len(Fh) else int(nV or 0)
+    n = ctypes.c_int64(0)
+    out = np.empty((max(1, len(Fh)), 2), dtype=np.int32)   # at most one entry per face: one call
+    L.check("wn_build_face_pairs", lib.wn_build_face_pairs(Fh.ctypes.data, len(Fh), nV, out.ctypes.data, len(out),
+                                                           ctypes.byref(n)))
+    return out[:n.value].copy()
+
+
+def _check_pairs(pairs, F):
+    if pairs is None:
+        return None
+    if pairs.dtype != torch.int32 or pairs.dim() != 2 or pairs.shape[1] != 2 or not pairs.is_cuda \
+            or not pairs.is_contiguous():
+        raise ValueError("pairs must be a contiguous int32 [n, 2] device tensor (wn_build_face_pairs)")
+    return pairs
+
+
 def wn_voxelize_strips(V, F, strips: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None,
                        W: torch.Tensor | None = None, occupancy: str | None = None, tau: float = 0.5,
                        k: float = 50.0, occ: torch.Tensor | None = None):
@@ -207,8 +231,11 @@ class SlicedBackward:
     The object owns its workspace, which holds the splits' running sums between calls;
     all calls go to the current stream of V's device."""
 
-    def __init__(self, V, F, grid: Grid | None = None, Q: torch.Tensor | None = None):
+    def __init__(self, V, F, grid: Grid | None = None, Q: torch.Tensor | None = None,
+                 pairs: torch.Tensor | None = None):
         _check_mesh(V, F)
+        self.pairs = _check_pairs(pairs, F)
+        self._np = 0 if pairs is None else int(pairs.shape[0])
         if (grid is None) == (Q is None):
             raise ValueError("pass exactly one of grid or Q")
         self.lib = L.load()
@@ -240,9 +267,10 @@ class SlicedBackward:
 
     def _call(self, dLdW, p0, n, flags, dLdV=None, dLdT=None):
         g = ctypes.byref(self._gc) if self._gc is not None else None
-        st = self.lib.wn_backward_range(_ptr(self.V), self.V.shape[0], _ptr(self.F), self.F.shape[0], g, self._qptr,
-                                        self._nQ, _ptr(dLdW), int(p0), int(n), flags, _ptr(dLdV), _ptr(dLdT),
-                                        self._ws, self._wsb, _stream_handle(self.dev))
+        st = self.lib.wn_backward_range(_ptr(self.V), self.V.shape[0], _ptr(self.F), self.F.shape[0],
+                                        _ptr(self.pairs), self._np, g, self._qptr, self._nQ, _ptr(dLdW), int(p0),
+                                        int(n), flags, _ptr(dLdV), _ptr(dLdT), self._ws, self._wsb,
+                                        _stream_handle(self.dev))
         L.check("wn_backward_range", st)
 
     def begin(self):
@@ -259,6 +287,10 @@ class SlicedBackward:
             raise ValueError(f"ranges must be consecutive: expected p0 = {self._next}, got {p0}")
         self._call(dLdW, p0, n, 0)
         self._next = int(p0) + int(n)
+
+    def device_error(self) -> int:
+        """The device error record of this adjoint's workspace (synchronises)."""
+        return int(self.lib.wn_get_device_error(self._ws, _stream_handle(self.dev)))
 
     def end(self, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None) -> torch.Tensor:
         if self._next != self.P:
@@ -332,8 +364,10 @@ def wn_sigmoid_mse(W: torch.Tensor, target: torch.Tensor, tau: float = 0.5, k: f
 
 def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None,
                 want_dLdT: bool = False, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None,
-                _entry: str = "wn_backward"):
-    """dL/dV [nV, 3] (and dL/dT [nF, 3, 3] if requested) for the given dL/dW."""
+                _entry: str = "wn_backward", pairs: torch.Tensor | None = None):
+    """dL/dV [nV, 3] (and dL/dT [nF, 3, 3] if requested) for the given dL/dW.  With
+    ``pairs`` (a device copy of :func:`wn_build_face_pairs`) two faces per lane, through
+    one wn_backward_range call."""
     lib = L.load()
     _check_mesh(V, F)
     if (grid is None) == (Q is None):
@@ -354,6 +388,13 @@ def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Ten
         dLdT = torch.empty((F.shape[0], 3, 3), dtype=torch.float32, device=dev)
     need = wn_workspace_size(L.WN_OP_BACKWARD, V.shape[0], F.shape[0], P)
     ws, wsb = Workspace.get(need, dev)
+    if pairs is not None:   # the whole range in one wn_backward_range call
+        pairs = _check_pairs(pairs, F)
+        st = lib.wn_backward_range(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(pairs), pairs.shape[0], gptr, qptr,
+                                   nQ, _ptr(dLdW), 0, P, L.WN_BWD_BEGIN | L.WN_BWD_END, _ptr(dLdV),
+                                   _ptr(dLdT if want_dLdT else None), ws, wsb, _stream_handle(dev))
+        L.check("wn_backward_range", st)
+        return (dLdV, dLdT) if want_dLdT else dLdV
     st = getattr(lib, _entry)(_ptr(V), V.shape[0], _ptr(F), F.shape[0], gptr, qptr, nQ, _ptr(dLdW), _ptr(dLdV),
                               _ptr(dLdT if want_dLdT else None), ws, wsb, _stream_handle(dev))
     L.check(_entry, st)

@@ -191,6 +191,21 @@ wn_status wn_build_strips(const int32_t *F, int64_t nF, int64_t nV, int32_t *rec
     return WN_OK;
 }
 
+wn_status wn_build_face_pairs(const int32_t *F, int64_t nF, int64_t nV, int32_t *pairs, int64_t capacity,
+                              int64_t *n_pairs) {
+    if (n_pairs == nullptr || nF < 0 || nV < 0 || nF > kMaxCount || nV > kMaxCount) return WN_ERR_INVALID_ARG;
+    if (nF > 0 && F == nullptr) return WN_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < 3 * nF; ++i)
+        if (F[i] < 0 || (int64_t)F[i] >= nV) return WN_ERR_INVALID_ARG;
+    std::vector<int32_t> out;
+    const int64_t n = build_face_pairs(F, nF, out);
+    *n_pairs = n;
+    if (pairs == nullptr) return WN_OK;
+    if (capacity < n) return WN_ERR_WORKSPACE;
+    if (n > 0) memcpy(pairs, out.data(), sizeof(int32_t) * 2 * (size_t)n);
+    return WN_OK;
+}
+
 wn_status wn_occupancy(const float *W, int64_t n, int32_t mode, float tau, float k, void *occ, void *stream) {
     if (n < 0) return WN_ERR_INVALID_ARG;
     if (mode != WN_OCC_THRESHOLD && mode != WN_OCC_SIGMOID) return WN_ERR_INVALID_ARG;
@@ -224,10 +239,12 @@ wn_status wn_sigmoid_mse(const float *W, const float *target, int64_t n, float t
     return hip_status(launch_sigmoid_mse(W, target, n, tau, k, loss, dLdW, scratch, static_cast<hipStream_t>(stream)));
 }
 
-wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF, const wn_grid *grid,
-                            const float *Q, int64_t nQ, const float *dLdW, int64_t p0, int64_t n, int32_t flags,
-                            float *dLdV, float *dLdT, void *ws, size_t ws_bytes, void *stream) {
+wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *pairs,
+                            int64_t n_pairs, const wn_grid *grid, const float *Q, int64_t nQ, const float *dLdW,
+                            int64_t p0, int64_t n, int32_t flags, float *dLdV, float *dLdT, void *ws,
+                            size_t ws_bytes, void *stream) {
     if (!mesh_ok(V, nV, F, nF)) return WN_ERR_INVALID_ARG;
+    if (pairs == nullptr ? n_pairs != 0 : (n_pairs < (nF + 1) / 2 || n_pairs > nF)) return WN_ERR_INVALID_ARG;
     const int64_t P = query_count(grid, Q, nQ);
     if (P < 0) return WN_ERR_INVALID_ARG;
     if (flags & ~(WN_BWD_BEGIN | WN_BWD_END)) return WN_ERR_INVALID_ARG;
@@ -240,7 +257,7 @@ wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_
             if (grid->n[d] > 0 && !(grid->hi[d] > grid->lo[d])) return WN_ERR_INVALID_ARG;
     const size_t need = bwd_workspace(nV, nF, P);
     if (ws == nullptr || !aligned256(ws) || ws_bytes < need) return WN_ERR_WORKSPACE;
-    return run_backward(V, nV, F, nF, make_point_src(grid, Q), P, dLdW, p0, n, flags, dLdV, dLdT,
+    return run_backward(V, nV, F, nF, pairs, n_pairs, make_point_src(grid, Q), P, dLdW, p0, n, flags, dLdV, dLdT,
                         static_cast<char *>(ws), ws_bytes, static_cast<hipStream_t>(stream));
 }
 
@@ -248,8 +265,8 @@ wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, 
                       const float *Q, int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, void *ws,
                       size_t ws_bytes, void *stream) {
     const int64_t P = query_count(grid, Q, nQ);
-    return wn_backward_range(V, nV, F, nF, grid, Q, nQ, dLdW, 0, P < 0 ? 0 : P, WN_BWD_BEGIN | WN_BWD_END, dLdV,
-                             dLdT, ws, ws_bytes, stream);
+    return wn_backward_range(V, nV, F, nF, nullptr, 0, grid, Q, nQ, dLdW, 0, P < 0 ? 0 : P, WN_BWD_BEGIN | WN_BWD_END,
+                             dLdV, dLdT, ws, ws_bytes, stream);
 }
 
 int64_t wn_backward_splits(int64_t nF, int64_t nQ) {

@@ -424,6 +424,8 @@ int64_t fwd_split_chunk(int64_t nR, int split);
 
 // Host triangle-strip builder (wn_strips.hip): records as int32 pairs.
 int64_t build_strips(const int32_t *F, int64_t nF, std::vector<int32_t> &out);
+// Host face pairing for the adjoint (wn_strips.hip): int32 pairs (f, g or -1).
+int64_t build_face_pairs(const int32_t *F, int64_t nF, std::vector<int32_t> &out);
 
 PointSrc make_point_src(const wn_grid *grid, const float *Q);
 
@@ -459,13 +461,16 @@ constexpr int kBwdBegin = 1, kBwdEnd = 2;
 constexpr int kBwdTile = 256;
 int bwd_splits(int64_t nF, int64_t nQ);
 size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ);
-wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
-                       int64_t nQ, const float *dLdW, int64_t p0, int64_t n, int flags, float *dLdV, float *dLdT,
-                       char *ws, size_t ws_bytes, hipStream_t s, bool naive = false);
+// `pairs` (device int32 [nP][2], optional): faces two per lane, each pair sharing an
+// edge (wn_build_face_pairs); the exact adjoint only.
+wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *pairs, int64_t nP,
+                       const PointSrc &ps, int64_t nQ, const float *dLdW, int64_t p0, int64_t n, int flags,
+                       float *dLdV, float *dLdT, char *ws, size_t ws_bytes, hipStream_t s, bool naive = false);
 inline wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF, const PointSrc &ps,
                               int64_t nQ, const float *dLdW, float *dLdV, float *dLdT, char *ws, size_t ws_bytes,
                               hipStream_t s, bool naive = false) {
-    return run_backward(V, nV, F, nF, ps, nQ, dLdW, 0, nQ, kBwdBegin | kBwdEnd, dLdV, dLdT, ws, ws_bytes, s, naive);
+    return run_backward(V, nV, F, nF, nullptr, 0, ps, nQ, dLdW, 0, nQ, kBwdBegin | kBwdEnd, dLdV, dLdT, ws,
+                        ws_bytes, s, naive);
 }
 
 // A split's running sums of face f: (sum, compensation) of its 9 corner components at

@@ -146,4 +146,62 @@ int64_t build_strips(const int32_t *F, int64_t nF, std::vector<int32_t> &out) {
     return (int64_t)(out.size() / 2);
 }
 
+// Pairs of faces that share an edge, for the adjoint's two-faces-per-lane kernel (the
+// shared edge's two vertices are evaluated once for both faces).  Consecutive faces of
+// each strip are paired; the faces left over (one per strip of odd length) are then
+// matched greedily, in face order, with a left-over face across one of their edges.
+// Only faces with three distinct vertex ids sharing exactly two of them are paired.
+// Output: int32 pairs (f, g), the pairs first, then the unpaired faces as (f, -1), so
+// that every face appears exactly once.  A pure function of F.
+int64_t build_face_pairs(const int32_t *F, int64_t nF, std::vector<int32_t> &out) {
+    auto distinct = [&](int64_t f) {
+        const int32_t *t = F + 3 * f;
+        return t[0] != t[1] && t[1] != t[2] && t[2] != t[0];
+    };
+    auto shared = [&](int64_t f, int64_t g) {
+        int n = 0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) n += F[3 * f + i] == F[3 * g + j];
+        return n;
+    };
+    std::vector<int32_t> rec;
+    build_strips(F, nF, rec);
+    const int64_t nR = (int64_t)rec.size() / 2;
+    std::vector<uint8_t> paired((size_t)nF, 0);
+    out.clear();
+    out.reserve((size_t)nF * 2 + 4);
+    // consecutive faces of each strip: face records come in runs after two openers
+    for (int64_t r = 0; r + 1 < nR; ++r) {
+        const int32_t f = rec[2 * r + 1], g = rec[2 * r + 3];
+        if (f < 0 || g < 0 || paired[(size_t)f] || paired[(size_t)g]) continue;
+        if (!distinct(f) || !distinct(g) || shared(f, g) != 2) continue;
+        paired[(size_t)f] = paired[(size_t)g] = 1;
+        out.push_back(f);
+        out.push_back(g);
+        ++r;  // the next record's face is taken
+    }
+    // left-over faces: a greedy match across their edges
+    Builder b;
+    b.F = F;
+    b.nF = nF;
+    b.build_edges();
+    for (int64_t f = 0; f < nF; ++f) {
+        if (paired[(size_t)f] || !distinct(f)) continue;
+        for (int j = 0; j < 3; ++j) {
+            const int32_t g = b.nbr[3 * (size_t)f + j];
+            if (g < 0 || g == f || paired[(size_t)g] || !distinct(g) || shared(f, g) != 2) continue;
+            paired[(size_t)f] = paired[(size_t)g] = 1;
+            out.push_back((int32_t)f);
+            out.push_back(g);
+            break;
+        }
+    }
+    for (int64_t f = 0; f < nF; ++f)
+        if (!paired[(size_t)f]) {
+            out.push_back((int32_t)f);
+            out.push_back(-1);
+        }
+    return (int64_t)(out.size() / 2);
+}
+
 }  // namespace wn

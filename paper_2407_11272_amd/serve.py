@@ -370,12 +370,14 @@ class GpuExecutor:
     the forward stream, and the loss of requests whose forward completed and adjoint
     units on a second stream after that forward; completion times from timing events."""
 
-    def __init__(self, device="cuda", graph: bool = True, strips: bool = True, keep_dLdT: bool = False):
+    def __init__(self, device="cuda", graph: bool = True, strips: bool = True, keep_dLdT: bool = False,
+                 face_pairs: bool = True):
         import concurrent.futures
         import torch
         self.torch = torch
         self.strips = strips
         self.keep_dLdT = keep_dLdT   # also return per-corner dL/dT of gradient requests
+        self.face_pairs = face_pairs  # gradient requests' adjoint with two faces per lane
         self.dev = torch.device(device)
         self.fwd = torch.cuda.Stream(self.dev)
         self.aux = torch.cuda.Stream(self.dev)   # losses and adjoint units (default priority)
@@ -387,11 +389,14 @@ class GpuExecutor:
         # call that releases the interpreter lock), off the loop that keeps the GPU fed
         self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=2)
         self.strip_jobs = {}
+        self.pair_jobs = {}
 
     def prepare(self, req: ServeRequest):
         import paper_2407_11272_amd as wn
         if self.strips and len(req.F):
             self.strip_jobs[req.rid] = self.pool.submit(wn.wn_build_strips, req.F, len(req.V))
+        if self.face_pairs and req.wants_grad and len(req.F):
+            self.pair_jobs[req.rid] = self.pool.submit(wn.wn_build_face_pairs, req.F, len(req.V))
 
     def start(self, t0: float):
         torch = self.torch
@@ -426,7 +431,14 @@ class GpuExecutor:
                 st["target"] = T.to(self.dev, non_blocking=True)
                 st["hold"] = (V, F, T)
                 st["dLdW"] = torch.empty(req.points, dtype=torch.float32, device=self.dev)
-                st["adj"] = wn.SlicedBackward(st["V"], st["F"], grid=job.grid)
+                pairs = None
+                if self.face_pairs and len(req.F):
+                    pj = self.pair_jobs.pop(req.rid, None)
+                    ph = pj.result() if pj is not None else wn.wn_build_face_pairs(req.F, len(req.V))
+                    Ph = torch.from_numpy(ph).pin_memory()
+                    pairs = Ph.to(self.dev, non_blocking=True)
+                    st["hold_pairs"] = Ph
+                st["adj"] = wn.SlicedBackward(st["V"], st["F"], grid=job.grid, pairs=pairs)
                 if self.keep_dLdT:
                     st["dLdT"] = torch.empty((len(req.F), 3, 3), dtype=torch.float32, device=self.dev)
         return st

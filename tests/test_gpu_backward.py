@@ -288,10 +288,10 @@ def test_sliced_adjoint_point_list_and_argument_errors(dev, orc):
     base = p(ws.data_ptr() + (-ws.data_ptr()) % 256)
     dV = torch.empty_like(Vt)
 
-    def call(p0, n, flags=0, wsb=need, dLdV=dV):
-        return lib.wn_backward_range(p(Vt.data_ptr()), 9, p(Ft.data_ptr()), 4, None, p(Qt.data_ptr()), 1000,
-                                     p(gt.data_ptr()), p0, n, flags, p(dLdV.data_ptr()) if dLdV is not None
-                                     else None, None, base, wsb, s)
+    def call(p0, n, flags=0, wsb=need, dLdV=dV, pairs=None, n_pairs=0):
+        return lib.wn_backward_range(p(Vt.data_ptr()), 9, p(Ft.data_ptr()), 4, pairs, n_pairs, None,
+                                     p(Qt.data_ptr()), 1000, p(gt.data_ptr()), p0, n, flags,
+                                     p(dLdV.data_ptr()) if dLdV is not None else None, None, base, wsb, s)
 
     assert call(0, 0, L.WN_BWD_BEGIN) == L.WN_OK
     assert call(100, 256) == L.WN_ERR_INVALID_ARG          # p0 not on a tile boundary
@@ -301,4 +301,80 @@ def test_sliced_adjoint_point_list_and_argument_errors(dev, orc):
     assert call(0, 256, 4) == L.WN_ERR_INVALID_ARG         # unknown flag
     assert call(0, 0, L.WN_BWD_END, dLdV=None) == L.WN_ERR_INVALID_ARG
     assert call(0, 256, wsb=need - 1) == L.WN_ERR_WORKSPACE
+    pr = torch.tensor([[0, 3], [1, 2]], dtype=torch.int32, device="cuda")
+    assert call(0, 256, pairs=p(pr.data_ptr()), n_pairs=1) == L.WN_ERR_INVALID_ARG   # fewer than nF / 2 entries
+    assert call(0, 256, pairs=p(pr.data_ptr()), n_pairs=5) == L.WN_ERR_INVALID_ARG   # more than nF
+    assert call(0, 256, pairs=None, n_pairs=2) == L.WN_ERR_INVALID_ARG
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("case", ["closed", "open"])
+def test_face_pair_adjoint_matches_one_face_per_lane_and_the_oracle(dev, orc, case):
+    """Two faces per lane (wn_build_face_pairs): the same per-face arithmetic as one face
+    per lane, so dL/dT within 5e-4 of its scale of that kernel's; both against the oracle
+    (bars (i) and (ii)) on the differentiable workload at 64^3 (the open variant has
+    unpaired faces at its holes); consecutive ranges give the same bits as one call."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable(res=64, open_variant=(case == "open"))
+    Wr, Lr, g32, Q = _oracle_dLdW(orc, c)
+    Vt, Ft = _to_dev(c)
+    g = torch.as_tensor(g32).cuda()
+    pairs_h = wn.wn_build_face_pairs(c.F, len(c.V))
+    pairs = torch.as_tensor(pairs_h).cuda()
+    print(f"[pairs {case}] {len(c.F)} faces -> {len(pairs_h)} lanes, {(pairs_h[:, 1] < 0).sum()} unpaired", flush=True)
+    D1, T1 = wn.wn_backward(Vt, Ft, g, grid=c.grid, want_dLdT=True)
+    D2, T2 = wn.wn_backward(Vt, Ft, g, grid=c.grid, want_dLdT=True, pairs=pairs)
+    assert wn.wn_get_device_error() == 0
+    sb = wn.SlicedBackward(Vt, Ft, grid=c.grid, pairs=pairs)
+    sb.begin()
+    P = c.grid.size
+    cut = [0, 256 * 7, 256 * 400, 256 * 401, P]
+    for a, b in zip(cut[:-1], cut[1:]):
+        sb.points(a, b - a, g)
+    T3 = torch.empty_like(T2)
+    D3 = sb.end(dLdT=T3)
+    torch.cuda.synchronize()
+    assert torch.equal(D3, D2) and torch.equal(T3, T2)
+    T1n, T2n = T1.cpu().numpy().astype(np.float64), T2.cpu().numpy().astype(np.float64)
+    scale = np.abs(T1n).max()
+    print(f"[pairs {case}] |pairs - one face per lane| / scale = {np.abs(T2n - T1n).max() / scale:.2e}", flush=True)
+    # the same per-face formula, rounded differently (E's sum order, contractions); the
+    # sums over 262 144 points cancel, which amplifies the difference
+    assert np.abs(T2n - T1n).max() <= 5e-4 * scale
+    Tr, Dr = orc.grad(_f32(c.V), c.F, Q, g32.astype(np.float64))
+    _check_T(T2n.reshape(-1), Tr.reshape(-1), f"pairs {case} dL/dT")
+    _check_V(D2.cpu().numpy().astype(np.float64), Dr, Tr, c.F, f"pairs {case} dL/dV")
+
+
+def test_face_pairs_that_break_the_rules_are_reported(dev):
+    """A face left out of the pairs, a face given twice, and a pair without a shared edge
+    are recorded as bad indices; a valid list is not."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config1_icosphere(res=8)
+    Vt, Ft = wn.as_mesh(torch.as_tensor(c.V), torch.as_tensor(c.F))
+    g = torch.ones(c.grid.size, device="cuda")
+    P = wn.wn_build_face_pairs(c.F, len(c.V))
+    missing = P.copy()
+    i = int(np.nonzero(missing[:, 1] >= 0)[0][0])
+    missing[i, 1] = -1                                  # face g of pair i appears nowhere
+    twice = P.copy()
+    twice[i, 1] = twice[i + 1, 0]                       # a face in two pairs
+    for name, pp, expect in (("valid", P, 0), ("missing", missing, wn._lib.WN_ERR_BAD_INDEX),
+                             ("twice", twice, wn._lib.WN_ERR_BAD_INDEX)):
+        d = wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=torch.as_tensor(pp).cuda())
+        assert wn.wn_get_device_error() == expect, name
+        assert torch.isfinite(d).all() or expect != 0
+    # a pair of two faces that share no edge keeps only its first face: reported
+    bad = P.copy()
+    a0 = int(bad[i, 0])
+    b0 = next(k for k in range(len(c.F)) if not (set(c.F[k].tolist()) & set(c.F[a0].tolist())))
+    rows = np.nonzero((bad == b0).any(axis=1))[0]
+    r = int(rows[0])
+    partner = bad[r, 1] if bad[r, 0] == b0 else bad[r, 0]
+    other = bad[i, 1]
+    bad[i] = [a0, b0]
+    bad[r] = [partner, other] if partner >= 0 else [other, -1]
+    d = wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=torch.as_tensor(bad).cuda())
+    assert wn.wn_get_device_error() == wn._lib.WN_ERR_BAD_INDEX

@@ -116,7 +116,7 @@ def test_budget_rejection_on_device(dev):
 
 def test_degenerate_requests_on_device(dev):
     """No faces, an empty grid, a one-voxel grid: every request completes; gradients
-    equal wn_backward run directly on the request's own dL/dW."""
+    equal wn_backward (with the same face pairs) run directly on the request's own dL/dW."""
     import torch
     import paper_2407_11272_amd as wn
     from paper_2407_11272_amd.serve import ServeRequest
@@ -139,7 +139,8 @@ def test_degenerate_requests_on_device(dev):
     for r, o in zip(reqs[3:], out[3:]):
         Vd, Fd = wn.as_mesh(torch.as_tensor(r.V), torch.as_tensor(r.F))
         loss, dLdW = wn.wn_sigmoid_mse(o.W.reshape(-1), torch.as_tensor(r.target).cuda(), r.tau, r.k)
-        D = wn.wn_backward(Vd, Fd, dLdW, grid=wn.Grid.of(r.grid))
+        pairs = torch.as_tensor(wn.wn_build_face_pairs(r.F, len(r.V))).cuda()  # as the server does
+        D = wn.wn_backward(Vd, Fd, dLdW, grid=wn.Grid.of(r.grid), pairs=pairs)
         torch.cuda.synchronize()
         assert torch.equal(D, o.dLdV) and torch.equal(loss, o.loss)
     assert float(out[4].dLdV.abs().max()) > 0.0
