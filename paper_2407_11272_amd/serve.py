@@ -14,9 +14,12 @@ caller wants d(loss)/d(vertices)).  The loop
     workspace and are added in split order at the end);
   * every scheduler step spends a bounded amount of work.  Under the default
     earliest-deadline policy each request gets a deadline at admission (its arrival
-    plus a slack proportional to its estimated service time) and the step's budget goes
-    to requests in deadline order, so short requests overtake long ones while a long
-    request, once its deadline is the earliest, is not starved.  Under the share
+    plus a slack proportional to its estimated service time, capped) and the step's
+    budget goes to requests in deadline order, so short requests overtake long ones
+    while a long request, once its deadline is the earliest, is not starved.  The cap
+    bounds how long the longest requests can be overtaken: requests arriving more than
+    the cap after one of them queue behind it, as they would in arrival order, which
+    keeps the tail of the latency distribution from growing past plain FIFO's.  Under the share
     policies every request gets a slice in proportion to a weight (equal, or growing
     with its age).  All forward slices of a step run in ONE batched persistent launch;
     the step's losses and adjoint units follow it on a second stream, overlapping with
@@ -44,8 +47,9 @@ POLICY = "edf"            # "edf": earliest deadline first; "fair": equal shares
 AGE_TAU = 0.25            # seconds of waiting that double a request's share under "age"
 ADJOINT_COST = 2.8        # cost of one adjoint (point, face) pair in forward pairs
 RATE_PAIRS = 1.4e12       # forward pairs per second, for the deadline estimate
-DEADLINE_SLACK = 1.0      # deadline = arrival + DEADLINE_SLACK * estimated service + DEADLINE_BASE
+DEADLINE_SLACK = 2.0      # deadline = arrival + min(DEADLINE_SLACK * estimated service, DEADLINE_CAP) + DEADLINE_BASE
 DEADLINE_BASE = 0.05      # seconds
+DEADLINE_CAP = 1.5        # seconds: past this, a long request is no longer overtaken by later arrivals
 
 
 @dataclass
@@ -151,7 +155,7 @@ class Server:
                  quantum_pairs: float = STEP_PAIRS, max_inflight: int = 2, clock=time.perf_counter,
                  policy: str | None = None, adjoint_cost: float = ADJOINT_COST, rate_pairs: float = RATE_PAIRS,
                  deadline_slack: float = DEADLINE_SLACK, deadline_base: float = DEADLINE_BASE,
-                 admit_ms: float = 4.0):
+                 deadline_cap: float = DEADLINE_CAP, admit_ms: float = 4.0):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.slots = int(slots)
@@ -165,6 +169,7 @@ class Server:
         self.rate = float(rate_pairs)
         self.slack = float(deadline_slack)
         self.base = float(deadline_base)
+        self.cap = float(deadline_cap)
         # host time per step for admissions (at least one is admitted): each uploads a mesh
         # (and a gradient request its target), so a burst of large arrivals is spread over
         # steps while the GPU works on those already admitted, and small ones still enter
@@ -201,7 +206,7 @@ class Server:
         if req.wants_grad:
             a.adj_unit = adjoint_unit(nF, P)
             work += self.adj_cost * P * nF
-        a.deadline = req.arrival + self.slack * work / self.rate + self.base
+        a.deadline = req.arrival + min(self.slack * work / self.rate, self.cap) + self.base
         prep = getattr(self.ex, "prepare", None)
         if prep is not None:
             prep(req)   # host-side work that can start before admission (strip order)
@@ -294,13 +299,22 @@ class Server:
                 left -= spent
         return fwd, fdone, adj
 
-    def step(self) -> bool:
+    def step(self, intake=None) -> bool:
         """Admit, launch one step (a batched forward launch and adjoint units), retire
-        completed requests.  Returns False when there is nothing left to do."""
+        completed requests.  Returns False when there is nothing left to do.
+
+        When there is work to launch, the host first waits until fewer than
+        ``max_inflight`` steps are queued on the device, then calls ``intake`` (which
+        submits the requests that arrived meanwhile), admits and plans: the plan sees
+        every arrival up to the moment it is launched, so a short request that arrives
+        while a long one runs waits for at most the steps already queued."""
+        if self.pending or any(not a.all_launched for a in self.active):
+            self.ex.wait_inflight(self.max_inflight - 1)
+        if intake is not None:
+            intake()
         self._admit(self.clock() - self.t0)
         fwd, fdone, adj = self._plan()
         if fwd or fdone or adj:
-            self.ex.wait_inflight(self.max_inflight - 1)
             self.ex.launch_step([(a.state, a.req, p0, n) for a, p0, n in fwd],
                                 [(a.state, a.req) for a in fdone],
                                 [(a.state, a.req, p0, n, last) for a, p0, n, last in adj])
@@ -335,12 +349,17 @@ class Server:
         self.t0 = t0
         self.ex.start(t0)
         i = 0
-        while i < len(reqs) or self.active or self.pending:
+
+        def intake():
+            nonlocal i
             now = self.clock() - t0
             while i < len(reqs) and reqs[i].arrival <= now:
                 self.submit(reqs[i])
                 i += 1
-            busy = self.step()
+
+        while i < len(reqs) or self.active or self.pending:
+            intake()
+            busy = self.step(intake)
             if not busy and i < len(reqs):
                 self.ex.idle(min(idle_sleep, max(0.0, reqs[i].arrival - (self.clock() - t0))))
             elif busy and all(a.all_launched for a in self.active):

@@ -244,6 +244,41 @@ def test_edf_large_gradient_request_is_not_starved():
     assert any(set(s) - {0} for s in ex.steps[k0:k1 + 1])
 
 
+def test_edf_deadline_cap_stops_overtaking_of_a_long_request():
+    """Under the deadline policy a long request's slack is capped: a short request that
+    arrives early in its run overtakes it, one that arrives after the cap has passed
+    queues behind it (as it would in arrival order)."""
+    big = _req(0, 102400, 256, 0.0)   # about 3.4 s of device time at the simulated rate
+    early = _req(1, 2000, 64, 0.2)
+    late = _req(2, 2000, 64, 1.0)
+    q = 48 * 2048 * 102400            # a step is exactly one slice of the long request
+    srv, ex, out = _run([big, early, late], slots=8, quantum_pairs=q, policy="edf",
+                        deadline_slack=2.0, deadline_cap=0.5, deadline_base=0.0)
+    res = {r.rid: r for r in out}
+    assert res[1].done < res[0].done
+    assert res[2].done >= res[0].done   # (it may share the long one's last step)
+    # without the cap both overtake
+    srv, ex, out = _run([big, early, late], slots=8, quantum_pairs=q, policy="edf",
+                        deadline_slack=2.0, deadline_cap=float("inf"), deadline_base=0.0)
+    res = {r.rid: r for r in out}
+    assert res[1].done < res[0].done and res[2].done < res[0].done
+
+
+def test_plan_sees_arrivals_made_while_the_host_waited():
+    """The host waits for a queued step before it plans the next one, and takes in the
+    requests that arrived during that wait: a short request arriving while a long one
+    runs is in the first step launched after its arrival."""
+    big = _req(0, 100000, 256, 0.0)
+    small = _req(1, 2000, 64, 0.105)
+    srv, ex, out = _run([big, small], slots=8, quantum_pairs=1e10, policy="edf", max_inflight=2)
+    step_time = 1e10 / ex.rate + ex.overhead
+    first = min(k for _, _, k in ex.slices[1])
+    # the step running when it arrived and the one queued behind it, then its own
+    res = {r.rid: r for r in out}
+    assert res[1].latency < 3 * step_time
+    assert first <= int(0.105 / step_time) + 2
+
+
 def test_idle_server_returns():
     srv, ex, out = _run([], slots=2)
     assert out == [] and srv.steps == 0
