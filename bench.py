@@ -43,7 +43,8 @@ PEAK_HBM = 8.0e12
 # Sources that define each profiled kernel (its code and everything it inlines).
 KERNEL_SOURCES = {"k_wn_fwd": ("wn_internal.hpp", "wn_fwd.hip"),
                   "k_batched_persistent": ("wn_internal.hpp", "wn_batched.hip"),
-                  "k_wn_bwd": ("wn_internal.hpp", "wn_bwd.hip")}
+                  "k_wn_bwd": ("wn_internal.hpp", "wn_bwd.hip"),
+                  "k_wn_bwd_pairs": ("wn_internal.hpp", "wn_bwd_pairs.hip")}
 
 
 def source_hash(kernel: str = "k_wn_fwd") -> str:
@@ -177,21 +178,29 @@ def bench_adjoint(steps, warmup):
         wn.wn_sigmoid_mse(W, T, 0.5, 50.0, loss=loss, dLdW=dLdW)
         wn.wn_backward(V, F, dLdW, grid=grid, dLdV=dLdV, pairs=pairs)
 
+    def adj():
+        wn.wn_backward(V, F, dLdW, grid=grid, dLdV=dLdV, pairs=pairs)
+
     n = max(2, steps)
     f_s, _ = time_steps(fwd, n, 1, stream)
     s_s, _ = time_steps(step, n, max(1, warmup), stream)
-    pairs = grid.size * len(c.F)
+    a_s, _ = time_steps(adj, n, 1, stream)
+    npairs = grid.size * len(c.F)
     bwd_s = max(s_s - f_s, 1e-12) / n
-    return {
+    out = {
         "workload": "icosphere-s4-5120f-64cube sigmoid(k=50) MSE, forward+loss+adjoint (two faces per lane)",
-        "pairs_per_pass": pairs,
+        "pairs_per_pass": npairs,
         "ms_per_step": s_s / n * 1e3,
         "fwd_ms": f_s / n * 1e3,
         "bwd_ms": bwd_s * 1e3,
-        "adjoint_pairs_per_s": pairs / bwd_s,
-        "adjoint_frac_fp32_peak": pairs / bwd_s * FLOP_BWD / PEAK_FP32,
-        "step_pairs_per_s": 2 * pairs / (s_s / n),
+        "adjoint_pairs_per_s": npairs / bwd_s,
+        "adjoint_frac_fp32_peak": npairs / bwd_s * FLOP_BWD / PEAK_FP32,
+        "step_pairs_per_s": 2 * npairs / (s_s / n),
+        # the adjoint call alone (pack, the two-faces-per-lane kernel, split and vertex sums)
+        "adjoint_call_ms": a_s / n * 1e3,
+        "roofline": roofline("k_wn_bwd_pairs", "c3", npairs, a_s / n, FLOP_BWD),
     }
+    return out
 
 
 def batch_jobs():
@@ -691,7 +700,9 @@ def summary(out) -> dict:
     if "adjoint" in r:
         a = r["adjoint"]
         s["adjoint_c3"] = {"pairs_per_s": a["adjoint_pairs_per_s"], "frac": round(a["adjoint_frac_fp32_peak"], 4),
-                           "ms": round(a["bwd_ms"], 3)}
+                           "ms": round(a["bwd_ms"], 3), "call_frac": round(a["roofline"]["frac"], 4)}
+        if "hw_frac" in a["roofline"]:
+            s["adjoint_c3"]["hw_frac"] = round(a["roofline"]["hw_frac"], 4)
     if "served" in r:
         s["served_c5"] = [{"load": x["load"], "p50_ms": [round(x["served"]["p50_ms"]), round(x["plain_fifo"]["p50_ms"])],
                            "p99_ms": [round(x["served"]["p99_ms"]), round(x["plain_fifo"]["p99_ms"])]}

@@ -457,6 +457,17 @@ int loss_blocks(int64_t n);
 // per corner in the workspace, and the splits are added in split order at the end.  A
 // call sequence BEGIN, consecutive point ranges of whole tiles in increasing order, END
 // therefore gives the same bits as one call over all points.
+// Two faces per lane (wn_bwd_pairs.hip): 80-byte pair records and 16-byte pair metadata
+// in the adjoint's workspace; pack (with the every-face-once check), the point-split
+// kernel over tiles [t0, t1), and the reduction of the 18 running sums per pair into T.
+constexpr size_t kPairRecBytes = 80, kPairMetaBytes = 16;
+hipError_t launch_pack_pairs(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *pairs, int64_t nP,
+                             char *recs, char *meta, int32_t *counts, WsHeader *hdr, hipStream_t s);
+hipError_t launch_bwd_pairs(const char *recs, const char *meta, int32_t nP, int32_t nF, const PointSrc &ps, int64_t nQ,
+                            int32_t S, int64_t t0, int64_t t1, int32_t rows, const float *dLdW, float2 *state,
+                            hipStream_t s);
+hipError_t launch_reduce_pairs(const float2 *state, int32_t S, int32_t nP, const char *meta, float scale, float *T,
+                               hipStream_t s);
 constexpr int kBwdBegin = 1, kBwdEnd = 2;
 constexpr int kBwdTile = 256;
 int bwd_splits(int64_t nF, int64_t nQ);
