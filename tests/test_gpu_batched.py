@@ -141,7 +141,8 @@ def test_autotune_does_not_change_results(dev, tmp_path, monkeypatch):
 
 def test_full_batch_64_meshes(dev, orc):
     """64 meshes of 500-50k faces at 32^3/64^3/128^3 in one launch: every mesh against the
-    plain launch, eight meshes against the oracle on 300 seeded voxels each."""
+    plain launch, and every mesh against the oracle on 1024 seeded voxels (65 536 voxels,
+    about 6e8 point-face pairs), W within 1e-4 outside the guard band."""
     import torch
     import paper_2407_11272_amd as wn
     ws = wi.config4_batch()
@@ -154,14 +155,18 @@ def test_full_batch_64_meshes(dev, orc):
         worst = max(worst, float(np.abs(Wp - Wb[i]).max()))
     print(f"[C4] max |batched - plain| = {worst:.2e}", flush=True)
     assert worst <= 2e-6
-    for i in rng.choice(len(ws), 8, replace=False):
-        w = ws[i]
+    worst, guarded = 0.0, 0
+    for i, w in enumerate(ws):
         Q = orc.grid_points(w.grid)
-        idx = rng.choice(len(Q), 300, replace=False)
+        idx = rng.choice(len(Q), 1024, replace=False)
         V64 = np.asarray(w.V, np.float32).astype(np.float64)
         Wr = orc.winding(V64, w.F, Q[idx])
         guard = orc.guard_mask(V64, w.F, Q[idx])
-        assert np.abs(Wb[i][idx] - Wr)[~guard].max() <= 1e-4
+        guarded += int(guard.sum())
+        worst = max(worst, float(np.abs(Wb[i][idx] - Wr)[~guard].max()))
+    print(f"[C4 vs oracle] 64 meshes x 1024 voxels: max |dW| = {worst:.2e} off the guard band "
+          f"({guarded} guarded)", flush=True)
+    assert worst <= 1e-4 and guarded <= 1e-3 * 64 * 1024
     torch.cuda.synchronize()
 
 
