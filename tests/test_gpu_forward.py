@@ -72,12 +72,15 @@ def test_config1_full_grid(dev, orc):
     assert 0.05 < (Wr > 0.5).mean() < 0.5
 
 
-def test_config2_full_size_strided(dev, orc):
+def test_config2_full_grid(dev, orc):
     """Non-watertight union (19 000 faces) at 128^3 on the path the benchmark times: the
     triangle-strip order, after the autotuner has picked the launch configuration.  Every
-    16th voxel (131 072 of 2 097 152, a deterministic stride through every slab of the
-    grid) plus the last is held to the oracle: W within 1e-4 outside the guard band, the
-    guard band at most 1e-4 of the points, occupancy bit-identical off the band."""
+    one of the 2 097 152 voxels is held to the oracle (4e10 FP64 point-face pairs, about
+    a minute on 16 host threads): W within 1e-4 wherever a point is not in the guard band
+    (the guard band is evaluated for the points that miss the bar, which must all be in
+    it, at most 1e-4 of the grid), and the occupancy bit-identical to the oracle's
+    wherever |W - 0.5| > 1e-3 off those points."""
+    import time
     import torch
     import paper_2407_11272_amd as wn
     c = wi.config2_ellipsoid_union()
@@ -90,11 +93,19 @@ def test_config2_full_size_strided(dev, orc):
     W, occ = wn.wn_voxelize_strips(V, F, R, grid=grid, occupancy="threshold")
     Wg, og = W.cpu().numpy().reshape(-1), occ.cpu().numpy().reshape(-1)
     assert Wg.shape == (128 ** 3,) and np.isfinite(Wg).all()
-    idx = np.unique(np.concatenate([np.arange(0, len(Wg), 16), [len(Wg) - 1]]))
-    assert len(idx) >= 131072
-    Q = orc.grid_points(c.grid)[idx]
-    Wr, guard = _compare(orc, c.V, c.F, Q, Wg[idx], "C2 every 16th voxel, strips", occ_g=og[idx])
-    assert guard.sum() <= 1e-4 * len(idx)
+    t0 = time.perf_counter()
+    V64 = np.asarray(c.V, np.float32).astype(np.float64)
+    Wr = orc.winding_grid(V64, c.F, c.grid)
+    miss = np.abs(Wg - Wr) > TOL_W
+    Q = orc.grid_points(c.grid)
+    guard = orc.guard_mask(V64, c.F, Q[miss]) if miss.any() else np.zeros(0, bool)
+    print(f"[C2 full grid, strips] oracle {time.perf_counter() - t0:.0f} s; max |dW| = "
+          f"{np.abs(Wg - Wr)[~miss].max():.2e} on {int((~miss).sum())} points, {int(miss.sum())} beyond 1e-4 "
+          f"(all in the guard band: {bool(guard.all())})", flush=True)
+    assert guard.all() and miss.sum() <= 1e-4 * len(Wg)
+    off = (np.abs(Wr - 0.5) > BAND) & ~miss
+    np.testing.assert_array_equal(og[off], orc.occupancy_threshold(Wr, 0.5)[off])
+    assert off.mean() > 0.99
 
 
 def test_largest_served_request_sampled(dev, orc):
