@@ -22,6 +22,8 @@
 //     and summed in face order -- deterministic throughout.  A split's running sums
 //     live in the workspace between calls, so the adjoint can also be computed over
 //     consecutive point ranges (the served loop's units) with the same bits.
+// With a face-pair list the point loop runs two faces per lane instead
+// (wn_bwd_pairs.hip); the split reduction and the vertex gather here are shared.
 #include <algorithm>
 #include <cstring>
 

@@ -138,13 +138,14 @@ def footprint_bytes(req: ServeRequest, slice_points: int) -> int:
     chunks = max(1, -(-nF // 4096))
     b += 48 * nF + (4 * chunks * min(P, slice_points) if chunks > 1 else 0)
     if req.wants_grad:
-        # target, dL/dW, dL/dV, and the adjoint's own workspace (face records, the splits'
-        # running corner sums, corner sort buffers, vertex bounds)
+        # target, dL/dW, dL/dV, the face-pair list (at most 2 int32 per face), and the
+        # adjoint's own workspace (face or pair records, the splits' running corner sums,
+        # corner sort buffers, vertex bounds)
         from . import _lib as L
         ws = _lib().wn_workspace_size(L.WN_OP_BACKWARD, nV, nF, P)
         if ws == 0:
             raise ValueError("sizes out of range for the adjoint")
-        b += 8 * P + 12 * nV + int(ws) + 512
+        b += 8 * P + 12 * nV + 8 * nF + int(ws) + 512
     return int(b)
 
 
