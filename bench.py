@@ -282,6 +282,15 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
                for r in base}
     skip = set(sorted(res_of, key=lambda i: base[i].arrival)[:int(warmup_frac * len(base))])
     sweep = []
+    last = [time.perf_counter()]
+
+    def progress(label):
+        def tick(done, total):  # a line every 30 s, so that long low-load runs show progress
+            now = time.perf_counter()
+            if now - last[0] >= 30.0:
+                last[0] = now
+                print(f"# {label}: {done}/{total} requests submitted", file=sys.stderr, flush=True)
+        return tick
     for load in loads:
         rate = load / mean_gpu_s
         reqs = [ServeRequest(r.rid, w.V.astype(np.float32), w.F.astype(np.int32), w.grid, r.arrival / rate,
@@ -305,14 +314,14 @@ def bench_served(n_requests: int, loads, fwd_pairs_per_s: float, adj_pairs_per_s
         srv = Server(GpuExecutor(), hbm_budget=int(torch.cuda.get_device_properties(0).total_memory * 0.5),
                      slots=16, quantum_pairs=step_pairs, policy=policy, adjoint_cost=fwd_pairs_per_s / adj_pairs_per_s,
                      rate_pairs=fwd_pairs_per_s)
-        served = srv.run_trace(reqs)
+        served = srv.run_trace(reqs, progress=progress(f"served load {load}"))
         s_stats = summary(served)
         s_stats["steps"] = srv.steps
         s_stats["peak_active"] = srv.peak_active
         del served
         torch.cuda.synchronize()
         print(f"# served load {load}: plain FIFO", file=sys.stderr, flush=True)
-        p_stats = summary(run_plain_fifo(reqs))
+        p_stats = summary(run_plain_fifo(reqs, progress=progress(f"plain FIFO load {load}")))
         sweep.append({"load": load, "rate_req_per_s": rate, "served": s_stats, "plain_fifo": p_stats,
                       "p50_speedup": p_stats["p50_ms"] / s_stats["p50_ms"],
                       "p99_speedup": p_stats["p99_ms"] / s_stats["p99_ms"]})

@@ -343,8 +343,9 @@ class Server:
                 self.ex.idle(idle_sleep)
 
     # ------------------------------------------------------------ trace driver
-    def run_trace(self, requests, idle_sleep: float = 2e-4):
-        """Replay ``requests`` (sorted by arrival, seconds from now) in real time."""
+    def run_trace(self, requests, idle_sleep: float = 2e-4, progress=None):
+        """Replay ``requests`` (sorted by arrival, seconds from now) in real time.
+        ``progress(submitted, total)``, if given, is called once per loop pass."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         t0 = self.clock()
         self.t0 = t0
@@ -361,6 +362,8 @@ class Server:
         while i < len(reqs) or self.active or self.pending:
             intake()
             busy = self.step(intake)
+            if progress is not None:
+                progress(i, len(reqs))
             if not busy and i < len(reqs):
                 self.ex.idle(min(idle_sleep, max(0.0, reqs[i].arrival - (self.clock() - t0))))
             elif busy and all(a.all_launched for a in self.active):
@@ -532,10 +535,10 @@ class GpuExecutor:
         self.torch.cuda.synchronize(self.dev)
 
 
-def run_plain_fifo(requests, device="cuda", keep_results: bool = False, strips: bool = True):
+def run_plain_fifo(requests, device="cuda", keep_results: bool = False, strips: bool = True, progress=None):
     """Baseline: the same trace, FIFO, one mesh per launch (the same forward kernel on
     the same strip order, then the loss and wn_backward for gradient requests), on one
-    stream; completion from events."""
+    stream; completion from events.  ``progress(submitted, total)`` as in run_trace."""
     import torch
     import paper_2407_11272_amd as wn
     dev = torch.device(device)
@@ -550,9 +553,13 @@ def run_plain_fifo(requests, device="cuda", keep_results: bool = False, strips: 
     out = []
     pend = []
     with torch.cuda.stream(s):
-        for r in reqs:
+        for n, r in enumerate(reqs):
             while time.perf_counter() - t0 < r.arrival:
                 time.sleep(2e-4)
+                if progress is not None:
+                    progress(n, len(reqs))
+            if progress is not None:
+                progress(n + 1, len(reqs))
             V = torch.from_numpy(np.ascontiguousarray(r.V, dtype=np.float32)).pin_memory().to(dev, non_blocking=True)
             F = torch.from_numpy(np.ascontiguousarray(r.F, dtype=np.int32)).pin_memory().to(dev, non_blocking=True)
             if strips and len(r.F):
