@@ -5,6 +5,8 @@ Remez exchange algorithm to minimise the maximum *relative* error
 |t P(t^2) - atan t| / atan t (weight 1 / f with f(x) = atan(sqrt x) / sqrt x).
 Relative error keeps small angles (far faces) proportionally accurate.
 
+The kernels use degree 6 (the default here).
+
 Run:  python gen_atan_poly.py [degree]  -> prints the coefficients (FP32-rounded,
 highest degree first) and the max relative error of an FP32 Horner evaluation.
 """
@@ -68,7 +70,7 @@ def fp32_check(p):
 
 
 if __name__ == "__main__":
-    n = int(sys.argv[1]) if len(sys.argv) > 1 else 7
+    n = int(sys.argv[1]) if len(sys.argv) > 1 else 6
     p, e = remez(n)
     p32 = [float(np.float32(c)) for c in p]
     rel, ab = fp32_check(p32)

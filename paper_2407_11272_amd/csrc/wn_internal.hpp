@@ -68,18 +68,20 @@ static_assert(sizeof(WsHeader) == kWsHeader, "header size");
 // ---------------------------------------------------------------- device math
 
 // atan(t) for t in [0, 1] as t P(t^2): minimax in relative error (Remez exchange,
-// degree 7 in t^2; coefficients from gen_atan_poly.py, max relative error 2.2e-7
-// when evaluated in FP32).
+// degree 6 in t^2; coefficients from gen_atan_poly.py, max relative error 7.6e-7 and
+// absolute error 5.9e-7 when evaluated in FP32).  The polynomial's share of the error in
+// W is at most 7.6e-7 times the sum of |angle| / 2 pi over a point's faces: about 8e-7
+// per closed surface around the point, 6e-6 inside eight stacked shells even with every
+// error of one sign, against the 1e-4 bar.  Degree 7 (2.2e-7) cost one more FMA per ATAN2.
 __device__ __forceinline__ float atan_unit(float t) {
     const float x = t * t;
-    float p = -0.0046932762f;
-    p = __builtin_fmaf(p, x, 0.024252404f);
-    p = __builtin_fmaf(p, x, -0.059486393f);
-    p = __builtin_fmaf(p, x, 0.09914293f);
-    p = __builtin_fmaf(p, x, -0.1401948f);
-    p = __builtin_fmaf(p, x, 0.19969724f);
-    p = __builtin_fmaf(p, x, -0.3333199f);
-    p = __builtin_fmaf(p, x, 0.9999999f);
+    float p = 0.007863377f;
+    p = __builtin_fmaf(p, x, -0.037013f);
+    p = __builtin_fmaf(p, x, 0.08387119f);
+    p = __builtin_fmaf(p, x, -0.13487191f);
+    p = __builtin_fmaf(p, x, 0.19881482f);
+    p = __builtin_fmaf(p, x, -0.33326516f);
+    p = __builtin_fmaf(p, x, 0.99999934f);
     return p * t;
 }
 
