@@ -206,12 +206,19 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
  *          index (wn_get_device_error);
  *   V, F, grid / Q, nQ: the same in every call of a sequence;
  *   dLdV:  needed with WN_BWD_END; dLdT optional, as in wn_backward;
+ *   flags: may add WN_BWD_VERTEX_SUMS (in every call of a sequence, or in none) when
+ *          only dLdV is wanted: with pairs, the two faces of a pair then share their
+ *          running sums at the shared edge's two vertices (12 instead of 18 per pair and
+ *          split, fewer operations per point), so the sums per vertex stay exact up to
+ *          rounding but those per corner do not; dLdT must then be NULL at WN_BWD_END.
+ *          Without pairs it has no effect;
  *   ws:    wn_workspace_size(WN_OP_BACKWARD, nV, nF, nQ) bytes, holding the running sums.
  * A range of at least S tiles keeps every split busy (about nF / 256 x S workgroups).
  * Argument errors return WN_ERR_INVALID_ARG before any launch.
  */
 #define WN_BWD_BEGIN 1
 #define WN_BWD_END 2
+#define WN_BWD_VERTEX_SUMS 4
 #define WN_BWD_TILE 256
 WN_API wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF,
                                    const int32_t *pairs, int64_t n_pairs,

@@ -43,6 +43,7 @@ WN_NOALLOC_SCRATCH_BYTES = 96 << 20
 
 WN_BWD_BEGIN = 1
 WN_BWD_END = 2
+WN_BWD_VERTEX_SUMS = 4
 WN_BWD_TILE = 256
 
 #: every symbol include/wn.h declares

@@ -227,15 +227,19 @@ class SlicedBackward:
     """The adjoint of one (mesh, grid or point list) computed over consecutive point
     ranges in separate calls (``wn_backward_range``): :meth:`begin`, then :meth:`points`
     for ranges of whole 256-point tiles in increasing order that together cover every
-    point once, then :meth:`end`.  The result has the same bits as :func:`wn_backward`.
-    The object owns its workspace, which holds the splits' running sums between calls;
-    all calls go to the current stream of V's device."""
+    point once, then :meth:`end`.  The result has the same bits as :func:`wn_backward`
+    with the same ``pairs`` and ``vertex_sums``.  ``vertex_sums`` (with pairs): the two
+    faces of a pair share their running sums at their common vertices, which is faster
+    and gives dL/dV only (``end`` then refuses dL/dT).  The object owns its workspace,
+    which holds the splits' running sums between calls; all calls go to the current
+    stream of V's device."""
 
     def __init__(self, V, F, grid: Grid | None = None, Q: torch.Tensor | None = None,
-                 pairs: torch.Tensor | None = None):
+                 pairs: torch.Tensor | None = None, vertex_sums: bool = False):
         _check_mesh(V, F)
         self.pairs = _check_pairs(pairs, F)
         self._np = 0 if pairs is None else int(pairs.shape[0])
+        self._mode = L.WN_BWD_VERTEX_SUMS if vertex_sums else 0
         if (grid is None) == (Q is None):
             raise ValueError("pass exactly one of grid or Q")
         self.lib = L.load()
@@ -269,7 +273,7 @@ class SlicedBackward:
         g = ctypes.byref(self._gc) if self._gc is not None else None
         st = self.lib.wn_backward_range(_ptr(self.V), self.V.shape[0], _ptr(self.F), self.F.shape[0],
                                         _ptr(self.pairs), self._np, g, self._qptr, self._nQ, _ptr(dLdW), int(p0),
-                                        int(n), flags, _ptr(dLdV), _ptr(dLdT), self._ws, self._wsb,
+                                        int(n), flags | self._mode, _ptr(dLdV), _ptr(dLdT), self._ws, self._wsb,
                                         _stream_handle(self.dev))
         L.check("wn_backward_range", st)
 
@@ -295,6 +299,8 @@ class SlicedBackward:
     def end(self, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None) -> torch.Tensor:
         if self._next != self.P:
             raise ValueError(f"the ranges covered {self._next} of {self.P} points")
+        if self._mode and dLdT is not None:
+            raise ValueError("dL/dT is not available with vertex_sums")
         if dLdV is None:
             dLdV = torch.empty_like(self.V)
         self._call(None, 0, 0, L.WN_BWD_END, dLdV, dLdT)
@@ -364,10 +370,11 @@ def wn_sigmoid_mse(W: torch.Tensor, target: torch.Tensor, tau: float = 0.5, k: f
 
 def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Tensor | None = None,
                 want_dLdT: bool = False, dLdV: torch.Tensor | None = None, dLdT: torch.Tensor | None = None,
-                _entry: str = "wn_backward", pairs: torch.Tensor | None = None):
+                _entry: str = "wn_backward", pairs: torch.Tensor | None = None, vertex_sums: bool | None = None):
     """dL/dV [nV, 3] (and dL/dT [nF, 3, 3] if requested) for the given dL/dW.  With
     ``pairs`` (a device copy of :func:`wn_build_face_pairs`) two faces per lane, through
-    one wn_backward_range call."""
+    one wn_backward_range call; ``vertex_sums`` (default: when dL/dT is not wanted) lets
+    the two faces of a pair share their sums at their common vertices."""
     lib = L.load()
     _check_mesh(V, F)
     if (grid is None) == (Q is None):
@@ -388,10 +395,15 @@ def wn_backward(V, F, dLdW: torch.Tensor, grid: Grid | None = None, Q: torch.Ten
         dLdT = torch.empty((F.shape[0], 3, 3), dtype=torch.float32, device=dev)
     need = wn_workspace_size(L.WN_OP_BACKWARD, V.shape[0], F.shape[0], P)
     ws, wsb = Workspace.get(need, dev)
+    if vertex_sums is None:
+        vertex_sums = not want_dLdT
+    if vertex_sums and want_dLdT:
+        raise ValueError("dL/dT is not available with vertex_sums")
     if pairs is not None:   # the whole range in one wn_backward_range call
         pairs = _check_pairs(pairs, F)
+        flags = L.WN_BWD_BEGIN | L.WN_BWD_END | (L.WN_BWD_VERTEX_SUMS if vertex_sums else 0)
         st = lib.wn_backward_range(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(pairs), pairs.shape[0], gptr, qptr,
-                                   nQ, _ptr(dLdW), 0, P, L.WN_BWD_BEGIN | L.WN_BWD_END, _ptr(dLdV),
+                                   nQ, _ptr(dLdW), 0, P, flags, _ptr(dLdV),
                                    _ptr(dLdT if want_dLdT else None), ws, wsb, _stream_handle(dev))
         L.check("wn_backward_range", st)
         return (dLdV, dLdT) if want_dLdT else dLdV

@@ -239,6 +239,9 @@ wn_status wn_sigmoid_mse(const float *W, const float *target, int64_t n, float t
     return hip_status(launch_sigmoid_mse(W, target, n, tau, k, loss, dLdW, scratch, static_cast<hipStream_t>(stream)));
 }
 
+static_assert(kBwdBegin == WN_BWD_BEGIN && kBwdEnd == WN_BWD_END && kBwdVertexSums == WN_BWD_VERTEX_SUMS,
+              "adjoint flags");
+
 wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *pairs,
                             int64_t n_pairs, const wn_grid *grid, const float *Q, int64_t nQ, const float *dLdW,
                             int64_t p0, int64_t n, int32_t flags, float *dLdV, float *dLdT, void *ws,
@@ -247,7 +250,8 @@ wn_status wn_backward_range(const float *V, int64_t nV, const int32_t *F, int64_
     if (pairs == nullptr ? n_pairs != 0 : (n_pairs < (nF + 1) / 2 || n_pairs > nF)) return WN_ERR_INVALID_ARG;
     const int64_t P = query_count(grid, Q, nQ);
     if (P < 0) return WN_ERR_INVALID_ARG;
-    if (flags & ~(WN_BWD_BEGIN | WN_BWD_END)) return WN_ERR_INVALID_ARG;
+    if (flags & ~(WN_BWD_BEGIN | WN_BWD_END | WN_BWD_VERTEX_SUMS)) return WN_ERR_INVALID_ARG;
+    if ((flags & WN_BWD_VERTEX_SUMS) && (flags & WN_BWD_END) && dLdT != nullptr) return WN_ERR_INVALID_ARG;
     if (p0 < 0 || n < 0 || p0 > P || n > P - p0) return WN_ERR_INVALID_ARG;
     if (n > 0 && (p0 % WN_BWD_TILE != 0 || (p0 + n != P && n % WN_BWD_TILE != 0))) return WN_ERR_INVALID_ARG;
     if ((flags & WN_BWD_END) && nV > 0 && dLdV == nullptr) return WN_ERR_INVALID_ARG;

@@ -415,6 +415,7 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
     char *pmeta = ws + p.off_pmeta;
     int32_t *pcount = reinterpret_cast<int32_t *>(ws + p.off_pcount);
     const bool use_pairs = pairs != nullptr && !naive && nP > 0;
+    const bool merged = use_pairs && (flags & kBwdVertexSums);  // 12 running sums per pair
     // begin: face (or face-pair) records and the index checks for the whole call sequence
     if (flags & kBwdBegin) {
         if ((e = launch_ws_reset(hdr, s)) != hipSuccess) return WN_ERR_HIP;
@@ -435,7 +436,7 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
             e = launch_naive_bwd(soup, (int32_t)nF, ps, nQ, p.split, t0, t1, (int32_t)rows, dLdW, state, s);
         } else if (use_pairs) {
             e = launch_bwd_pairs(prec, pmeta, (int32_t)nP, (int32_t)nF, ps, nQ, S, t0, t1, (int32_t)rows, dLdW, state,
-                                 s);
+                                 merged, s);
         } else {
             k_wn_bwd<<<dim3(blocks_for(nF), (unsigned)rows), kBlock, 0, s>>>(soup, (int32_t)nF, ps, nQ, p.split, t0,
                                                                               t1, dLdW, state);
@@ -458,7 +459,8 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
     int32_t *vs = reinterpret_cast<int32_t *>(ws + p.off_vs);
     int32_t *ve = reinterpret_cast<int32_t *>(ws + p.off_ve);
     if (nQ > 0 && use_pairs) {
-        if ((e = launch_reduce_pairs(state, S, (int32_t)nP, pmeta, kInv2Pi, T, s)) != hipSuccess) return WN_ERR_HIP;
+        if ((e = launch_reduce_pairs(state, S, (int32_t)nP, pmeta, kInv2Pi, T, merged, s)) != hipSuccess)
+            return WN_ERR_HIP;
     } else if (nQ > 0) {
         k_bwd_reduce<<<blocks_for(9 * nF), kBlock, 0, s>>>(state, p.split, (int32_t)nF, naive ? kInv8Pi : kInv2Pi, T);
     } else {

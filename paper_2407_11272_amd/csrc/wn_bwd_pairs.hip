@@ -26,6 +26,7 @@ constexpr int kPointTile = kBwdTile;
 //        are (s3, s1, s2) (else (s3, s2, s1)).
 //   state: float2 (sum, compensation) [S][18][nP], per pair f's 9 corner components in
 //        rotated order, then g's by slot 1, 2, 3; k_bwd_reduce_pairs maps them to T.
+//        Merged ([S][12][nP], dL/dV only): slot 0, slots 1 and 2 of both faces, g's slot 3.
 struct PairRec {
     float4 a, b, c, d, e;
 };
@@ -115,21 +116,22 @@ __global__ __launch_bounds__(kBlock) void k_pack_pairs(const float *__restrict__
     meta[p] = PairMeta{f, g, rf | (rg << 2) | (flip << 4), 0};
 }
 
-// Nine running sums of a lane, rows[i * nP + p] (i < 9, rows wave-uniform): all nine
-// loaded, the tile's sums folded in (from zero when `first`), stored if `live`.
+// N running sums of a lane, rows[i * nP + p] (i < N, rows wave-uniform): all N loaded,
+// the tile's sums t[0..N) folded in (from zero when `first`), stored if `live`.
+template <int N>
 __device__ __forceinline__ void fold_rows(float2 *__restrict__ rows, int32_t nP, int32_t p, bool live, bool first,
-                                          const float (&t)[9]) {
-    float2 x[9];
+                                          const float *t) {
+    float2 x[N];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) x[i] = rows[(int64_t)i * nP + p];
+    for (int i = 0; i < N; ++i) x[i] = rows[(int64_t)i * nP + p];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < N; ++i) {
         if (first) x[i] = make_float2(0.0f, 0.0f);
         neumaier_add(x[i].x, x[i].y, t[i]);
     }
     if (live) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) rows[(int64_t)i * nP + p] = x[i];
+        for (int i = 0; i < N; ++i) rows[(int64_t)i * nP + p] = x[i];
     }
 }
 
@@ -139,6 +141,11 @@ __global__ __launch_bounds__(kBlock) void k_check_counts(const int32_t *__restri
     if (f < nF && counts[f] != 1) atomicOr(&hdr->bad_index, 1);
 }
 
+// kMerge: the two faces add their sums at their shared vertices (slots 1 and 2): 12 rows
+// per pair (slot 0, slots 1 and 2 merged, slot 3) instead of 18, for callers that want
+// dL/dV only.  A lane without a second face has its normal Ng = 0, so that face's per-point
+// corner terms are exactly zero; its tile sums of w (the beta u_j terms) are dropped.
+template <bool kMerge>
 __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restrict__ recs,
                                                          const PairMeta *__restrict__ meta, int32_t nP, int32_t nF,
                                                          PointSrc ps, int64_t nQ, int32_t S, int64_t t0, int64_t t1,
@@ -153,7 +160,9 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
     p = live ? p : nP - 1;
     const PairRec r = recs[p];
     const PairMeta m = meta[p];
-    const bool any_g = __builtin_amdgcn_ballot_w64(live && m.g >= 0) != 0ull;  // wave-uniform
+    const bool has_g = m.g >= 0;
+    const bool any_g = __builtin_amdgcn_ballot_w64(live && has_g) != 0ull;  // wave-uniform
+    constexpr int kRows = kMerge ? 12 : 18;  // running sums per pair and split
     const int flip = (m.code >> 4) & 1;
     const float v[4][3] = {{r.a.x, r.a.y, r.a.z}, {r.a.w, r.b.x, r.b.y}, {r.b.z, r.b.w, r.c.x}, {r.c.y, r.c.z, r.c.w}};
     const float Nf[3] = {r.d.x, r.d.y, r.d.z}, Ng[3] = {r.d.w, r.e.x, r.e.y};
@@ -196,6 +205,9 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
             float e12[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) e12[d] = e[1][d] + e[2][d];
+            float ngaf = 0.0f, Ef[3] = {0.0f, 0.0f, 0.0f};  // kept for the merged slots 1, 2
+            (void)ngaf;
+            (void)Ef;
             {  // face f = (s0, s1, s2)
                 const float rho = ri[0] * r12;
                 const float alpha = rho * (R[0][0] * Nf[0] + R[0][1] * Nf[1] + R[0][2] * Nf[2]);
@@ -210,14 +222,22 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
 #pragma unroll
                 for (int d = 0; d < 3; ++d) E[d] = e[0][d] + e12[d];
                 const float dd[3] = {d12, d20, d01};  // e_k . e_l of corner j
+                // merging with a second face in the wave: corners 1 and 2 go with g's slots
+                const int jn = (kMerge && any_g) ? 1 : 3;
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
+                    if (j >= jn) break;
                     const float nca = nga * ri[j], ncd = nca * dd[j];
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         tf[3 * j + d] = __builtin_fmaf(nca, E[d], tf[3 * j + d]);
                         tf[3 * j + d] = __builtin_fmaf(ncd, e[j][d], tf[3 * j + d]);
                     }
+                }
+                if constexpr (kMerge) {
+                    ngaf = nga;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) Ef[d] = E[d];
                 }
             }
             if (any_g) {  // face g = (s3, s1, s2) up to winding; accumulators by slot 1, 2, 3
@@ -237,13 +257,35 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
                 for (int d = 0; d < 3; ++d) E[d] = e[3][d] + e12[d];
                 const float dd[3] = {d23, d13, d12};  // slots 1, 2, 3
                 const float rs[3] = {ri[1], ri[2], ri[3]};
+                if constexpr (kMerge) {
+                    // slots 1 and 2: f's corner and g's slot on the same vertex, one e_j term
+                    const float ddf[2] = {d20, d01};
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const float nca = nga * rs[j], ncd = nca * dd[j];
+                    for (int j = 0; j < 2; ++j) {
+                        const float ncf = ngaf * ri[j + 1], ncg = nga * rs[j];
+                        const float ncd = ncf * ddf[j] + ncg * dd[j];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            tf[3 * (j + 1) + d] = __builtin_fmaf(ncf, Ef[d], tf[3 * (j + 1) + d]);
+                            tf[3 * (j + 1) + d] = __builtin_fmaf(ncg, E[d], tf[3 * (j + 1) + d]);
+                            tf[3 * (j + 1) + d] = __builtin_fmaf(ncd, e[j + 1][d], tf[3 * (j + 1) + d]);
+                        }
+                    }
+                    const float nca = nga * rs[2], ncd = nca * dd[2];  // slot 3: g alone
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        tg[3 * j + d] = __builtin_fmaf(nca, E[d], tg[3 * j + d]);
-                        tg[3 * j + d] = __builtin_fmaf(ncd, e[j + 1][d], tg[3 * j + d]);
+                        tg[6 + d] = __builtin_fmaf(nca, E[d], tg[6 + d]);
+                        tg[6 + d] = __builtin_fmaf(ncd, e[3][d], tg[6 + d]);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const float nca = nga * rs[j], ncd = nca * dd[j];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            tg[3 * j + d] = __builtin_fmaf(nca, E[d], tg[3 * j + d]);
+                            tg[3 * j + d] = __builtin_fmaf(ncd, e[j + 1][d], tg[3 * j + d]);
+                        }
                     }
                 }
             }
@@ -272,6 +314,11 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
             }
         }
         if (any_g) {
+            if constexpr (kMerge) {  // a lane without a second face: its w sums are dropped
+                swg = has_g ? swg : 0.0f;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sqg[d] = has_g ? sqg[d] : 0.0f;
+            }
             const float sgn = flip ? 1.0f : -1.0f;
             const float sq[3] = {sgn * sqg[0], sgn * sqg[1], sgn * sqg[2]};
             // slots 1, 2, 3: (v2 - v3), (v3 - v1), (v1 - v2), and C = Ng at slot 3
@@ -281,46 +328,58 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const float cj = (j == 2) ? swg : 0.0f;
-                tg[3 * j + 0] += cj * Ng[0] + (D[j][1] * sq[2] - D[j][2] * sq[1]);
-                tg[3 * j + 1] += cj * Ng[1] + (D[j][2] * sq[0] - D[j][0] * sq[2]);
-                tg[3 * j + 2] += cj * Ng[2] + (D[j][0] * sq[1] - D[j][1] * sq[0]);
+                float *acc = (kMerge && j < 2) ? &tf[3 * (j + 1)] : &tg[3 * j];  // merged slots 1, 2
+                acc[0] += cj * Ng[0] + (D[j][1] * sq[2] - D[j][2] * sq[1]);
+                acc[1] += cj * Ng[1] + (D[j][2] * sq[0] - D[j][0] * sq[2]);
+                acc[2] += cj * Ng[2] + (D[j][0] * sq[1] - D[j][1] * sq[0]);
             }
         }
         // rows of the state are wave-uniform pointers (scalar registers), the lane adds p;
         // all loads are issued before the first add (a fresh split reads and discards)
         const bool first = t < S;  // tile t is its split's first: the sums start at zero
-        fold_rows(state + (int64_t)sy * 18 * nP, nP, p, live, first, tf);
-        if (any_g) fold_rows(state + ((int64_t)sy * 18 + 9) * nP, nP, p, live, first, tg);
+        fold_rows<9>(state + (int64_t)sy * kRows * nP, nP, p, live, first, tf);
+        if constexpr (kMerge) {
+            if (any_g) fold_rows<3>(state + ((int64_t)sy * kRows + 9) * nP, nP, p, live, first, tg + 6);
+        } else {
+            if (any_g) fold_rows<9>(state + ((int64_t)sy * kRows + 9) * nP, nP, p, live, first, tg);
+        }
     }
 }
 
 // T from the pairs' running sums: each (sum, compensation) slot summed over the splits
 // in split order, then written to its face's corner in F order (f by rotated corner, g by
-// slot: slots 1, 2, 3 are g's rotated corners (flip ? 1 : 2), (flip ? 2 : 1), 0).
+// slot: slots 1, 2, 3 are g's rotated corners (flip ? 1 : 2), (flip ? 2 : 1), 0).  With
+// rows == 12 (merged slots 1 and 2) the merged sums go to f's corners, g's corners at
+// slots 1 and 2 get zero, and rows 9..11 are g's slot 3: the sums per vertex are exact,
+// the split between the two corners of a shared vertex is not.
 __global__ __launch_bounds__(kBlock) void k_bwd_reduce_pairs(const float2 *__restrict__ state, int32_t split,
-                                                             int32_t nP, const PairMeta *__restrict__ meta,
-                                                             float scale, float *__restrict__ T) {
+                                                             int32_t nP, int32_t rows,
+                                                             const PairMeta *__restrict__ meta, float scale,
+                                                             float *__restrict__ T) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)nP * 18) return;
+    if (t >= (int64_t)nP * rows) return;
     const int32_t i = (int32_t)(t / nP);
     const int32_t p = (int32_t)(t - (int64_t)i * nP);
     const PairMeta m = meta[p];
     const int rf = m.code & 3, rg = (m.code >> 2) & 3, flip = (m.code >> 4) & 1;
+    auto g_corner = [&](int slot) {
+        const int cj = slot == 3 ? 0 : (slot == 1 ? (flip ? 1 : 2) : (flip ? 2 : 1));
+        return (cj + rg) % 3;
+    };
     int32_t face;
     int corner;
     const int d = i % 3;
     if (i < 9) {
         face = m.f;
         corner = (i / 3 + rf) % 3;
+        if (rows == 12 && i >= 3 && m.g >= 0) T[(int64_t)m.g * 9 + 3 * g_corner(i / 3) + d] = 0.0f;
     } else {
         face = m.g;
-        const int slot = (i - 9) / 3 + 1;
-        const int cj = slot == 3 ? 0 : (slot == 1 ? (flip ? 1 : 2) : (flip ? 2 : 1));
-        corner = (cj + rg) % 3;
+        corner = g_corner(rows == 12 ? 3 : (i - 9) / 3 + 1);
     }
     if (face < 0) return;
     const float2 *q = state + (int64_t)i * nP + p;
-    const int64_t stride = (int64_t)18 * nP;  // from one split to the next
+    const int64_t stride = (int64_t)rows * nP;  // from one split to the next
     float s = 0.0f, c = 0.0f;
     int32_t k = 0;
     for (; k + 8 <= split; k += 8) {
@@ -358,17 +417,22 @@ hipError_t launch_pack_pairs(const float *V, int64_t nV, const int32_t *F, int64
 
 hipError_t launch_bwd_pairs(const char *recs, const char *meta, int32_t nP, int32_t nF, const PointSrc &ps, int64_t nQ,
                             int32_t S, int64_t t0, int64_t t1, int32_t rows, const float *dLdW, float2 *state,
-                            hipStream_t s) {
-    k_wn_bwd_pairs<<<dim3(blocks_of(nP), (unsigned)rows), kBlock, 0, s>>>(
-        reinterpret_cast<const PairRec *>(recs), reinterpret_cast<const PairMeta *>(meta), nP, nF, ps, nQ, S, t0, t1,
-        dLdW, state);
+                            bool merged, hipStream_t s) {
+    const dim3 grid(blocks_of(nP), (unsigned)rows);
+    const auto *r = reinterpret_cast<const PairRec *>(recs);
+    const auto *m = reinterpret_cast<const PairMeta *>(meta);
+    if (merged)
+        k_wn_bwd_pairs<true><<<grid, kBlock, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
+    else
+        k_wn_bwd_pairs<false><<<grid, kBlock, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_pairs(const float2 *state, int32_t S, int32_t nP, const char *meta, float scale, float *T,
-                               hipStream_t s) {
-    k_bwd_reduce_pairs<<<blocks_of((int64_t)18 * nP), kBlock, 0, s>>>(state, S, nP,
-                                                                      reinterpret_cast<const PairMeta *>(meta), scale, T);
+                               bool merged, hipStream_t s) {
+    const int32_t rows = merged ? 12 : 18;
+    k_bwd_reduce_pairs<<<blocks_of((int64_t)rows * nP), kBlock, 0, s>>>(
+        state, S, nP, rows, reinterpret_cast<const PairMeta *>(meta), scale, T);
     return hipGetLastError();
 }
 

@@ -462,15 +462,17 @@ int loss_blocks(int64_t n);
 // Two faces per lane (wn_bwd_pairs.hip): 80-byte pair records and 16-byte pair metadata
 // in the adjoint's workspace; pack (with the every-face-once check), the point-split
 // kernel over tiles [t0, t1), and the reduction of the 18 running sums per pair into T.
+// `merged`: the two faces share their sums at the shared edge's vertices (12 per pair),
+// which keeps the sums per vertex exact but not those per corner (dL/dV only).
 constexpr size_t kPairRecBytes = 80, kPairMetaBytes = 16;
 hipError_t launch_pack_pairs(const float *V, int64_t nV, const int32_t *F, int64_t nF, const int32_t *pairs, int64_t nP,
                              char *recs, char *meta, int32_t *counts, WsHeader *hdr, hipStream_t s);
 hipError_t launch_bwd_pairs(const char *recs, const char *meta, int32_t nP, int32_t nF, const PointSrc &ps, int64_t nQ,
                             int32_t S, int64_t t0, int64_t t1, int32_t rows, const float *dLdW, float2 *state,
-                            hipStream_t s);
+                            bool merged, hipStream_t s);
 hipError_t launch_reduce_pairs(const float2 *state, int32_t S, int32_t nP, const char *meta, float scale, float *T,
-                               hipStream_t s);
-constexpr int kBwdBegin = 1, kBwdEnd = 2;
+                               bool merged, hipStream_t s);
+constexpr int kBwdBegin = 1, kBwdEnd = 2, kBwdVertexSums = 4;
 constexpr int kBwdTile = 256;
 int bwd_splits(int64_t nF, int64_t nQ);
 size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ);

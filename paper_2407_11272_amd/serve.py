@@ -461,7 +461,8 @@ class GpuExecutor:
                     Ph = torch.from_numpy(ph).pin_memory()
                     pairs = Ph.to(self.dev, non_blocking=True)
                     st["hold_pairs"] = Ph
-                st["adj"] = wn.SlicedBackward(st["V"], st["F"], grid=job.grid, pairs=pairs)
+                st["adj"] = wn.SlicedBackward(st["V"], st["F"], grid=job.grid, pairs=pairs,
+                                              vertex_sums=not self.keep_dLdT)
                 if self.keep_dLdT:
                     st["dLdT"] = torch.empty((len(req.F), 3, 3), dtype=torch.float32, device=self.dev)
         return st

@@ -288,17 +288,22 @@ def test_sliced_adjoint_point_list_and_argument_errors(dev, orc):
     base = p(ws.data_ptr() + (-ws.data_ptr()) % 256)
     dV = torch.empty_like(Vt)
 
-    def call(p0, n, flags=0, wsb=need, dLdV=dV, pairs=None, n_pairs=0):
+    dT = torch.empty((4, 3, 3), dtype=torch.float32, device="cuda")
+
+    def call(p0, n, flags=0, wsb=need, dLdV=dV, pairs=None, n_pairs=0, dLdT=None):
         return lib.wn_backward_range(p(Vt.data_ptr()), 9, p(Ft.data_ptr()), 4, pairs, n_pairs, None,
                                      p(Qt.data_ptr()), 1000, p(gt.data_ptr()), p0, n, flags,
-                                     p(dLdV.data_ptr()) if dLdV is not None else None, None, base, wsb, s)
+                                     p(dLdV.data_ptr()) if dLdV is not None else None,
+                                     p(dLdT.data_ptr()) if dLdT is not None else None, base, wsb, s)
 
     assert call(0, 0, L.WN_BWD_BEGIN) == L.WN_OK
     assert call(100, 256) == L.WN_ERR_INVALID_ARG          # p0 not on a tile boundary
     assert call(0, 300) == L.WN_ERR_INVALID_ARG            # n not whole tiles and not the end
     assert call(768, 233) == L.WN_ERR_INVALID_ARG          # past the last point
     assert call(-256, 256) == L.WN_ERR_INVALID_ARG
-    assert call(0, 256, 4) == L.WN_ERR_INVALID_ARG         # unknown flag
+    assert call(0, 256, 8) == L.WN_ERR_INVALID_ARG         # unknown flag
+    # per-vertex sums only: no dL/dT at the end
+    assert call(0, 0, L.WN_BWD_END | L.WN_BWD_VERTEX_SUMS, dLdT=dT) == L.WN_ERR_INVALID_ARG
     assert call(0, 0, L.WN_BWD_END, dLdV=None) == L.WN_ERR_INVALID_ARG
     assert call(0, 256, wsb=need - 1) == L.WN_ERR_WORKSPACE
     pr = torch.tensor([[0, 3], [1, 2]], dtype=torch.int32, device="cuda")
@@ -345,6 +350,64 @@ def test_face_pair_adjoint_matches_one_face_per_lane_and_the_oracle(dev, orc, ca
     Tr, Dr = orc.grad(_f32(c.V), c.F, Q, g32.astype(np.float64))
     _check_T(T2n.reshape(-1), Tr.reshape(-1), f"pairs {case} dL/dT")
     _check_V(D2.cpu().numpy().astype(np.float64), Dr, Tr, c.F, f"pairs {case} dL/dV")
+    # the two faces of a pair sharing their sums at the shared edge (dL/dV only): the
+    # same vertex sums in another grouping, against the oracle; ranges give the same bits
+    D4 = wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=pairs)
+    sb = wn.SlicedBackward(Vt, Ft, grid=c.grid, pairs=pairs, vertex_sums=True)
+    sb.begin()
+    for a, b in zip(cut[:-1], cut[1:]):
+        sb.points(a, b - a, g)
+    with pytest.raises(ValueError):
+        sb.end(dLdT=T3)
+    D5 = sb.end()
+    torch.cuda.synchronize()
+    assert wn.wn_get_device_error() == 0
+    assert torch.equal(D5, D4)
+    D2n, D4n = D2.cpu().numpy().astype(np.float64), D4.cpu().numpy().astype(np.float64)
+    print(f"[pairs {case}] |merged - per corner| / scale = {np.abs(D4n - D2n).max() / np.abs(D2n).max():.2e}",
+          flush=True)
+    _check_V(D4n, Dr, Tr, c.F, f"pairs {case} merged dL/dV")
+
+
+def test_vertex_sums_with_unpaired_faces(dev, orc):
+    """Shared vertex sums with lanes that hold one face, on the open variant of the
+    differentiable mesh at 32^3: every face alone (no lane has a second face; the same
+    arithmetic as the per-corner sums, up to the compiler's contractions), and a list in
+    which every third pair is split into two single faces, so that waves mix lanes with
+    and without a second face; both against the oracle."""
+    import torch
+    import paper_2407_11272_amd as wn
+    c = wi.config3_differentiable(res=32, open_variant=True)
+    Wr, Lr, g32, Q = _oracle_dLdW(orc, c)
+    Vt, Ft = _to_dev(c)
+    g = torch.as_tensor(g32).cuda()
+    nF = len(c.F)
+    alone = torch.as_tensor(np.stack([np.arange(nF), np.full(nF, -1)], 1).astype(np.int32)).cuda()
+    Tr, Dr = orc.grad(_f32(c.V), c.F, Q, g32.astype(np.float64))
+    Da = wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=alone, vertex_sums=False)
+    Db = wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=alone, vertex_sums=True)
+    torch.cuda.synchronize()
+    assert wn.wn_get_device_error() == 0
+    Dan, Dbn = Da.cpu().numpy().astype(np.float64), Db.cpu().numpy().astype(np.float64)
+    print(f"[vertex sums] singles: |merged - per corner|_inf = {np.abs(Dbn - Dan).max():.3e} "
+          f"of {np.abs(Dan).max():.3e}", flush=True)
+    _check_V(Dbn, Dr, Tr, c.F, "single lanes merged dL/dV")
+    P = wn.wn_build_face_pairs(c.F, len(c.V))
+    mixed = []
+    for i, (f, h) in enumerate(P.tolist()):
+        if h >= 0 and i % 3 == 0:
+            mixed += [[f, -1], [h, -1]]
+        else:
+            mixed.append([f, h])
+    mixed = np.asarray(mixed, np.int32)
+    print(f"[vertex sums] {nF} faces, {len(P)} pairs -> {len(mixed)} lanes, {(mixed[:, 1] < 0).sum()} single",
+          flush=True)
+    Dm = wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=torch.as_tensor(mixed).cuda())
+    torch.cuda.synchronize()
+    assert wn.wn_get_device_error() == 0
+    _check_V(Dm.cpu().numpy().astype(np.float64), Dr, Tr, c.F, "mixed lanes merged dL/dV")
+    with pytest.raises(ValueError):
+        wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=alone, want_dLdT=True, vertex_sums=True)
 
 
 def test_face_pairs_that_break_the_rules_are_reported(dev):
