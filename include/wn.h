@@ -185,7 +185,9 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
  * The adjoint of wn_backward in pieces, so that a scheduler can interleave a large
  * adjoint with other work (Section 2.4's gradients, served in slices).  The points are
  * taken in tiles of WN_BWD_TILE consecutive points, dealt in turn to the S =
- * wn_backward_splits(nF, nQ) splits of the adjoint (tile t to split t mod S); each split
+ * wn_backward_splits(nF, nQ) splits of the adjoint (tile t to split t mod S; with pairs,
+ * the count whose running sums fit the same space, about S nF / (2 n_pairs), or 1.5 times
+ * that with WN_BWD_VERTEX_SUMS, at most one split per tile); each split
  * keeps compensated running sums per face corner in the workspace between calls, and the
  * splits are added in split order at the end.  A sequence of calls on one workspace
  *     flags WN_BWD_BEGIN (pack the faces), then consecutive point ranges [p0, p0 + n) in

@@ -148,13 +148,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd_reduce(const float2 *__restrict_
     const int64_t stride = (int64_t)9 * nF;  // from one split to the next
     float s = 0.0f, c = 0.0f;
     int32_t k = 0;
-    // eight loads in flight, then added in split order (the same order as one at a time)
-    for (; k + 8 <= split; k += 8) {
-        float2 x[8];
+    // kReduceBatch loads in flight, then added in split order (the same order as one at a time)
+    for (; k + kReduceBatch <= split; k += kReduceBatch) {
+        float2 x[kReduceBatch];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = p[(int64_t)(k + u) * stride];
+        for (int u = 0; u < kReduceBatch; ++u) x[u] = p[(int64_t)(k + u) * stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) neumaier_add(s, c, x[u].x + x[u].y);
+        for (int u = 0; u < kReduceBatch; ++u) neumaier_add(s, c, x[u].x + x[u].y);
     }
     for (; k < split; ++k) {
         const float2 x = p[(int64_t)k * stride];
@@ -425,9 +425,14 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
             (e = launch_pack_pairs(V, nV, F, nF, pairs, nP, prec, pmeta, pcount, hdr, s)) != hipSuccess)
             return WN_ERR_HIP;
     }
-    // With pairs the running sums take 18 floats2 per pair and split; the splits are cut so
-    // that they fit the workspace sized for 9 per face (the same S when nP <= nF / 2).
-    const int S = use_pairs ? (int)std::max<int64_t>(1, (int64_t)p.split * nF / (2 * nP)) : p.split;
+    // With pairs the running sums take 18 float2 per pair and split (12 when merged); the
+    // split count is the largest that fits the workspace sized for 9 per face (the same S
+    // when nP <= nF / 2 and not merged, 1.5 S merged), and at most one split per tile.
+    // More splits mean shorter workgroups and a shorter tail of the launch.
+    const int64_t per_pair = merged ? 12 : 18;
+    const int S = use_pairs ? (int)std::max<int64_t>(
+                                  1, std::min<int64_t>(p.tiles, (int64_t)p.split * 9 * nF / (per_pair * nP)))
+                            : p.split;
     // points [p0, p0 + n): its tiles [t0, t1), one workgroup row per split that owns one
     if (n > 0 && nV > 0 && nF > 0) {
         const int64_t t0 = p0 / kPointTile, t1 = (p0 + n + kPointTile - 1) / kPointTile;

@@ -382,12 +382,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_reduce_pairs(const float2 *__res
     const int64_t stride = (int64_t)rows * nP;  // from one split to the next
     float s = 0.0f, c = 0.0f;
     int32_t k = 0;
-    for (; k + 8 <= split; k += 8) {
-        float2 x[8];
+    for (; k + kReduceBatch <= split; k += kReduceBatch) {
+        float2 x[kReduceBatch];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = q[(int64_t)(k + u) * stride];
+        for (int u = 0; u < kReduceBatch; ++u) x[u] = q[(int64_t)(k + u) * stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) neumaier_add(s, c, x[u].x + x[u].y);
+        for (int u = 0; u < kReduceBatch; ++u) neumaier_add(s, c, x[u].x + x[u].y);
     }
     for (; k < split; ++k) {
         const float2 x = q[(int64_t)k * stride];

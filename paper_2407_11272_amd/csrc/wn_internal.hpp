@@ -473,6 +473,9 @@ hipError_t launch_bwd_pairs(const char *recs, const char *meta, int32_t nP, int3
 hipError_t launch_reduce_pairs(const float2 *state, int32_t S, int32_t nP, const char *meta, float scale, float *T,
                                bool merged, hipStream_t s);
 constexpr int kBwdBegin = 1, kBwdEnd = 2, kBwdVertexSums = 4;
+// Loads in flight per thread in the reductions over the splits (each thread's loop over
+// several hundred splits is bound by memory latency, not bandwidth).
+constexpr int kReduceBatch = 32;
 constexpr int kBwdTile = 256;
 int bwd_splits(int64_t nF, int64_t nQ);
 size_t bwd_workspace(int64_t nV, int64_t nF, int64_t nQ);
