@@ -212,8 +212,8 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
  *          only dLdV is wanted: with pairs, the two faces of a pair then share their
  *          running sums at the shared edge's two vertices (12 instead of 18 per pair and
  *          split, fewer operations per point), so the sums per vertex stay exact up to
- *          rounding but those per corner do not; dLdT must then be NULL at WN_BWD_END.
- *          Without pairs it has no effect;
+ *          rounding but those per corner do not; dLdT must then be NULL at WN_BWD_END
+ *          (also without pairs, where the flag changes nothing else);
  *   ws:    wn_workspace_size(WN_OP_BACKWARD, nV, nF, nQ) bytes, holding the running sums.
  * A range of at least S tiles keeps every split busy (about nF / 256 x S workgroups).
  * Argument errors return WN_ERR_INVALID_ARG before any launch.

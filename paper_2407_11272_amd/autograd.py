@@ -11,20 +11,25 @@ from . import api
 class WindingNumber(torch.autograd.Function):
     """W = winding number of (V, F) at the centres of ``grid`` (or the rows of ``Q``);
     differentiable in V.  Backward recomputes solid angles per tile (no stored
-    point x face matrix) and returns dL/dV."""
+    point x face matrix) and returns dL/dV.  Optional device ``strips`` (from
+    ``wn_build_strips``) select the strip-order forward, and ``pairs`` (from
+    ``wn_build_face_pairs``) the adjoint with two faces per lane and shared vertex sums;
+    both depend only on F, so a loop over vertex positions builds them once."""
 
     @staticmethod
-    def forward(ctx, V, F, grid=None, Q=None):
-        ctx.save_for_backward(V, F, Q)
+    def forward(ctx, V, F, grid=None, Q=None, strips=None, pairs=None):
+        ctx.save_for_backward(V, F, Q, pairs)
         ctx.grid = grid
+        if strips is not None:
+            return api.wn_voxelize_strips(V, F, strips, grid=grid, Q=Q)
         return api.wn_voxelize(V, F, grid=grid, Q=Q)
 
     @staticmethod
     def backward(ctx, gW):
-        V, F, Q = ctx.saved_tensors
+        V, F, Q, pairs = ctx.saved_tensors
         g = gW.contiguous().reshape(-1).to(torch.float32)
-        dLdV = api.wn_backward(V, F, g, grid=ctx.grid, Q=Q)
-        return dLdV, None, None, None
+        dLdV = api.wn_backward(V, F, g, grid=ctx.grid, Q=Q, pairs=pairs)
+        return dLdV, None, None, None, None, None
 
 
 class NaiveWindingNumber(torch.autograd.Function):
@@ -63,13 +68,13 @@ class SigmoidOccupancy(torch.autograd.Function):
         return api.wn_occupancy_backward(W, g, ctx.tau, ctx.k), None, None
 
 
-def winding_number(V, F, grid=None, Q=None):
-    return WindingNumber.apply(V, F, grid, Q)
+def winding_number(V, F, grid=None, Q=None, strips=None, pairs=None):
+    return WindingNumber.apply(V, F, grid, Q, strips, pairs)
 
 
 def naive_winding_number(V, F, grid=None, Q=None):
     return NaiveWindingNumber.apply(V, F, grid, Q)
 
 
-def soft_occupancy(V, F, grid=None, Q=None, tau: float = 0.5, k: float = 50.0):
-    return SigmoidOccupancy.apply(WindingNumber.apply(V, F, grid, Q), tau, k)
+def soft_occupancy(V, F, grid=None, Q=None, tau: float = 0.5, k: float = 50.0, strips=None, pairs=None):
+    return SigmoidOccupancy.apply(WindingNumber.apply(V, F, grid, Q, strips, pairs), tau, k)

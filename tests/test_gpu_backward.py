@@ -171,6 +171,19 @@ def test_autograd_function_matches_direct_calls(dev):
     dLdV = wn.wn_backward(Vt, Ft, dLdW, grid=c.grid)
     torch.cuda.synchronize()
     torch.testing.assert_close(V.grad, dLdV, rtol=1e-4, atol=1e-7 * float(dLdV.abs().max()))
+    # the strip-order forward and the face-pair adjoint through the same Function
+    R = torch.as_tensor(wn.wn_build_strips(c.F, len(c.V))).cuda()
+    P = torch.as_tensor(wn.wn_build_face_pairs(c.F, len(c.V))).cuda()
+    V2 = Vt.clone().requires_grad_(True)
+    occ2 = wn.soft_occupancy(V2, Ft, grid=c.grid, tau=0.5, k=50.0, strips=R, pairs=P)
+    ((occ2 - T) ** 2).mean().backward()
+    W2 = wn.wn_voxelize_strips(Vt, Ft, R, grid=c.grid).reshape(-1)
+    _, dLdW2 = wn.wn_sigmoid_mse(W2, T.reshape(-1), 0.5, 50.0)
+    dLdV2 = wn.wn_backward(Vt, Ft, dLdW2, grid=c.grid, pairs=P)
+    torch.cuda.synchronize()
+    torch.testing.assert_close(occ2, occ, rtol=0, atol=1e-4)
+    torch.testing.assert_close(V2.grad, dLdV2, rtol=1e-4, atol=1e-7 * float(dLdV2.abs().max()))
+    torch.testing.assert_close(V2.grad, V.grad, rtol=0, atol=1e-3 * float(V.grad.abs().max()))
 
 
 def test_backward_edge_cases(dev, orc):
