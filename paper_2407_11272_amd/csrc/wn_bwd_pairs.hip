@@ -145,8 +145,10 @@ __global__ __launch_bounds__(kBlock) void k_check_counts(const int32_t *__restri
 // per pair (slot 0, slots 1 and 2 merged, slot 3) instead of 18, for callers that want
 // dL/dV only.  A lane without a second face has its normal Ng = 0, so that face's per-point
 // corner terms are exactly zero; its tile sums of w (the beta u_j terms) are dropped.
-template <bool kMerge>
-__global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restrict__ recs,
+// kThreads: lanes per workgroup, 256 or 64 (one wave); every wave stages the whole point
+// tile, so the per-lane arithmetic and the bits do not depend on it.
+template <bool kMerge, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_wn_bwd_pairs(const PairRec *__restrict__ recs,
                                                          const PairMeta *__restrict__ meta, int32_t nP, int32_t nF,
                                                          PointSrc ps, int64_t nQ, int32_t S, int64_t t0, int64_t t1,
                                                          const float *__restrict__ dLdW,
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
     const int tid = threadIdx.x;
     const int64_t tfirst = t0 + blockIdx.y;
     const int64_t sy = tfirst % S;
-    int32_t p = (int32_t)blockIdx.x * kBlock + tid;
+    int32_t p = (int32_t)blockIdx.x * kThreads + tid;
     const bool live = p < nP;
     p = live ? p : nP - 1;
     const PairRec r = recs[p];
@@ -174,10 +176,14 @@ __global__ __launch_bounds__(kBlock) void k_wn_bwd_pairs(const PairRec *__restri
         const int64_t q0 = t * kPointTile;
         const int nt = (int)min((int64_t)kPointTile, nQ - q0);
         __syncthreads();
-        if (tid < nt) {
-            float x, y, z;
-            ps.get(q0 + tid, x, y, z);
-            pts[tid] = make_float4(x, y, z, dLdW[q0 + tid]);
+#pragma unroll
+        for (int k = 0; k < kPointTile / kThreads; ++k) {
+            const int j = tid + k * kThreads;
+            if (j < nt) {
+                float x, y, z;
+                ps.get(q0 + j, x, y, z);
+                pts[j] = make_float4(x, y, z, dLdW[q0 + j]);
+            }
         }
         __syncthreads();
         float tf[9], tg[9], swf = 0.0f, swg = 0.0f, sqf[3] = {0.0f, 0.0f, 0.0f}, sqg[3] = {0.0f, 0.0f, 0.0f};
@@ -418,13 +424,28 @@ hipError_t launch_pack_pairs(const float *V, int64_t nV, const int32_t *F, int64
 hipError_t launch_bwd_pairs(const char *recs, const char *meta, int32_t nP, int32_t nF, const PointSrc &ps, int64_t nQ,
                             int32_t S, int64_t t0, int64_t t1, int32_t rows, const float *dLdW, float2 *state,
                             bool merged, hipStream_t s) {
-    const dim3 grid(blocks_of(nP), (unsigned)rows);
+    static_assert(kPointTile % 64 == 0 && kBlock % 64 == 0, "whole waves");
+    // One-wave workgroups avoid the idle waves of a last, mostly empty column of 256-lane
+    // workgroups (C3: 2576 pairs, 44 waves for 41 of work); they cost about 2.5 % more per
+    // wave otherwise (four times the workgroups, each staging the whole tile), so they are
+    // taken only when that column would waste more than that.
+    const int64_t waves_wide = (int64_t)(kBlock / 64) * ((nP + kBlock - 1) / kBlock), waves_narrow = (nP + 63) / 64;
+    const bool narrow = waves_wide * 40 > waves_narrow * 41;
     const auto *r = reinterpret_cast<const PairRec *>(recs);
     const auto *m = reinterpret_cast<const PairMeta *>(meta);
-    if (merged)
-        k_wn_bwd_pairs<true><<<grid, kBlock, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
-    else
-        k_wn_bwd_pairs<false><<<grid, kBlock, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
+    if (narrow) {
+        const dim3 grid((unsigned)waves_narrow, (unsigned)rows);
+        if (merged)
+            k_wn_bwd_pairs<true, 64><<<grid, 64, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
+        else
+            k_wn_bwd_pairs<false, 64><<<grid, 64, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
+    } else {
+        const dim3 grid(blocks_of(nP), (unsigned)rows);
+        if (merged)
+            k_wn_bwd_pairs<true, kBlock><<<grid, kBlock, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
+        else
+            k_wn_bwd_pairs<false, kBlock><<<grid, kBlock, 0, s>>>(r, m, nP, nF, ps, nQ, S, t0, t1, dLdW, state);
+    }
     return hipGetLastError();
 }
 
