@@ -21,7 +21,7 @@ def _check_stream(F, R):
     assert len(R) == 0 or (R[0, 1] == -1 and R[1, 1] == -1)
 
 
-@pytest.mark.parametrize("mesh", ["ico3", "ico4", "c2", "open", "soup", "degenerate"])
+@pytest.mark.parametrize("mesh", ["ico3", "ico4", "c2", "open", "soup", "degenerate", "dense", "fan"])
 def test_strip_stream_is_valid(mesh):
     rng = np.random.default_rng(3)
     if mesh == "ico3":
@@ -37,6 +37,12 @@ def test_strip_stream_is_valid(mesh):
     elif mesh == "soup":
         V = rng.normal(size=(90, 3))
         F = rng.permutation(90).reshape(30, 3)
+    elif mesh == "dense":   # 300 random faces on 12 vertices: repeated, degenerate, non-manifold
+        V = rng.normal(size=(12, 3))
+        F = rng.integers(0, 12, size=(300, 3))
+    elif mesh == "fan":     # 50 faces around one edge
+        V = rng.normal(size=(52, 3))
+        F = np.array([[0, 1, 2 + k] for k in range(50)])
     else:
         V = rng.normal(size=(10, 3))
         F = np.array([[0, 1, 2], [1, 1, 3], [2, 3, 3], [4, 5, 6], [5, 4, 7], [0, 0, 0]])
@@ -67,7 +73,7 @@ def test_strip_builder_errors():
     assert lib.wn_build_strips(F.ctypes.data, 1, 3, None, 0, None) == L.WN_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("mesh", ["ico4", "c2", "open", "soup", "degenerate"])
+@pytest.mark.parametrize("mesh", ["ico4", "c2", "open", "soup", "degenerate", "dense", "fan"])
 def test_face_pairs_are_valid(mesh):
     """wn_build_face_pairs: every face exactly once; a pair's faces have three distinct
     vertex ids each and share exactly two; pairs come before the unpaired faces;
@@ -84,6 +90,12 @@ def test_face_pairs_are_valid(mesh):
     elif mesh == "soup":
         V = rng.normal(size=(90, 3))
         F = rng.permutation(90).reshape(30, 3)
+    elif mesh == "dense":   # 300 random faces on 12 vertices: repeated, degenerate, non-manifold
+        V = rng.normal(size=(12, 3))
+        F = rng.integers(0, 12, size=(300, 3))
+    elif mesh == "fan":     # 50 faces around one edge: at most 25 pairs
+        V = rng.normal(size=(52, 3))
+        F = np.array([[0, 1, 2 + k] for k in range(50)])
     else:
         V = rng.normal(size=(10, 3))
         F = np.array([[0, 1, 2], [1, 1, 3], [2, 3, 3], [4, 5, 6], [5, 4, 7], [0, 0, 0], [1, 2, 3], [2, 1, 8]])
