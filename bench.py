@@ -188,7 +188,7 @@ def bench_adjoint(steps, warmup):
     npairs = grid.size * len(c.F)
     bwd_s = max(s_s - f_s, 1e-12) / n
     out = {
-        "workload": "icosphere-s4-5120f-64cube sigmoid(k=50) MSE, forward+loss+adjoint (two faces per lane)",
+        "workload": "icosphere-s4-5120f-64cube sigmoid(k=50) MSE, forward+loss+adjoint (two faces per lane, sums shared per vertex)",
         "pairs_per_pass": npairs,
         "ms_per_step": s_s / n * 1e3,
         "fwd_ms": f_s / n * 1e3,
@@ -196,7 +196,7 @@ def bench_adjoint(steps, warmup):
         "adjoint_pairs_per_s": npairs / bwd_s,
         "adjoint_frac_fp32_peak": npairs / bwd_s * FLOP_BWD / PEAK_FP32,
         "step_pairs_per_s": 2 * npairs / (s_s / n),
-        # the adjoint call alone (pack, the two-faces-per-lane kernel, split and vertex sums)
+        # the adjoint call alone (pack, the two-faces-per-lane kernel, split reduction, per-vertex gather)
         "adjoint_call_ms": a_s / n * 1e3,
         "adjoint_call_pairs_per_s": npairs / (a_s / n),
         "roofline": roofline("k_wn_bwd_pairs", "c3", npairs, a_s / n, FLOP_BWD),
