@@ -187,7 +187,8 @@ WN_API wn_status wn_backward(const float *V, int64_t nV, const int32_t *F, int64
  * taken in tiles of WN_BWD_TILE consecutive points, dealt in turn to the S =
  * wn_backward_splits(nF, nQ) splits of the adjoint (tile t to split t mod S; with pairs,
  * the count whose running sums fit the same space, about S nF / (2 n_pairs), or 1.5 times
- * that with WN_BWD_VERTEX_SUMS, at most one split per tile); each split
+ * that with WN_BWD_VERTEX_SUMS, 3 times when there are at least 12 tiles per split; at
+ * most one split per tile); each split
  * keeps compensated running sums per face corner in the workspace between calls, and the
  * splits are added in split order at the end.  A sequence of calls on one workspace
  *     flags WN_BWD_BEGIN (pack the faces), then consecutive point ranges [p0, p0 + n) in
@@ -246,8 +247,9 @@ WN_API wn_status wn_build_face_pairs(const int32_t *F, int64_t nF, int64_t nV, i
 
 /* The number of splits S of the adjoint of nF faces over nQ points (a pure function of the
  * sizes: about 32 768 waves of (face block, split) work, at most one split per tile, at
- * most 4096, and at most 256 MiB of running sums, 72 bytes per face per split); -1 on
- * invalid sizes. */
+ * most 4096, and at most 256 MiB of running sums, 72 bytes per face per split; the
+ * workspace holds twice that space when there are at least 12 tiles per split, for the
+ * face-pair adjoint with WN_BWD_VERTEX_SUMS); -1 on invalid sizes. */
 WN_API int64_t wn_backward_splits(int64_t nF, int64_t nQ);
 
 /*

@@ -283,6 +283,7 @@ namespace {
 struct BwdPlan {
     int split;      // S: tile t of the points belongs to split t mod S
     int64_t tiles;  // 256-point tiles of the points
+    bool wide;      // running-sum space for twice the merged face-pair splits
     unsigned bits;
     size_t sort_tmp;
     size_t off_soup, off_part, off_T, off_keys, off_vals, off_keys2, off_vals2, off_tmp, off_vs, off_ve;
@@ -315,6 +316,10 @@ BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ) {
     BwdPlan p{};
     p.split = bwd_splits(nF, nQ);
     p.tiles = (nQ + kPointTile - 1) / kPointTile;
+    // With at least 12 tiles per split, twice the merged face-pair splits still leave each
+    // about 4 tiles, and their shorter workgroups shorten the launch's tail (measured 3.5 %
+    // at 128^3 x 5120 faces, nothing at 64^3): the running-sum space is doubled for them.
+    p.wide = p.tiles >= 12 * (int64_t)p.split;
     unsigned bits = 1;
     while (bits < 31 && ((int64_t)1 << bits) < nV) ++bits;
     p.bits = bits;
@@ -328,7 +333,7 @@ BwdPlan plan_backward(int64_t nV, int64_t nF, int64_t nQ) {
     p.off_soup = o;
     o += align_up((size_t)nF * sizeof(FaceRec));
     p.off_part = o;
-    o += align_up((size_t)p.split * 9 * (size_t)nF * sizeof(float2));
+    o += align_up((size_t)p.split * 9 * (size_t)nF * sizeof(float2) * (p.wide ? 2 : 1));
     p.off_T = o;
     o += align_up((size_t)nF * 9 * sizeof(float));
     p.off_keys = o;
@@ -426,12 +431,13 @@ wn_status run_backward(const float *V, int64_t nV, const int32_t *F, int64_t nF,
             return WN_ERR_HIP;
     }
     // With pairs the running sums take 18 float2 per pair and split (12 when merged); the
-    // split count is the largest that fits the workspace sized for 9 per face (the same S
-    // when nP <= nF / 2 and not merged, 1.5 S merged), and at most one split per tile.
-    // More splits mean shorter workgroups and a shorter tail of the launch.
-    const int64_t per_pair = merged ? 12 : 18;
+    // split count is the largest that fits the space sized for 9 per face and split (the
+    // same S when nP <= nF / 2 and not merged, 1.5 S merged; merged and wide, twice that in
+    // the doubled space), and at most one split per tile.  More splits mean shorter
+    // workgroups and a shorter tail of the launch.
+    const int64_t per_pair = merged ? 12 : 18, space = (merged && p.wide) ? 2 : 1;
     const int S = use_pairs ? (int)std::max<int64_t>(
-                                  1, std::min<int64_t>(p.tiles, (int64_t)p.split * 9 * nF / (per_pair * nP)))
+                                  1, std::min<int64_t>(p.tiles, space * ((int64_t)p.split * 9 * nF / (per_pair * nP))))
                             : p.split;
     // points [p0, p0 + n): its tiles [t0, t1), one workgroup row per split that owns one
     if (n > 0 && nV > 0 && nF > 0) {

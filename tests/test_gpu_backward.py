@@ -423,6 +423,49 @@ def test_vertex_sums_with_unpaired_faces(dev, orc):
         wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=alone, want_dLdT=True, vertex_sums=True)
 
 
+def test_merged_adjoint_with_wide_splits_at_128(dev, orc):
+    """At 128^3 (8192 tiles, at least 12 per split) the merged pair adjoint takes twice its
+    splits in a doubled running-sum space: point ranges give the same bits as one call,
+    and dL/dV at 8 rim and 8 interior vertices of the open differentiable mesh (seeded
+    choices, with every face around them) holds to the oracle for a seeded dL/dW."""
+    import torch
+    import paper_2407_11272_amd as wn
+    L = wn._lib
+    c = wi.config3_differentiable(res=128, open_variant=True)
+    Vt, Ft = _to_dev(c)
+    P, nF = c.grid.size, len(c.F)
+    splits = int(L.load().wn_backward_splits(nF, P))
+    assert P // 256 >= 12 * splits
+    assert wn.wn_workspace_size(L.WN_OP_BACKWARD, len(c.V), nF, P) >= 2 * 72 * splits * nF
+    rng = np.random.default_rng(11)
+    g32 = rng.standard_normal(P).astype(np.float32)
+    g = torch.as_tensor(g32).cuda()
+    pairs = torch.as_tensor(wn.wn_build_face_pairs(c.F, len(c.V))).cuda()
+    D = wn.wn_backward(Vt, Ft, g, grid=c.grid, pairs=pairs)
+    sb = wn.SlicedBackward(Vt, Ft, grid=c.grid, pairs=pairs, vertex_sums=True)
+    sb.begin()
+    cut = [0, 256 * 5, 256 * 3000, 256 * 3001, P]
+    for a, b in zip(cut[:-1], cut[1:]):
+        sb.points(a, b - a, g)
+    D2 = sb.end()
+    torch.cuda.synchronize()
+    assert wn.wn_get_device_error() == 0
+    assert torch.equal(D, D2)
+    F = np.asarray(c.F)
+    edges = np.sort(F[:, [[0, 1], [1, 2], [2, 0]]].reshape(-1, 2), axis=1)
+    uniq, cnt = np.unique(edges, axis=0, return_counts=True)
+    rim = np.unique(uniq[cnt == 1])
+    interior = np.setdiff1d(np.arange(len(c.V)), rim)
+    vs = np.concatenate([rng.choice(rim, 8, replace=False), rng.choice(interior, 8, replace=False)])
+    faces = np.nonzero(np.isin(F, vs).any(axis=1))[0]
+    Tr, Dr = orc.grad(_f32(c.V), F[faces], orc.grid_points(c.grid), g32.astype(np.float64))
+    Dg = Dr.copy()
+    Dg[vs] = D.cpu().numpy().astype(np.float64)[vs]
+    print(f"[wide splits] {splits} base splits, {len(faces)} faces around {len(vs)} vertices; "
+          f"|dL/dV| at the rim up to {np.abs(Dr[vs[:8]]).max():.3e}", flush=True)
+    _check_V(Dg, Dr, Tr, F[faces], "128^3 merged, wide splits, sampled dL/dV")
+
+
 def test_face_pairs_that_break_the_rules_are_reported(dev):
     """A face left out of the pairs, a face given twice, and a pair without a shared edge
     are recorded as bad indices; a valid list is not."""
