@@ -70,3 +70,19 @@ def test_backward_splits_are_host_only():
     # the adjoint workspace grows with the split count's running sums
     b = wn.wn_workspace_size(L.WN_OP_BACKWARD, 2562, 5120, 64 ** 3)
     assert b >= 256 + 48 * 5120 + 72 * 5120 * lib.wn_backward_splits(5120, 64 ** 3)
+
+
+def test_backward_workspace_doubles_its_running_sums_with_many_tiles_per_split():
+    """With at least 12 point tiles per split the adjoint workspace holds twice the running
+    sums (room for three times the merged face-pair splits); below that it does not."""
+    lib = L.load()
+    for nV, nF, P in ((2562, 5120, 64 ** 3), (2562, 5120, 96 ** 3), (2562, 5120, 128 ** 3),
+                      (642, 1280, 128 ** 3), (50000, 100000, 256 ** 3)):
+        S = lib.wn_backward_splits(nF, P)
+        wide = P // 256 >= 12 * S
+        # the running sums, then records, corner sort buffers and the rest (under 300 B
+        # per face and 32 B per vertex, plus alignment and the sort's scratch)
+        b = wn.wn_workspace_size(L.WN_OP_BACKWARD, nV, nF, P)
+        base = 72 * nF * S
+        assert b >= base * (2 if wide else 1)
+        assert b < base * (2 if wide else 1) + 256 * 16 + 300 * nF + 32 * nV + (1 << 20)
