@@ -85,16 +85,21 @@ __device__ __forceinline__ float atan_unit(float t) {
     return p * t;
 }
 
-// ATAN2(y, x) with the case table of Eq. 8: ATAN2(+-0, +-0) = 0 and, for x < 0,
-// y = -0 takes the y >= 0 branch (+pi).  Finite inputs; NaN propagates.
-__device__ __forceinline__ float atan2_eq8(float y, float x) {
+// |ATAN2(y, x)|: the angle of (|y|, x), in [0, pi].
+__device__ __forceinline__ float atan2_mag(float y, float x) {
     const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
     const float mn = __builtin_fminf(ax, ay);
     const float mx = __builtin_fmaxf(ax, ay);
     const float t = mn * __builtin_amdgcn_rcpf(__builtin_fmaxf(mx, kFltMin));
     float a = atan_unit(t);
     a = (ay > ax) ? (kHalfPi - a) : a;
-    a = (x < 0.0f) ? (kPi - a) : a;
+    return (x < 0.0f) ? (kPi - a) : a;
+}
+
+// ATAN2(y, x) with the case table of Eq. 8: ATAN2(+-0, +-0) = 0 and, for x < 0,
+// y = -0 takes the y >= 0 branch (+pi).  Finite inputs; NaN propagates.
+__device__ __forceinline__ float atan2_eq8(float y, float x) {
+    const float a = atan2_mag(y, x);
     return (y < 0.0f) ? -a : a;
 }
 
@@ -181,13 +186,19 @@ __device__ __forceinline__ void face_terms(const float4 n, const Slot<PPL> &A, c
 // exactly 0 or pi, a face seen edge-on) and products outside the normal FP32 range take
 // the two ATAN2s one by one.
 __device__ __forceinline__ float pair_angle(float a0, float b0, float a1, float b1) {
-    const float pre = b0 * b1 - a0 * a1;
+    const float a01 = a0 * a1;
+    const float pre = __builtin_fmaf(b0, b1, -a01);
     const float pim = a0 * b1 + b0 * a1;
-    float t = atan2_eq8(pim, pre);
-    const bool n0 = a0 < 0.0f, n1 = a1 < 0.0f, np = pim < 0.0f;
-    if (n0 == n1 && n0 != np) t += n0 ? -kTwoPi : kTwoPi;
+    // Same sign: a01 > 0 (where it is not, |a01| < FLT_MIN or a zero angle, the two ATAN2s
+    // are taken below).  A wrap has the angles' sign opposite to pim's, so the corrected
+    // sum is the ATAN2's sign applied to (|angle| - 2 pi): one subtraction and one select,
+    // with the same rounding as adding -+2 pi to the signed angle.
+    const bool np = pim < 0.0f;
+    float u = atan2_mag(pim, pre);
+    if ((a01 > 0.0f) & ((a0 < 0.0f) != np)) u -= kTwoPi;
+    float t = np ? -u : u;
     const float mx = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(pre), __builtin_fabsf(pim)), kFltMin);
-    if (__builtin_expect(__builtin_fabsf(a0 * a1) < kFltMin || mx > kPairMax, 0))
+    if (__builtin_expect(__builtin_fabsf(a01) < kFltMin || mx > kPairMax, 0))
         t = atan2_eq8(a0, b0) + atan2_eq8(a1, b1);
     return t;
 }
